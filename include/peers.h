@@ -1,0 +1,180 @@
+/*
+ * peers.h -- C ABI of libpeers: exact effective resistances on MI355X (gfx950)
+ * by the implicit-inverse sweep of Chen, Gan, Yang and Yu, "PEERS: A Parallel
+ * and Exact Effective Resistance Solver via Implicit Inversion and Augmented
+ * Symbolic Analysis".
+ *
+ * Problem statement (Section II-A, eq 1-4; Algorithm 8 inputs/outputs):
+ *   a weighted undirected graph G = (V, E, w) with n nodes and m edges, a ground
+ *   node g, and a query set of node pairs (u, v); the result for query k is the
+ *   effective resistance R_uv = (e_u - e_v)^T L_r^{-1} (e_u - e_v), where L_r is
+ *   the Laplacian L_G with g's row and column deleted and e_g := 0 (eq 4).
+ *   The answer array is indexed by query number (the query graph's edge
+ *   weights are answer indices, Section III-G).
+ *
+ * Method: L_r is ordered by nested dissection and factored on the host as
+ *   P L_r P^T = L D L^T (Algorithm 8 step 1). The device never forms L^{-1}: the
+ *   rows of Z = D^{-1/2} L^{-1} are produced implicitly by sweeping
+ *   elimination-tree paths (eq 11, Section III-C) and every query accumulates
+ *   its contributions (Z_ju - Z_jv)^2 as the rows pass (eq 12, Algorithm 7).
+ *
+ * Conventions for every function:
+ *   - Return value: peers_status; 0 (PEERS_OK) on success, negative on error.
+ *     Nothing aborts or throws. peers_last_error() gives a thread-local message.
+ *   - Input arrays are borrowed for the duration of the call only; the library
+ *     copies what it keeps. Handles are owned by the library and released only
+ *     by the matching destroy/release/close/stop call.
+ *   - Node ids are 0-based int32 in [0, n). Floating point is IEEE FP64
+ *     throughout (host preparation and device sweep).
+ *   - hip_stream is a hipStream_t (NULL = the null stream). Device calls are
+ *     stream-ordered: they return after enqueueing; the caller synchronizes.
+ */
+#ifndef PEERS_H_
+#define PEERS_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PEERS_OK = 0,
+  PEERS_E_INVALID_ARG = -1,   /* null pointer, bad size, bad option */
+  PEERS_E_NODE_RANGE = -2,    /* a node id (edge endpoint, ground, query endpoint) outside [0, n) */
+  PEERS_E_WEIGHT = -3,        /* a conductance that is not finite and > 0 */
+  PEERS_E_DISCONNECTED = -4,  /* the graph is not connected: L_r is singular */
+  PEERS_E_NOT_SPD = -5,       /* a non-positive pivot in L D L^T */
+  PEERS_E_HOST_OOM = -6,      /* host allocation failed */
+  PEERS_E_OVER_BUDGET = -7,   /* the device HBM budget would be exceeded; nothing was admitted */
+  PEERS_E_HIP = -8,           /* a HIP runtime error (message in peers_last_error) */
+  PEERS_E_BUSY = -9,          /* the server queue is full */
+  PEERS_E_CANCELLED = -10,    /* the request was cancelled or the server stopped */
+  PEERS_E_TIMEOUT = -11,      /* a wait timed out; the request is still pending */
+  PEERS_E_UNSUPPORTED = -12,  /* the operation is not available for this input */
+  PEERS_E_INTERNAL = -99
+} peers_status;
+
+typedef struct peers_graph_s* peers_graph;   /* host: ordering, symbolic, L D L^T; immutable */
+typedef struct peers_device_s* peers_device; /* one GPU with an HBM budget */
+typedef struct peers_factor_s* peers_factor; /* one graph's sweep data resident in HBM */
+typedef struct peers_server_s* peers_server; /* asynchronous request server */
+
+/* Ordering choices (nested dissection, Section II-D, Lemma 2). */
+enum {
+  PEERS_ORDER_AUTO = 0,  /* coordinates if given, else graph bisection */
+  PEERS_ORDER_COORD = 1, /* coordinate bisection; needs coords */
+  PEERS_ORDER_GRAPH = 2, /* breadth-first level-structure bisection */
+  PEERS_ORDER_GIVEN = 3  /* caller's elimination order (given_order) */
+};
+
+typedef struct {
+  int32_t ordering;           /* PEERS_ORDER_*; 0 = auto */
+  const double* coords;       /* optional n x 3 row-major point coordinates, original ids */
+  const int32_t* given_order; /* PEERS_ORDER_GIVEN: n-1 original ids (ground excluded), elimination order */
+  int32_t threads;            /* host threads for the factorization; 0 = all hardware threads */
+  int32_t leaf_size;          /* nested-dissection leaf size; 0 = 64 */
+} peers_graph_opts;
+
+typedef struct {
+  int64_t n, m;            /* as given */
+  int64_t N;               /* n - 1: order of L_r */
+  int64_t nnz_l;           /* strict-lower nonzeros of L */
+  int32_t height;          /* elimination-tree height h (root depth 1) */
+  int32_t n_supernodes;    /* fundamental supernodes */
+  int32_t max_sn_width;
+  int32_t n_roots;         /* elimination-forest roots (> 1 when the ground is a cut node) */
+  int64_t self_loops;
+  double f_sweep;          /* sweep FMAs: sum over L_ki != 0 of depth(k) (the work of Theorem 4, Part I) */
+  double acc_terms;        /* all-edge accumulation terms: sum over edges of depth(lower endpoint) */
+  double t_ingest, t_order, t_symbolic, t_numeric; /* host preparation seconds */
+} peers_graph_stats;
+
+/* Build the host factor of a graph (Algorithm 8 step 1: ground, reorder, factor).
+ * eu, ev: m endpoint ids; w: m conductances (> 0, finite). Self-loops are
+ * accepted and ignored (they do not enter L_G, eq 1); parallel edges add.
+ * ground: the grounded node g. opts may be NULL (defaults).
+ * Errors: INVALID_ARG, NODE_RANGE, WEIGHT, DISCONNECTED, NOT_SPD, HOST_OOM. */
+peers_status peers_graph_create(int64_t n, int64_t m, const int32_t* eu, const int32_t* ev,
+                                const double* w, int32_t ground, const peers_graph_opts* opts,
+                                peers_graph* out);
+peers_status peers_graph_stats_get(peers_graph g, peers_graph_stats* out);
+/* Symbolic structures (Lemma 1, Definition 2), caller-allocated from the stats:
+ * perm[N]: original id eliminated i-th; parent[N] (-1 at roots); colptr[N+1] and
+ * rowidx[nnz_l]: strict-lower pattern of L in CSC with rows ascending;
+ * snptr[n_supernodes+1]: fundamental supernode column ranges. Any pointer may be NULL. */
+peers_status peers_graph_export_symbolic(peers_graph g, int32_t* perm, int32_t* parent, int64_t* colptr,
+                                         int32_t* rowidx, int32_t* snptr);
+/* Numeric factor: Lx[nnz_l] aligned with rowidx, D[N] pivots. Either may be NULL. */
+peers_status peers_graph_export_factor(peers_graph g, double* Lx, double* D);
+void peers_graph_destroy(peers_graph g);
+
+/* Open GPU `ordinal` (HIP device index). hbm_budget_bytes caps what factors
+ * and per-call work buffers may hold (0 = 90% of the device memory). */
+peers_status peers_device_open(int32_t ordinal, uint64_t hbm_budget_bytes, peers_device* out);
+void peers_device_close(peers_device d);
+/* Bytes currently held on the device by this library, and the budget. */
+peers_status peers_device_usage(peers_device d, uint64_t* used, uint64_t* budget);
+
+/* Upload a graph's sweep data to HBM (the factor in the device layout, the
+ * schedule and the resident edge-query plan). Errors: OVER_BUDGET, HIP. */
+peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream, peers_factor* out);
+void peers_factor_release(peers_factor f);
+/* Device bytes of a resident factor and its per-call workspace bound. */
+peers_status peers_factor_footprint(peers_factor f, uint64_t* resident_bytes, uint64_t* workspace_bytes);
+
+enum {
+  PEERS_OUT_DEVICE = 1u,    /* R_out is a device pointer (else host memory) */
+  PEERS_IN_DEVICE = 2u,     /* qu/qv are device pointers (peers_query only) */
+  PEERS_SYNC = 4u           /* synchronize the stream before returning */
+};
+
+/* All-edge effective resistances (Section III-G, eq 12): R_out[e] for every
+ * input edge e in input order (m values; self-loops give +0.0). */
+peers_status peers_query_all_edges(peers_factor f, double* R_out, uint32_t flags, void* hip_stream);
+
+/* Resistances for q arbitrary pairs given in original ids (eq 4 and eq 12):
+ * pairs with u == v give +0.0, pairs with the ground use the grounded case.
+ * Errors: NODE_RANGE for an id outside [0, n). */
+peers_status peers_query(peers_factor f, int64_t q, const int32_t* qu, const int32_t* qv, double* R_out,
+                         uint32_t flags, void* hip_stream);
+
+/* Batched form: nb resident factors answered in one launch sequence; each
+ * result is bit-identical to the same query run alone. qu[i]/qv[i] may be NULL
+ * for all-edge queries of factor i (then q[i] is ignored). */
+peers_status peers_batch_query(peers_device d, int32_t nb, const peers_factor* f, const int64_t* q,
+                               const int32_t* const* qu, const int32_t* const* qv, double* const* R_out,
+                               uint32_t flags, void* hip_stream);
+
+/* Served form: thread-safe asynchronous requests with continuous batching. */
+typedef struct {
+  int32_t max_batch_pairs;  /* work cap per device batch (0 = 1<<20 pairs) */
+  int32_t max_wait_us;      /* longest a request waits for batch-mates (0 = 200 us) */
+  int32_t queue_capacity;   /* pending requests before PEERS_E_BUSY (0 = 4096) */
+  int32_t streams;          /* device streams in flight (0 = 2) */
+} peers_server_opts;
+
+typedef struct {
+  uint64_t submitted, completed, rejected, batches;
+  double p50_us, p99_us, max_us;   /* submit -> result latency */
+  double resistances_per_s;        /* completed pairs / busy wall time */
+} peers_server_stats;
+
+peers_status peers_server_start(peers_device d, const peers_server_opts* opts, peers_server* out);
+/* Enqueue q pairs (original ids) against a resident factor; R_out (host, length
+ * q) must stay valid until peers_server_wait returns for the ticket. */
+peers_status peers_server_submit(peers_server s, peers_factor f, int64_t q, const int32_t* qu,
+                                 const int32_t* qv, double* R_out, uint64_t* ticket);
+/* Wait for a ticket; timeout_us < 0 waits forever. *result gets the request's status. */
+peers_status peers_server_wait(peers_server s, uint64_t ticket, int64_t timeout_us, peers_status* result);
+peers_status peers_server_stats_get(peers_server s, peers_server_stats* out);
+peers_status peers_server_stop(peers_server s);
+
+const char* peers_status_string(peers_status st);
+const char* peers_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PEERS_H_ */

@@ -1,0 +1,338 @@
+"""Python binding of libpeers (exact effective resistances on MI355X).
+
+Argument marshalling only: every computation happens in the native library
+(host C++ preparation, HIP sweep kernels). The binding exposes the C ABI of
+``include/peers.h`` under the same names and thin handle classes around them.
+Device buffers and streams may be passed as torch tensors / streams; numpy
+arrays are accepted for host data.
+
+If the built library is missing this module raises on import of any entry
+point: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libpeers.so")
+
+PEERS_OK = 0
+STATUS_NAMES = {
+    0: "OK", -1: "E_INVALID_ARG", -2: "E_NODE_RANGE", -3: "E_WEIGHT", -4: "E_DISCONNECTED",
+    -5: "E_NOT_SPD", -6: "E_HOST_OOM", -7: "E_OVER_BUDGET", -8: "E_HIP", -9: "E_BUSY",
+    -10: "E_CANCELLED", -11: "E_TIMEOUT", -12: "E_UNSUPPORTED", -99: "E_INTERNAL",
+}
+PEERS_ORDER_AUTO, PEERS_ORDER_COORD, PEERS_ORDER_GRAPH, PEERS_ORDER_GIVEN = 0, 1, 2, 3
+PEERS_OUT_DEVICE, PEERS_IN_DEVICE, PEERS_SYNC = 1, 2, 4
+
+
+class PeersError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)} ({msg})")
+        self.status = status
+
+
+class peers_graph_opts(C.Structure):
+    _fields_ = [("ordering", C.c_int32), ("coords", C.POINTER(C.c_double)),
+                ("given_order", C.POINTER(C.c_int32)), ("threads", C.c_int32), ("leaf_size", C.c_int32)]
+
+
+class peers_graph_stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("m", C.c_int64), ("N", C.c_int64), ("nnz_l", C.c_int64),
+                ("height", C.c_int32), ("n_supernodes", C.c_int32), ("max_sn_width", C.c_int32),
+                ("n_roots", C.c_int32), ("self_loops", C.c_int64), ("f_sweep", C.c_double),
+                ("acc_terms", C.c_double), ("t_ingest", C.c_double), ("t_order", C.c_double),
+                ("t_symbolic", C.c_double), ("t_numeric", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class peers_server_opts(C.Structure):
+    _fields_ = [("max_batch_pairs", C.c_int32), ("max_wait_us", C.c_int32),
+                ("queue_capacity", C.c_int32), ("streams", C.c_int32)]
+
+
+class peers_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("rejected", C.c_uint64),
+                ("batches", C.c_uint64), ("p50_us", C.c_double), ("p99_us", C.c_double),
+                ("max_us", C.c_double), ("resistances_per_s", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_vp = C.c_void_p
+_i32p = C.POINTER(C.c_int32)
+_i64p = C.POINTER(C.c_int64)
+_f64p = C.POINTER(C.c_double)
+
+# name -> (restype, argtypes); every name is an exported symbol of include/peers.h
+SIGNATURES = {
+    "peers_graph_create": (C.c_int, [C.c_int64, C.c_int64, _i32p, _i32p, _f64p, C.c_int32,
+                                     C.POINTER(peers_graph_opts), C.POINTER(_vp)]),
+    "peers_graph_stats_get": (C.c_int, [_vp, C.POINTER(peers_graph_stats)]),
+    "peers_graph_export_symbolic": (C.c_int, [_vp, _i32p, _i32p, _i64p, _i32p, _i32p]),
+    "peers_graph_export_factor": (C.c_int, [_vp, _f64p, _f64p]),
+    "peers_graph_destroy": (None, [_vp]),
+    "peers_device_open": (C.c_int, [C.c_int32, C.c_uint64, C.POINTER(_vp)]),
+    "peers_device_close": (None, [_vp]),
+    "peers_device_usage": (C.c_int, [_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+    "peers_factor_upload": (C.c_int, [_vp, _vp, _vp, C.POINTER(_vp)]),
+    "peers_factor_release": (None, [_vp]),
+    "peers_factor_footprint": (C.c_int, [_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+    "peers_query_all_edges": (C.c_int, [_vp, _vp, C.c_uint32, _vp]),
+    "peers_query": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, C.c_uint32, _vp]),
+    "peers_batch_query": (C.c_int, [_vp, C.c_int32, C.POINTER(_vp), _i64p, C.POINTER(_vp),
+                                    C.POINTER(_vp), C.POINTER(_vp), C.c_uint32, _vp]),
+    "peers_server_start": (C.c_int, [_vp, C.POINTER(peers_server_opts), C.POINTER(_vp)]),
+    "peers_server_submit": (C.c_int, [_vp, _vp, C.c_int64, _i32p, _i32p, _f64p, C.POINTER(C.c_uint64)]),
+    "peers_server_wait": (C.c_int, [_vp, C.c_uint64, C.c_int64, C.POINTER(C.c_int)]),
+    "peers_server_stats_get": (C.c_int, [_vp, C.POINTER(peers_server_stats)]),
+    "peers_server_stop": (C.c_int, [_vp]),
+    "peers_status_string": (C.c_char_p, [C.c_int]),
+    "peers_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libpeers.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libpeers.so not built at {LIB_PATH}; run paper_2606_31535_amd.build_lib")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status, where):
+    if status != PEERS_OK:
+        msg = lib().peers_last_error()
+        raise PeersError(status, where, msg.decode() if msg else "")
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    h = getattr(stream, "cuda_stream", None)
+    if h is not None:
+        return int(h)
+    raise TypeError("stream must be None, an int hipStream_t or a torch stream")
+
+
+def _buf_ptr(x):
+    """(pointer, is_device) of a numpy array or torch tensor."""
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data, False
+    if hasattr(x, "data_ptr"):
+        return int(x.data_ptr()), bool(getattr(x, "is_cuda", False))
+    raise TypeError("expected a numpy array or a torch tensor")
+
+
+# --------------------------------------------------------------------------- graph
+
+def peers_graph_create(n, eu, ev, w, ground=0, coords=None, ordering=PEERS_ORDER_AUTO,
+                       given_order=None, threads=0, leaf_size=0):
+    eu, ev, w = _i32(eu), _i32(ev), _f64(w)
+    if not (eu.shape == ev.shape == w.shape):
+        raise ValueError("eu, ev, w must have the same length")
+    opts = peers_graph_opts()
+    opts.ordering = ordering
+    keep = []
+    if coords is not None:
+        c = _f64(coords).reshape(n, 3)
+        keep.append(c)
+        opts.coords = _ptr(c, C.c_double)
+    if given_order is not None:
+        go = _i32(given_order)
+        keep.append(go)
+        opts.given_order = _ptr(go, C.c_int32)
+    opts.threads = threads
+    opts.leaf_size = leaf_size
+    h = _vp()
+    _check(lib().peers_graph_create(int(n), int(eu.shape[0]), _ptr(eu, C.c_int32), _ptr(ev, C.c_int32),
+                                    _ptr(w, C.c_double), int(ground), C.byref(opts), C.byref(h)),
+           "peers_graph_create")
+    return h
+
+
+def peers_graph_stats_get(g) -> dict:
+    s = peers_graph_stats()
+    _check(lib().peers_graph_stats_get(g, C.byref(s)), "peers_graph_stats_get")
+    return s.as_dict()
+
+
+def peers_graph_export_symbolic(g):
+    st = peers_graph_stats_get(g)
+    N, nnz, ns = st["N"], st["nnz_l"], st["n_supernodes"]
+    perm = np.empty(N, np.int32)
+    parent = np.empty(N, np.int32)
+    colptr = np.empty(N + 1, np.int64)
+    rowidx = np.empty(nnz, np.int32)
+    snptr = np.empty(ns + 1, np.int32)
+    _check(lib().peers_graph_export_symbolic(g, _ptr(perm, C.c_int32), _ptr(parent, C.c_int32),
+                                             _ptr(colptr, C.c_int64), _ptr(rowidx, C.c_int32),
+                                             _ptr(snptr, C.c_int32)), "peers_graph_export_symbolic")
+    return {"perm": perm, "parent": parent, "colptr": colptr, "rowidx": rowidx, "snptr": snptr}
+
+
+def peers_graph_export_factor(g):
+    st = peers_graph_stats_get(g)
+    Lx = np.empty(st["nnz_l"], np.float64)
+    D = np.empty(st["N"], np.float64)
+    _check(lib().peers_graph_export_factor(g, _ptr(Lx, C.c_double), _ptr(D, C.c_double)),
+           "peers_graph_export_factor")
+    return Lx, D
+
+
+def peers_graph_destroy(g):
+    if g:
+        lib().peers_graph_destroy(g)
+
+
+# --------------------------------------------------------------------------- device
+
+def peers_device_open(ordinal=0, hbm_budget_bytes=0):
+    h = _vp()
+    _check(lib().peers_device_open(int(ordinal), int(hbm_budget_bytes), C.byref(h)), "peers_device_open")
+    return h
+
+
+def peers_device_close(d):
+    if d:
+        lib().peers_device_close(d)
+
+
+def peers_device_usage(d):
+    used, budget = C.c_uint64(), C.c_uint64()
+    _check(lib().peers_device_usage(d, C.byref(used), C.byref(budget)), "peers_device_usage")
+    return used.value, budget.value
+
+
+def peers_factor_upload(d, g, stream=None):
+    h = _vp()
+    _check(lib().peers_factor_upload(d, g, _stream_handle(stream), C.byref(h)), "peers_factor_upload")
+    return h
+
+
+def peers_factor_release(f):
+    if f:
+        lib().peers_factor_release(f)
+
+
+def peers_factor_footprint(f):
+    a, b = C.c_uint64(), C.c_uint64()
+    _check(lib().peers_factor_footprint(f, C.byref(a), C.byref(b)), "peers_factor_footprint")
+    return a.value, b.value
+
+
+def peers_query_all_edges(f, R_out, flags=0, stream=None):
+    p, dev = _buf_ptr(R_out)
+    if dev:
+        flags |= PEERS_OUT_DEVICE
+    _check(lib().peers_query_all_edges(f, p, flags, _stream_handle(stream)), "peers_query_all_edges")
+    return R_out
+
+
+def peers_query(f, qu, qv, R_out, flags=0, stream=None):
+    pu, du = _buf_ptr(qu)
+    pv, dv = _buf_ptr(qv)
+    pr, dr = _buf_ptr(R_out)
+    if du != dv:
+        raise ValueError("qu and qv must live on the same side")
+    if du:
+        flags |= PEERS_IN_DEVICE
+    if dr:
+        flags |= PEERS_OUT_DEVICE
+    q = int(qu.shape[0])
+    _check(lib().peers_query(f, q, pu, pv, pr, flags, _stream_handle(stream)), "peers_query")
+    return R_out
+
+
+def peers_batch_query(d, factors, qus, qvs, R_outs, flags=0, stream=None):
+    nb = len(factors)
+    fa = (_vp * nb)(*factors)
+    qa = (C.c_int64 * nb)()
+    ua = (_vp * nb)()
+    va = (_vp * nb)()
+    ra = (_vp * nb)()
+    for i in range(nb):
+        if qus[i] is None:
+            ua[i] = None
+            va[i] = None
+            qa[i] = 0
+        else:
+            ua[i] = _buf_ptr(qus[i])[0]
+            va[i] = _buf_ptr(qvs[i])[0]
+            qa[i] = int(qus[i].shape[0])
+        p, dev = _buf_ptr(R_outs[i])
+        ra[i] = p
+        if dev:
+            flags |= PEERS_OUT_DEVICE
+    _check(lib().peers_batch_query(d, nb, fa, qa, ua, va, ra, flags, _stream_handle(stream)), "peers_batch_query")
+    return R_outs
+
+
+def peers_server_start(d, max_batch_pairs=0, max_wait_us=0, queue_capacity=0, streams=0):
+    o = peers_server_opts(max_batch_pairs, max_wait_us, queue_capacity, streams)
+    h = _vp()
+    _check(lib().peers_server_start(d, C.byref(o), C.byref(h)), "peers_server_start")
+    return h
+
+
+def peers_server_submit(s, f, qu, qv, R_out):
+    qu, qv = _i32(qu), _i32(qv)
+    t = C.c_uint64()
+    _check(lib().peers_server_submit(s, f, int(qu.shape[0]), _ptr(qu, C.c_int32), _ptr(qv, C.c_int32),
+                                     _ptr(R_out, C.c_double), C.byref(t)), "peers_server_submit")
+    return t.value, (qu, qv)
+
+
+def peers_server_wait(s, ticket, timeout_us=-1):
+    r = C.c_int()
+    st = lib().peers_server_wait(s, int(ticket), int(timeout_us), C.byref(r))
+    return st, r.value
+
+
+def peers_server_stats_get(s) -> dict:
+    o = peers_server_stats()
+    _check(lib().peers_server_stats_get(s, C.byref(o)), "peers_server_stats_get")
+    return o.as_dict()
+
+
+def peers_server_stop(s):
+    if s:
+        _check(lib().peers_server_stop(s), "peers_server_stop")
+
+
+def peers_status_string(st) -> str:
+    return lib().peers_status_string(int(st)).decode()
+
+
+def peers_last_error() -> str:
+    m = lib().peers_last_error()
+    return m.decode() if m else ""

@@ -1,0 +1,376 @@
+// Device half of the C ABI: device handles, factor upload into HBM, and the
+// plain all-edge / pair queries (Algorithm 8 steps 2-3 on one GPU).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+
+#include "../../../include/peers.h"
+#include "../host/graph_handle.h"
+#include "device_handle.h"
+#include "sweep_kernels.h"
+
+namespace peers {
+
+Status hip_fail(hipError_t e, const char* what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return E_HIP;
+}
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t _e = (expr);                             \
+    if (_e != hipSuccess) return hip_fail(_e, #expr);   \
+  } while (0)
+
+namespace {
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Packs host vectors into one device allocation.
+struct Packer {
+  struct Item { const void* src; size_t bytes; size_t off; void** dst; };
+  std::vector<Item> items;
+  size_t total = 0;
+  template <class T>
+  void add(const std::vector<T>& v, const T** dst) {
+    const size_t b = v.size() * sizeof(T);
+    items.push_back({v.data(), b, total, (void**)dst});
+    total = align_up(total + std::max<size_t>(b, 1), 256);
+  }
+  template <class T>
+  void add(const std::vector<T>& v, T** dst) { add(v, (const T**)dst); }
+  Status commit(void* base, hipStream_t s) {
+    for (auto& it : items) {
+      *it.dst = (char*)base + it.off;
+      if (it.bytes) HIP_TRY(hipMemcpyAsync((char*)base + it.off, it.src, it.bytes, hipMemcpyHostToDevice, s));
+    }
+    return OK;
+  }
+};
+
+}  // namespace
+
+Status DeviceHandle::reserve(uint64_t bytes) {
+  std::lock_guard<std::mutex> g(mu);
+  if (used + bytes > budget) {
+    set_error("HBM budget: " + std::to_string(used) + " used + " + std::to_string(bytes) + " requested > " +
+              std::to_string(budget));
+    return E_OVER_BUDGET;
+  }
+  used += bytes;
+  return OK;
+}
+
+void DeviceHandle::release(uint64_t bytes) {
+  std::lock_guard<std::mutex> g(mu);
+  used = bytes > used ? 0 : used - bytes;
+}
+
+Status upload_query_plan(FactorHandle& F, const QueryPlan& Q, DeviceQueryPlan& D, hipStream_t s) {
+  Packer pk;
+  pk.add(Q.bq_ptr, &D.args.bq_ptr);
+  pk.add(Q.bq_hicode, &D.args.bq_hicode);
+  pk.add(Q.bq_slot, &D.args.bq_slot);
+  pk.add(Q.bq_out, &D.args.bq_out);
+  pk.add(Q.bq_nwin, &D.args.bq_nwin);
+  pk.add(Q.tq_lo, &D.args.tq_lo);
+  pk.add(Q.tq_hi, &D.args.tq_hi);
+  pk.add(Q.tq_out, &D.args.tq_out);
+  pk.add(Q.zero_out, &D.args.zero_out);
+  D.args.nbq = (int64_t)Q.bq_out.size();
+  D.args.ntq = (int64_t)Q.tq_out.size();
+  D.args.nzero = (int64_t)Q.zero_out.size();
+  D.nslots = Q.nslots;
+  D.q = Q.q;
+  D.bytes = pk.total;
+  Status st = F.dev->reserve(D.bytes);
+  if (st != OK) return st;
+  hipError_t e = hipMalloc(&D.base, std::max<size_t>(D.bytes, 256));
+  if (e != hipSuccess) { F.dev->release(D.bytes); D.bytes = 0; return hip_fail(e, "hipMalloc(query plan)"); }
+  return pk.commit(D.base, s);
+}
+
+void free_query_plan(FactorHandle& F, DeviceQueryPlan& D) {
+  if (D.base) { (void)hipFree(D.base); F.dev->release(D.bytes); }
+  D.base = nullptr;
+  D.bytes = 0;
+}
+
+Status ensure_workspace(FactorHandle& F, int64_t nslots, int64_t nres) {
+  const uint64_t need_part = (uint64_t)std::max<int64_t>(nslots, 1) * 8;
+  const uint64_t need_res = (uint64_t)std::max<int64_t>(nres, 1) * 8;
+  if (need_part > F.part_bytes) {
+    if (F.part) { (void)hipFree(F.part); F.dev->release(F.part_bytes); F.part = nullptr; F.part_bytes = 0; }
+    Status st = F.dev->reserve(need_part);
+    if (st != OK) return st;
+    hipError_t e = hipMalloc(&F.part, need_part);
+    if (e != hipSuccess) { F.dev->release(need_part); return hip_fail(e, "hipMalloc(partials)"); }
+    F.part_bytes = need_part;
+  }
+  if (need_res > F.res_bytes) {
+    if (F.res) { (void)hipFree(F.res); F.dev->release(F.res_bytes); F.res = nullptr; F.res_bytes = 0; }
+    Status st = F.dev->reserve(need_res);
+    if (st != OK) return st;
+    hipError_t e = hipMalloc(&F.res, need_res);
+    if (e != hipSuccess) { F.dev->release(need_res); return hip_fail(e, "hipMalloc(results)"); }
+    F.res_bytes = need_res;
+  }
+  return OK;
+}
+
+Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t s) {
+  QueryArgs q = D.args;
+  q.part = (double*)F.part;
+  q.R = R_dev;
+  const FactorPlan& P = *F.plan;
+  for (int32_t l = 0; l < P.nlevels; ++l) {
+    const int64_t t0 = P.level_ptr[l], t1 = P.level_ptr[l + 1];
+    HIP_TRY(launch_top_level(F.sweep, t0, t1 - t0, s));
+  }
+  HIP_TRY(launch_bottom(F.sweep, q, (int64_t)P.bwork_task.size(), s));
+  HIP_TRY(launch_finish(F.sweep, q, s));
+  return OK;
+}
+
+Status build_query_plan_handle(const FactorHandle& F, int64_t q, const int32_t* a, const int32_t* b,
+                               QueryPlan& Q) {
+  return build_query_plan(F.first, F.depth, *F.plan, q, a, b, Q);
+}
+
+// Reduced-permuted index of an original node id (-1 for the ground).
+inline int32_t perm_index(const FactorHandle& F, int32_t x) {
+  if (x == F.ground) return -1;
+  return F.iperm[x < F.ground ? x : x - 1];
+}
+
+}  // namespace peers
+
+using namespace peers;
+
+extern "C" {
+
+peers_status peers_device_open(int32_t ordinal, uint64_t hbm_budget_bytes, peers_device* out) {
+  if (!out) { set_error("out is null"); return PEERS_E_INVALID_ARG; }
+  *out = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess) return (peers_status)hip_fail(e, "hipGetDeviceCount");
+  if (ordinal < 0 || ordinal >= count) { set_error("device ordinal out of range"); return PEERS_E_INVALID_ARG; }
+  e = hipSetDevice(ordinal);
+  if (e != hipSuccess) return (peers_status)hip_fail(e, "hipSetDevice");
+  size_t freeb = 0, total = 0;
+  e = hipMemGetInfo(&freeb, &total);
+  if (e != hipSuccess) return (peers_status)hip_fail(e, "hipMemGetInfo");
+  auto* D = new DeviceHandle();
+  D->ordinal = ordinal;
+  D->total = total;
+  D->budget = hbm_budget_bytes ? std::min<uint64_t>(hbm_budget_bytes, total) : (uint64_t)(0.9 * (double)total);
+  *out = reinterpret_cast<peers_device>(D);
+  return PEERS_OK;
+}
+
+void peers_device_close(peers_device d) { delete reinterpret_cast<DeviceHandle*>(d); }
+
+peers_status peers_device_usage(peers_device d, uint64_t* used, uint64_t* budget) {
+  if (!d) { set_error("null device"); return PEERS_E_INVALID_ARG; }
+  auto* D = reinterpret_cast<DeviceHandle*>(d);
+  std::lock_guard<std::mutex> g(D->mu);
+  if (used) *used = D->used;
+  if (budget) *budget = D->budget;
+  return PEERS_OK;
+}
+
+peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream, peers_factor* out) {
+  if (!d || !g || !out) { set_error("null argument"); return PEERS_E_INVALID_ARG; }
+  *out = nullptr;
+  auto* D = reinterpret_cast<DeviceHandle*>(d);
+  const GraphHandle& G = *reinterpret_cast<GraphHandle*>(g);
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipError_t he = hipSetDevice(D->ordinal);
+  if (he != hipSuccess) return (peers_status)hip_fail(he, "hipSetDevice");
+  std::unique_ptr<FactorHandle> F(new FactorHandle());
+  F->dev = D;
+  F->n = G.ing.n;
+  F->m = G.ing.m;
+  F->ground = G.ing.ground;
+  F->N = G.sym.N;
+  F->iperm = G.sym.iperm;
+  F->first = G.sym.first;
+  F->depth = G.sym.depth;
+  F->plan.reset(new FactorPlan());
+  Status st = build_plan(G.sym, G.num, *F->plan);
+  if (st != OK) return (peers_status)st;
+  const FactorPlan& P = *F->plan;
+  // resident all-edge query plan
+  {
+    std::vector<int32_t> a(F->m), b(F->m);
+    for (int64_t e = 0; e < F->m; ++e) {
+      a[e] = perm_index(*F, G.eu[e]);
+      b[e] = perm_index(*F, G.ev[e]);
+      if (G.eu[e] == G.ev[e]) a[e] = b[e];  // self-loop: R = 0
+    }
+    QueryPlan Q;
+    st = build_query_plan(F->first, F->depth, P, F->m, a.data(), b.data(), Q);
+    if (st != OK) return (peers_status)st;
+    if (Q.n_general) { set_error("internal: an edge whose endpoints are not etree-related"); return PEERS_E_INTERNAL; }
+    st = upload_query_plan(*F, Q, F->edges, s);
+    if (st != OK) return (peers_status)st;
+  }
+  Packer pk;
+  SweepArgs& A = F->sweep;
+  pk.add(P.task_chunk, &A.task_chunk);
+  pk.add(P.task_win, &A.task_win);
+  pk.add(P.chunks, &A.chunks);
+  pk.add(P.ext_off, &A.ext_off);
+  pk.add(P.ext_depth, &A.ext_depth);
+  pk.add(P.coef, &A.coef);
+  pk.add(P.tri, &A.tri);
+  pk.add(P.top_off, &A.top_off);
+  pk.add(P.top_depth, &A.top_depth);
+  pk.add(P.top_isd, &A.top_isd);
+  pk.add(P.bwork_task, &A.bwork_task);
+  pk.add(P.bwork_win, &A.bwork_win);
+  pk.add(P.btask_ptr, &A.btask_ptr);
+  pk.add(P.bnodes, &A.bnodes);
+  pk.add(P.bent_ptr, &A.bent_ptr);
+  pk.add(P.bent_src, &A.bent_src);
+  pk.add(P.bent_coef, &A.bent_coef);
+  pk.add(P.bdepth, &A.depth);
+  pk.add(P.isd, &A.isd);
+  pk.add(P.lslot, &A.lslot);
+  F->resident_bytes = pk.total;
+  F->store_bytes = (uint64_t)std::max<int64_t>(P.store_elems, 1) * 8;
+  st = D->reserve(F->resident_bytes + F->store_bytes);
+  if (st != OK) { free_query_plan(*F, F->edges); return (peers_status)st; }
+  F->reserved = F->resident_bytes + F->store_bytes;
+  he = hipMalloc(&F->base, F->resident_bytes);
+  if (he != hipSuccess) return (peers_status)hip_fail(he, "hipMalloc(factor)");
+  he = hipMalloc(&F->store, F->store_bytes);
+  if (he != hipSuccess) return (peers_status)hip_fail(he, "hipMalloc(top store)");
+  A.store = (double*)F->store;
+  st = pk.commit(F->base, s);
+  if (st != OK) return (peers_status)st;
+  st = ensure_workspace(*F, F->edges.nslots, F->m);
+  if (st != OK) return (peers_status)st;
+  he = hipStreamSynchronize(s);
+  if (he != hipSuccess) return (peers_status)hip_fail(he, "hipStreamSynchronize(upload)");
+  // host-side copies of the plan are only needed for query planning now
+  FactorPlan& Pm = *F->plan;
+  std::vector<double>().swap(Pm.coef);
+  std::vector<double>().swap(Pm.tri);
+  std::vector<double>().swap(Pm.bent_coef);
+  std::vector<int32_t>().swap(Pm.bent_src);
+  *out = reinterpret_cast<peers_factor>(F.release());
+  return PEERS_OK;
+}
+
+void peers_factor_release(peers_factor f) {
+  if (!f) return;
+  auto* F = reinterpret_cast<FactorHandle*>(f);
+  (void)hipSetDevice(F->dev->ordinal);
+  (void)hipDeviceSynchronize();
+  free_query_plan(*F, F->edges);
+  if (F->base) (void)hipFree(F->base);
+  if (F->store) (void)hipFree(F->store);
+  if (F->part) (void)hipFree(F->part);
+  if (F->res) (void)hipFree(F->res);
+  F->dev->release(F->reserved + F->part_bytes + F->res_bytes);
+  delete F;
+}
+
+peers_status peers_factor_footprint(peers_factor f, uint64_t* resident_bytes, uint64_t* workspace_bytes) {
+  if (!f) { set_error("null factor"); return PEERS_E_INVALID_ARG; }
+  auto* F = reinterpret_cast<FactorHandle*>(f);
+  if (resident_bytes) *resident_bytes = F->resident_bytes + F->edges.bytes;
+  if (workspace_bytes) *workspace_bytes = F->store_bytes + F->part_bytes + F->res_bytes;
+  return PEERS_OK;
+}
+
+peers_status peers_query_all_edges(peers_factor f, double* R_out, uint32_t flags, void* hip_stream) {
+  if (!f || (!R_out && reinterpret_cast<FactorHandle*>(f)->m > 0)) { set_error("null argument"); return PEERS_E_INVALID_ARG; }
+  auto* F = reinterpret_cast<FactorHandle*>(f);
+  hipStream_t s = (hipStream_t)hip_stream;
+  std::lock_guard<std::mutex> g(F->mu);
+  hipError_t he = hipSetDevice(F->dev->ordinal);
+  if (he != hipSuccess) return (peers_status)hip_fail(he, "hipSetDevice");
+  if (F->m == 0) return PEERS_OK;
+  const bool dev_out = flags & PEERS_OUT_DEVICE;
+  double* Rd = dev_out ? R_out : (double*)F->res;
+  Status st = run_sweep(*F, F->edges, Rd, s);
+  if (st != OK) return (peers_status)st;
+  if (!dev_out) {
+    he = hipMemcpyAsync(R_out, Rd, sizeof(double) * F->m, hipMemcpyDeviceToHost, s);
+    if (he != hipSuccess) return (peers_status)hip_fail(he, "hipMemcpyAsync(results)");
+  }
+  if (!dev_out || (flags & PEERS_SYNC)) {
+    he = hipStreamSynchronize(s);
+    if (he != hipSuccess) return (peers_status)hip_fail(he, "hipStreamSynchronize");
+  }
+  return PEERS_OK;
+}
+
+peers_status peers_query(peers_factor f, int64_t q, const int32_t* qu, const int32_t* qv, double* R_out,
+                         uint32_t flags, void* hip_stream) {
+  if (!f || q < 0 || (q > 0 && (!qu || !qv || !R_out))) { set_error("null argument"); return PEERS_E_INVALID_ARG; }
+  auto* F = reinterpret_cast<FactorHandle*>(f);
+  hipStream_t s = (hipStream_t)hip_stream;
+  std::lock_guard<std::mutex> g(F->mu);
+  hipError_t he = hipSetDevice(F->dev->ordinal);
+  if (he != hipSuccess) return (peers_status)hip_fail(he, "hipSetDevice");
+  if (q == 0) return PEERS_OK;
+  std::vector<int32_t> hu, hv;
+  const int32_t* u = qu;
+  const int32_t* v = qv;
+  if (flags & PEERS_IN_DEVICE) {
+    hu.resize(q);
+    hv.resize(q);
+    he = hipMemcpyAsync(hu.data(), qu, sizeof(int32_t) * q, hipMemcpyDeviceToHost, s);
+    if (he == hipSuccess) he = hipMemcpyAsync(hv.data(), qv, sizeof(int32_t) * q, hipMemcpyDeviceToHost, s);
+    if (he == hipSuccess) he = hipStreamSynchronize(s);
+    if (he != hipSuccess) return (peers_status)hip_fail(he, "copy query pairs");
+    u = hu.data();
+    v = hv.data();
+  }
+  std::vector<int32_t> a(q), b(q);
+  for (int64_t k = 0; k < q; ++k) {
+    if (u[k] < 0 || u[k] >= F->n || v[k] < 0 || v[k] >= F->n) {
+      set_error("query " + std::to_string(k) + " has a node id outside [0, n)");
+      return PEERS_E_NODE_RANGE;
+    }
+    a[k] = perm_index(*F, u[k]);
+    b[k] = perm_index(*F, v[k]);
+    if (u[k] == v[k]) a[k] = b[k];
+  }
+  QueryPlan Q;
+  Status st = build_query_plan_handle(*F, q, a.data(), b.data(), Q);
+  if (st != OK) return (peers_status)st;
+  if (Q.n_general) {
+    set_error(std::to_string(Q.n_general) + " pairs are not ancestor-related in the elimination tree");
+    return PEERS_E_UNSUPPORTED;
+  }
+  DeviceQueryPlan DQ;
+  st = upload_query_plan(*F, Q, DQ, s);
+  if (st != OK) return (peers_status)st;
+  st = ensure_workspace(*F, DQ.nslots, q);
+  if (st == OK) {
+    const bool dev_out = flags & PEERS_OUT_DEVICE;
+    double* Rd = dev_out ? R_out : (double*)F->res;
+    st = run_sweep(*F, DQ, Rd, s);
+    if (st == OK && !dev_out) {
+      he = hipMemcpyAsync(R_out, Rd, sizeof(double) * q, hipMemcpyDeviceToHost, s);
+      if (he != hipSuccess) st = hip_fail(he, "hipMemcpyAsync(results)");
+    }
+  }
+  he = hipStreamSynchronize(s);
+  free_query_plan(*F, DQ);
+  if (st != OK) return (peers_status)st;
+  if (he != hipSuccess) return (peers_status)hip_fail(he, "hipStreamSynchronize");
+  return PEERS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,59 @@
+// Device and factor handles shared by the plain, batched and served paths.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "../host/plan.h"
+#include "sweep_kernels.h"
+
+namespace peers {
+
+struct DeviceHandle {
+  int32_t ordinal = 0;
+  uint64_t total = 0;
+  uint64_t budget = 0;
+  uint64_t used = 0;
+  std::mutex mu;
+  Status reserve(uint64_t bytes);
+  void release(uint64_t bytes);
+};
+
+struct DeviceQueryPlan {
+  void* base = nullptr;
+  uint64_t bytes = 0;
+  QueryArgs args{};
+  int64_t nslots = 0;
+  int64_t q = 0;
+};
+
+struct FactorHandle {
+  DeviceHandle* dev = nullptr;
+  int64_t n = 0, m = 0;
+  int32_t ground = 0;
+  int32_t N = 0;
+  std::vector<int32_t> iperm;  // reduced id -> permuted index
+  std::vector<int32_t> first, depth;
+  std::unique_ptr<FactorPlan> plan;
+  SweepArgs sweep{};
+  void* base = nullptr;
+  void* store = nullptr;
+  void* part = nullptr;
+  void* res = nullptr;
+  uint64_t resident_bytes = 0, store_bytes = 0, part_bytes = 0, res_bytes = 0, reserved = 0;
+  DeviceQueryPlan edges;  // all-edge queries, resident
+  std::mutex mu;          // one sweep at a time per factor (shared top store)
+};
+
+Status hip_fail(hipError_t e, const char* what);
+Status upload_query_plan(FactorHandle& F, const QueryPlan& Q, DeviceQueryPlan& D, hipStream_t s);
+void free_query_plan(FactorHandle& F, DeviceQueryPlan& D);
+Status ensure_workspace(FactorHandle& F, int64_t nslots, int64_t nres);
+Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t s);
+Status build_query_plan_handle(const FactorHandle& F, int64_t q, const int32_t* a, const int32_t* b,
+                               QueryPlan& Q);
+
+}  // namespace peers

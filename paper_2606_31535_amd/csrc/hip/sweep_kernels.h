@@ -1,0 +1,65 @@
+// Device kernels of the implicit-inverse sweep (gfx950, wave64, FP64).
+//
+// Layout and notation are those of host/plan.h: lanes of a wavefront are 64
+// consecutive depths d of a window, and the value a lane holds for node i is
+// z_i[d] = Z_{a_d(i), i}, the entry of the inverse Cholesky factor in the row
+// of i's ancestor at depth d+1 (eq 11: Z_jj = D_j^{-1/2}, Z_ji = sum over
+// H-edges (k, i) of w~_ki Z_jk with w~_ki = -L_ki for unit-lower L).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../host/plan.h"
+
+namespace peers {
+
+struct SweepArgs {
+  // top tree
+  const int32_t* task_chunk;
+  const int32_t* task_win;
+  const TopChunk* chunks;
+  const int64_t* ext_off;
+  const int32_t* ext_depth;
+  const double* coef;
+  const double* tri;
+  const int64_t* top_off;
+  const int32_t* top_depth;
+  const double* top_isd;
+  double* store;
+  // bottom subtrees
+  const int32_t* bwork_task;
+  const int32_t* bwork_win;
+  const int32_t* btask_ptr;
+  const int32_t* bnodes;
+  const int64_t* bent_ptr;
+  const int32_t* bent_src;
+  const double* bent_coef;
+  const int32_t* depth;
+  const double* isd;
+  const int32_t* lslot;
+};
+
+struct QueryArgs {
+  const int32_t* bq_ptr;
+  const int32_t* bq_hicode;
+  const int64_t* bq_slot;
+  const int64_t* bq_out;
+  const int32_t* bq_nwin;
+  int64_t nbq;
+  const int32_t* tq_lo;
+  const int32_t* tq_hi;
+  const int64_t* tq_out;
+  int64_t ntq;
+  const int64_t* zero_out;
+  int64_t nzero;
+  double* part;
+  double* R;
+};
+
+hipError_t launch_top_level(const SweepArgs& a, int64_t task0, int64_t ntasks, hipStream_t s);
+hipError_t launch_bottom(const SweepArgs& a, const QueryArgs& q, int64_t nwork, hipStream_t s);
+hipError_t launch_finish(const SweepArgs& a, const QueryArgs& q, hipStream_t s);
+
+}  // namespace peers

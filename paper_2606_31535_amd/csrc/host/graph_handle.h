@@ -1,0 +1,21 @@
+// The host graph handle: ingest + ordering + symbolic + numeric results and the
+// statistics reported through the C ABI.
+#pragma once
+
+#include "../../../include/peers.h"
+#include "host.h"
+
+namespace peers {
+
+struct GraphHandle {
+  Ingested ing;
+  Symbolic sym;
+  Numeric num;
+  peers_graph_stats stats{};
+  std::vector<int32_t> eu, ev;  // the input edge list (all-edge queries in input order)
+};
+
+Status build_graph(int64_t n, int64_t m, const int32_t* eu, const int32_t* ev, const double* w, int32_t ground,
+                   const peers_graph_opts& o, GraphHandle& G);
+
+}  // namespace peers
