@@ -126,8 +126,26 @@ peers_status peers_factor_footprint(peers_factor f, uint64_t* resident_bytes, ui
 enum {
   PEERS_OUT_DEVICE = 1u,    /* R_out is a device pointer (else host memory) */
   PEERS_IN_DEVICE = 2u,     /* qu/qv are device pointers (peers_query only) */
-  PEERS_SYNC = 4u           /* synchronize the stream before returning */
+  PEERS_SYNC = 4u,          /* synchronize the stream before returning */
+  PEERS_PROFILE = 8u        /* record per-phase HIP event times (peers_factor_timings) */
 };
+
+/* Per-phase device times of the last sweep on this factor, recorded with HIP
+ * events on the caller's stream when the sweep ran with PEERS_PROFILE set
+ * (milliseconds; 0 for phases that did not run). */
+typedef struct {
+  double top_ms;      /* top tree: separator chains (dense blocks) */
+  double bottom_ms;   /* bottom subtrees: path sweep with LDS path stacks */
+  double finish_ms;   /* ordered window reduction, top-node queries, zero pairs */
+  double total_ms;
+  int32_t top_launches;
+  int32_t bottom_launches;
+  double top_flops;     /* algorithmic FP64 flops of the top phase (2 per FMA) */
+  double bottom_flops;  /* algorithmic FP64 flops of the bottom phase */
+  double top_bytes;     /* algorithmic HBM bytes of the top phase */
+  double bottom_bytes;  /* algorithmic HBM bytes of the bottom phase */
+} peers_sweep_timings;
+peers_status peers_factor_timings(peers_factor f, peers_sweep_timings* out);
 
 /* All-edge effective resistances (Section III-G, eq 12): R_out[e] for every
  * input edge e in input order (m values; self-loops give +0.0). */

@@ -26,7 +26,7 @@ STATUS_NAMES = {
     -10: "E_CANCELLED", -11: "E_TIMEOUT", -12: "E_UNSUPPORTED", -99: "E_INTERNAL",
 }
 PEERS_ORDER_AUTO, PEERS_ORDER_COORD, PEERS_ORDER_GRAPH, PEERS_ORDER_GIVEN = 0, 1, 2, 3
-PEERS_OUT_DEVICE, PEERS_IN_DEVICE, PEERS_SYNC = 1, 2, 4
+PEERS_OUT_DEVICE, PEERS_IN_DEVICE, PEERS_SYNC, PEERS_PROFILE = 1, 2, 4, 8
 
 
 class PeersError(RuntimeError):
@@ -46,6 +46,16 @@ class peers_graph_stats(C.Structure):
                 ("n_roots", C.c_int32), ("self_loops", C.c_int64), ("f_sweep", C.c_double),
                 ("acc_terms", C.c_double), ("t_ingest", C.c_double), ("t_order", C.c_double),
                 ("t_symbolic", C.c_double), ("t_numeric", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class peers_sweep_timings(C.Structure):
+    _fields_ = [("top_ms", C.c_double), ("bottom_ms", C.c_double), ("finish_ms", C.c_double),
+                ("total_ms", C.c_double), ("top_launches", C.c_int32), ("bottom_launches", C.c_int32),
+                ("top_flops", C.c_double), ("bottom_flops", C.c_double), ("top_bytes", C.c_double),
+                ("bottom_bytes", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -84,6 +94,7 @@ SIGNATURES = {
     "peers_factor_upload": (C.c_int, [_vp, _vp, _vp, C.POINTER(_vp)]),
     "peers_factor_release": (None, [_vp]),
     "peers_factor_footprint": (C.c_int, [_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+    "peers_factor_timings": (C.c_int, [_vp, C.POINTER(peers_sweep_timings)]),
     "peers_query_all_edges": (C.c_int, [_vp, _vp, C.c_uint32, _vp]),
     "peers_query": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, C.c_uint32, _vp]),
     "peers_batch_query": (C.c_int, [_vp, C.c_int32, C.POINTER(_vp), _i64p, C.POINTER(_vp),
@@ -248,6 +259,12 @@ def peers_factor_footprint(f):
     a, b = C.c_uint64(), C.c_uint64()
     _check(lib().peers_factor_footprint(f, C.byref(a), C.byref(b)), "peers_factor_footprint")
     return a.value, b.value
+
+
+def peers_factor_timings(f) -> dict:
+    o = peers_sweep_timings()
+    _check(lib().peers_factor_timings(f, C.byref(o)), "peers_factor_timings")
+    return o.as_dict()
 
 
 def peers_query_all_edges(f, R_out, flags=0, stream=None):

@@ -123,17 +123,26 @@ Status ensure_workspace(FactorHandle& F, int64_t nslots, int64_t nres) {
   return OK;
 }
 
-Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t s) {
+Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t s, bool profile) {
   QueryArgs q = D.args;
   q.part = (double*)F.part;
   q.R = R_dev;
   const FactorPlan& P = *F.plan;
+  if (profile && !F.ev[0])
+    for (auto& e : F.ev) HIP_TRY(hipEventCreate(&e));
+  F.timed = profile;
+  if (profile) HIP_TRY(hipEventRecord(F.ev[0], s));
   for (int32_t l = 0; l < P.nlevels; ++l) {
     const int64_t t0 = P.level_ptr[l], t1 = P.level_ptr[l + 1];
     HIP_TRY(launch_top_level(F.sweep, t0, t1 - t0, s));
   }
+  F.top_launches = P.nlevels;
+  if (profile) HIP_TRY(hipEventRecord(F.ev[1], s));
   HIP_TRY(launch_bottom(F.sweep, q, (int64_t)P.bwork_task.size(), s));
+  F.bottom_launches = P.bwork_task.empty() ? 0 : 1;
+  if (profile) HIP_TRY(hipEventRecord(F.ev[2], s));
   HIP_TRY(launch_finish(F.sweep, q, s));
+  if (profile) HIP_TRY(hipEventRecord(F.ev[3], s));
   return OK;
 }
 
@@ -259,6 +268,22 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
   if (st != OK) return (peers_status)st;
   he = hipStreamSynchronize(s);
   if (he != hipSuccess) return (peers_status)hip_fail(he, "hipStreamSynchronize(upload)");
+  {
+    // algorithmic work per phase: 2 flops per FMA of the exact count
+    // F = sum over L_ki != 0 of depth(k) restricted to the phase's columns,
+    // and 12 bytes (value + row index) per factor entry plus the top store
+    double fb = 0, nb = 0, nt = 0;
+    for (int32_t i = 0; i < G.sym.N; ++i) {
+      double fi = 0;
+      for (int64_t p = G.sym.colptr[i]; p < G.sym.colptr[i + 1]; ++p) fi += G.sym.depth[G.sym.rowidx[p]];
+      if (P.small[i]) { fb += fi; nb += (double)(G.sym.colptr[i + 1] - G.sym.colptr[i]); }
+      else nt += (double)(G.sym.colptr[i + 1] - G.sym.colptr[i]);
+    }
+    F->top_flops = 2.0 * P.f_top;
+    F->bottom_flops = 2.0 * fb;
+    F->top_bytes = 12.0 * nt + 8.0 * (double)P.store_elems;
+    F->bottom_bytes = 12.0 * nb + 16.0 * (double)F->m;
+  }
   // host-side copies of the plan are only needed for query planning now
   FactorPlan& Pm = *F->plan;
   std::vector<double>().swap(Pm.coef);
@@ -277,6 +302,8 @@ void peers_factor_release(peers_factor f) {
   free_query_plan(*F, F->edges);
   if (F->base) (void)hipFree(F->base);
   if (F->store) (void)hipFree(F->store);
+  for (auto& e : F->ev)
+    if (e) (void)hipEventDestroy(e);
   if (F->part) (void)hipFree(F->part);
   if (F->res) (void)hipFree(F->res);
   F->dev->release(F->reserved + F->part_bytes + F->res_bytes);
@@ -291,6 +318,32 @@ peers_status peers_factor_footprint(peers_factor f, uint64_t* resident_bytes, ui
   return PEERS_OK;
 }
 
+peers_status peers_factor_timings(peers_factor f, peers_sweep_timings* out) {
+  if (!f || !out) { set_error("null argument"); return PEERS_E_INVALID_ARG; }
+  auto* F = reinterpret_cast<FactorHandle*>(f);
+  std::lock_guard<std::mutex> g(F->mu);
+  *out = peers_sweep_timings{};
+  out->top_launches = F->top_launches;
+  out->bottom_launches = F->bottom_launches;
+  out->top_flops = F->top_flops;
+  out->bottom_flops = F->bottom_flops;
+  out->top_bytes = F->top_bytes;
+  out->bottom_bytes = F->bottom_bytes;
+  if (!F->timed) return PEERS_OK;
+  hipError_t e = hipEventSynchronize(F->ev[3]);
+  if (e != hipSuccess) return (peers_status)hip_fail(e, "hipEventSynchronize");
+  float ms[3] = {0, 0, 0};
+  for (int k = 0; k < 3; ++k) {
+    e = hipEventElapsedTime(&ms[k], F->ev[k], F->ev[k + 1]);
+    if (e != hipSuccess) return (peers_status)hip_fail(e, "hipEventElapsedTime");
+  }
+  out->top_ms = ms[0];
+  out->bottom_ms = ms[1];
+  out->finish_ms = ms[2];
+  out->total_ms = (double)ms[0] + ms[1] + ms[2];
+  return PEERS_OK;
+}
+
 peers_status peers_query_all_edges(peers_factor f, double* R_out, uint32_t flags, void* hip_stream) {
   if (!f || (!R_out && reinterpret_cast<FactorHandle*>(f)->m > 0)) { set_error("null argument"); return PEERS_E_INVALID_ARG; }
   auto* F = reinterpret_cast<FactorHandle*>(f);
@@ -301,7 +354,7 @@ peers_status peers_query_all_edges(peers_factor f, double* R_out, uint32_t flags
   if (F->m == 0) return PEERS_OK;
   const bool dev_out = flags & PEERS_OUT_DEVICE;
   double* Rd = dev_out ? R_out : (double*)F->res;
-  Status st = run_sweep(*F, F->edges, Rd, s);
+  Status st = run_sweep(*F, F->edges, Rd, s, flags & PEERS_PROFILE);
   if (st != OK) return (peers_status)st;
   if (!dev_out) {
     he = hipMemcpyAsync(R_out, Rd, sizeof(double) * F->m, hipMemcpyDeviceToHost, s);
@@ -360,7 +413,7 @@ peers_status peers_query(peers_factor f, int64_t q, const int32_t* qu, const int
   if (st == OK) {
     const bool dev_out = flags & PEERS_OUT_DEVICE;
     double* Rd = dev_out ? R_out : (double*)F->res;
-    st = run_sweep(*F, DQ, Rd, s);
+    st = run_sweep(*F, DQ, Rd, s, flags & PEERS_PROFILE);
     if (st == OK && !dev_out) {
       he = hipMemcpyAsync(R_out, Rd, sizeof(double) * q, hipMemcpyDeviceToHost, s);
       if (he != hipSuccess) st = hip_fail(he, "hipMemcpyAsync(results)");

@@ -46,13 +46,18 @@ struct FactorHandle {
   uint64_t resident_bytes = 0, store_bytes = 0, part_bytes = 0, res_bytes = 0, reserved = 0;
   DeviceQueryPlan edges;  // all-edge queries, resident
   std::mutex mu;          // one sweep at a time per factor (shared top store)
+  // per-phase timing of the last profiled sweep
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool timed = false;
+  int32_t top_launches = 0, bottom_launches = 0;
+  double top_flops = 0, bottom_flops = 0, top_bytes = 0, bottom_bytes = 0;
 };
 
 Status hip_fail(hipError_t e, const char* what);
 Status upload_query_plan(FactorHandle& F, const QueryPlan& Q, DeviceQueryPlan& D, hipStream_t s);
 void free_query_plan(FactorHandle& F, DeviceQueryPlan& D);
 Status ensure_workspace(FactorHandle& F, int64_t nslots, int64_t nres);
-Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t s);
+Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t s, bool profile);
 Status build_query_plan_handle(const FactorHandle& F, int64_t q, const int32_t* a, const int32_t* b,
                                QueryPlan& Q);
 
