@@ -123,6 +123,20 @@ Status ensure_workspace(FactorHandle& F, int64_t nslots, int64_t nres) {
   return OK;
 }
 
+// L_CC^{-1} of every top chain into F.X: 64 x 64 diagonal inverses, then per
+// recursion height T = L21 X11 and X21 = -X22 T. Returns the launch count.
+static Status run_chain_inverse(FactorHandle& F, hipStream_t s, int32_t& launches) {
+  const FactorPlan& P = *F.plan;
+  HIP_TRY(launch_inv_base(F.sweep, s));
+  launches += P.base_blocks.empty() ? 0 : 1;
+  for (int32_t h = 1; h <= P.inv_heights; ++h) {
+    HIP_TRY(launch_gemm(F.gemm, P.inv_X_ptr[h - 1], P.inv_T_ptr[h] - P.inv_X_ptr[h - 1], s));
+    HIP_TRY(launch_gemm(F.gemm, P.inv_T_ptr[h], P.inv_X_ptr[h] - P.inv_T_ptr[h], s));
+    launches += 2;
+  }
+  return OK;
+}
+
 Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t s, bool profile) {
   QueryArgs q = D.args;
   q.part = (double*)F.part;
@@ -132,11 +146,16 @@ Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t
     for (auto& e : F.ev) HIP_TRY(hipEventCreate(&e));
   F.timed = profile;
   if (profile) HIP_TRY(hipEventRecord(F.ev[0], s));
-  for (int32_t l = 0; l < P.nlevels; ++l) {
-    const int64_t t0 = P.level_ptr[l], t1 = P.level_ptr[l + 1];
-    HIP_TRY(launch_top_level(F.sweep, t0, t1 - t0, s));
+  int32_t launches = 0;
+  Status st = run_chain_inverse(F, s, launches);
+  if (st != OK) return st;
+  HIP_TRY(launch_chain_rows(F.sweep, P.ntop, s));
+  launches += P.ntop > 0 ? 1 : 0;
+  for (size_t l = 0; l + 1 < P.t2_ptr.size(); ++l) {
+    HIP_TRY(launch_gemm(F.gemm, P.t2_ptr[l], P.t2_ptr[l + 1] - P.t2_ptr[l], s));
+    ++launches;
   }
-  F.top_launches = P.nlevels;
+  F.top_launches = launches;
   if (profile) HIP_TRY(hipEventRecord(F.ev[1], s));
   HIP_TRY(launch_bottom(F.sweep, q, (int64_t)P.bwork_task.size(), s));
   F.bottom_launches = P.bwork_task.empty() ? 0 : 1;
@@ -232,13 +251,16 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
   }
   Packer pk;
   SweepArgs& A = F->sweep;
-  pk.add(P.task_chunk, &A.task_chunk);
-  pk.add(P.task_win, &A.task_win);
-  pk.add(P.chunks, &A.chunks);
-  pk.add(P.ext_off, &A.ext_off);
-  pk.add(P.ext_depth, &A.ext_depth);
-  pk.add(P.coef, &A.coef);
-  pk.add(P.tri, &A.tri);
+  GemmArgs& GA = F->gemm;
+  const double* lcc_dev = nullptr;
+  pk.add(P.chains, &A.chains);
+  pk.add(P.base_blocks, &A.base_blocks);
+  pk.add(P.top_chain, &A.top_chain);
+  pk.add(P.top_node, &A.top_node);
+  pk.add(P.lcc, &lcc_dev);
+  pk.add(P.u_off, &GA.gather);
+  pk.add(P.probs, &GA.probs);
+  pk.add(P.tasks, &GA.tasks);
   pk.add(P.top_off, &A.top_off);
   pk.add(P.top_depth, &A.top_depth);
   pk.add(P.top_isd, &A.top_isd);
@@ -252,17 +274,58 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
   pk.add(P.bdepth, &A.depth);
   pk.add(P.isd, &A.isd);
   pk.add(P.lslot, &A.lslot);
-  F->resident_bytes = pk.total;
-  F->store_bytes = (uint64_t)std::max<int64_t>(P.store_elems, 1) * 8;
-  st = D->reserve(F->resident_bytes + F->store_bytes);
+  A.nbase = (int32_t)P.base_blocks.size();
+  F->resident_bytes = pk.total + (uint64_t)std::max<int64_t>(P.bt_elems, 1) * 8;
+  F->store_bytes = (uint64_t)(std::max<int64_t>(P.store_elems, 1) + std::max<int64_t>(P.x_elems, 1) +
+                              std::max<int64_t>(P.t_elems, 1)) * 8;
+  const uint64_t luc_bytes = (uint64_t)std::max<int64_t>(P.bt_elems, 1) * 8;
+  st = D->reserve(F->resident_bytes + F->store_bytes + luc_bytes);
   if (st != OK) { free_query_plan(*F, F->edges); return (peers_status)st; }
   F->reserved = F->resident_bytes + F->store_bytes;
-  he = hipMalloc(&F->base, F->resident_bytes);
-  if (he != hipSuccess) return (peers_status)hip_fail(he, "hipMalloc(factor)");
-  he = hipMalloc(&F->store, F->store_bytes);
-  if (he != hipSuccess) return (peers_status)hip_fail(he, "hipMalloc(top store)");
+  he = hipMalloc(&F->base, pk.total);
+  if (he != hipSuccess) { D->release(luc_bytes); return (peers_status)hip_fail(he, "hipMalloc(factor)"); }
+  he = hipMalloc(&F->store, (size_t)std::max<int64_t>(P.store_elems, 1) * 8);
+  if (he == hipSuccess) he = hipMalloc(&F->xbuf, (size_t)std::max<int64_t>(P.x_elems, 1) * 8);
+  if (he == hipSuccess) he = hipMalloc(&F->tbuf, (size_t)std::max<int64_t>(P.t_elems, 1) * 8);
+  if (he == hipSuccess) he = hipMalloc(&F->btbuf, (size_t)std::max<int64_t>(P.bt_elems, 1) * 8);
+  void* lucbuf = nullptr;
+  if (he == hipSuccess) he = hipMalloc(&lucbuf, luc_bytes);
+  if (he != hipSuccess) { D->release(luc_bytes); return (peers_status)hip_fail(he, "hipMalloc(top workspace)"); }
   A.store = (double*)F->store;
+  A.X = (double*)F->xbuf;
   st = pk.commit(F->base, s);
+  if (st != OK) { (void)hipFree(lucbuf); D->release(luc_bytes); return (peers_status)st; }
+  A.lcc = lcc_dev;
+  GA.buf[BUF_STORE] = (double*)F->store;
+  GA.buf[BUF_LCC] = const_cast<double*>(lcc_dev);
+  GA.buf[BUF_X] = (double*)F->xbuf;
+  GA.buf[BUF_T] = (double*)F->tbuf;
+  GA.buf[BUF_BT] = (double*)F->btbuf;
+  GA.buf[BUF_LUC] = (double*)lucbuf;
+  // zero the triangular-inverse workspace once (its upper blocks are never written)
+  // and the transfer blocks' padding; then B_C = -L_{U,C} L_CC^{-1} on the GPU
+  he = hipMemsetAsync(F->xbuf, 0, (size_t)std::max<int64_t>(P.x_elems, 1) * 8, s);
+  if (he == hipSuccess) he = hipMemsetAsync(F->btbuf, 0, (size_t)std::max<int64_t>(P.bt_elems, 1) * 8, s);
+  if (he == hipSuccess && !P.luc.empty())
+    he = hipMemcpyAsync(lucbuf, P.luc.data(), P.luc.size() * 8, hipMemcpyHostToDevice, s);
+  if (he != hipSuccess) { (void)hipFree(lucbuf); D->release(luc_bytes); return (peers_status)hip_fail(he, "upload"); }
+  {
+    const double t0 = now_s();
+    int32_t nl = 0;
+    st = run_chain_inverse(*F, s, nl);
+    if (st == OK) {
+      he = launch_gemm(F->gemm, P.bpre_begin, P.bpre_end - P.bpre_begin, s);
+      if (he != hipSuccess) st = hip_fail(he, "transfer blocks");
+    }
+    if (st == OK) {
+      he = hipStreamSynchronize(s);
+      if (he != hipSuccess) st = hip_fail(he, "hipStreamSynchronize(transfer blocks)");
+    }
+    F->t_transform = now_s() - t0;
+  }
+  (void)hipFree(lucbuf);
+  D->release(luc_bytes);
+  GA.buf[BUF_LUC] = nullptr;
   if (st != OK) return (peers_status)st;
   st = ensure_workspace(*F, F->edges.nslots, F->m);
   if (st != OK) return (peers_status)st;
@@ -279,15 +342,15 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
       if (P.small[i]) { fb += fi; nb += (double)(G.sym.colptr[i + 1] - G.sym.colptr[i]); }
       else nt += (double)(G.sym.colptr[i + 1] - G.sym.colptr[i]);
     }
-    F->top_flops = 2.0 * P.f_top;
+    F->top_flops = 2.0 * P.f_top;  // exact count; the blocked forms do f_top_gemm + f_top_inv
     F->bottom_flops = 2.0 * fb;
     F->top_bytes = 12.0 * nt + 8.0 * (double)P.store_elems;
     F->bottom_bytes = 12.0 * nb + 16.0 * (double)F->m;
   }
   // host-side copies of the plan are only needed for query planning now
   FactorPlan& Pm = *F->plan;
-  std::vector<double>().swap(Pm.coef);
-  std::vector<double>().swap(Pm.tri);
+  std::vector<double>().swap(Pm.lcc);
+  std::vector<double>().swap(Pm.luc);
   std::vector<double>().swap(Pm.bent_coef);
   std::vector<int32_t>().swap(Pm.bent_src);
   *out = reinterpret_cast<peers_factor>(F.release());
@@ -302,6 +365,9 @@ void peers_factor_release(peers_factor f) {
   free_query_plan(*F, F->edges);
   if (F->base) (void)hipFree(F->base);
   if (F->store) (void)hipFree(F->store);
+  if (F->xbuf) (void)hipFree(F->xbuf);
+  if (F->tbuf) (void)hipFree(F->tbuf);
+  if (F->btbuf) (void)hipFree(F->btbuf);
   for (auto& e : F->ev)
     if (e) (void)hipEventDestroy(e);
   if (F->part) (void)hipFree(F->part);

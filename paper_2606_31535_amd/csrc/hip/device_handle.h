@@ -39,8 +39,13 @@ struct FactorHandle {
   std::vector<int32_t> first, depth;
   std::unique_ptr<FactorPlan> plan;
   SweepArgs sweep{};
+  GemmArgs gemm{};
   void* base = nullptr;
   void* store = nullptr;
+  void* xbuf = nullptr;   // L_CC^{-1} workspace
+  void* tbuf = nullptr;   // recursion temporaries
+  void* btbuf = nullptr;  // transfer blocks B_C (resident)
+  double t_transform = 0;
   void* part = nullptr;
   void* res = nullptr;
   uint64_t resident_bytes = 0, store_bytes = 0, part_bytes = 0, res_bytes = 0, reserved = 0;

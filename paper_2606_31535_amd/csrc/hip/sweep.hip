@@ -1,15 +1,13 @@
 // HIP kernels of the implicit sweep (Section III-C eq 11, Section III-G eq 12).
 //
-//  * top_chunk_kernel: one workgroup per (top chunk, window). A chunk is up to
-//    kChunk consecutive columns of one supernode. Its columns share the
-//    ancestors ext = struct(L_:,b), so the window values are a dense product
-//    of the ext columns' window (read from the top store) with the chunk's
-//    coefficient panel, done with FP64 MFMA tiles (v_mfma_f64_16x16x4f64:
-//    both operands stay in VGPRs, so neither LDS nor scalar registers carry
-//    the reuse), followed by the chunk's own unit-lower triangle on VALU
-//    with scalar-broadcast coefficients. The four waves split the ancestors
-//    and combine in LDS in a fixed order. Launched level by level down the
-//    chunk tree.
+//  * top tree (chains of separator nodes, see host/plan.h): gemm_kernel is a
+//    generic FP64 MFMA GEMM (v_mfma_f64_16x16x4f64; both operands stay in
+//    VGPRs, so neither LDS nor scalar registers carry the reuse) driven by task
+//    lists. It forms L_CC^{-1} of every chain by recursive 2x2 blocking on top
+//    of inv_base_kernel's 64 x 64 diagonal inverses; chain_rows_kernel writes
+//    the chain rows D^{-1/2} L_CC^{-1} of every top column; then, chain level
+//    by chain level, Z[rows above C, C] = Z[rows above C, U_C] B_C with the
+//    ancestor columns gathered straight from the top store.
 //  * bottom_kernel: one wavefront per (bottom subtree task, window). Nodes are
 //    visited in descending index, a topological order of every row's
 //    traversal; the values of the current root path live in an LDS stack
@@ -39,127 +37,177 @@ __device__ __forceinline__ T load_uniform(const T* p) {
   return *(const __attribute__((address_space(4))) T*)p;
 }
 
-__global__ __launch_bounds__(256) void top_chunk_kernel(SweepArgs A, int64_t task0) {
-  // partial 64 x kChunk tiles of waves 1..3 in the MFMA register layout, then
-  // wave 0's row-major copy of the sum (reusing the same buffer)
-  __shared__ double red[3][kChunk / 16 * 4][4][kWin];
-  const int64_t task = task0 + blockIdx.x;
-  const int32_t c = A.task_chunk[task];
-  const int32_t t = A.task_win[task];
-  const TopChunk ch = A.chunks[c];
+// Reduction loop of gemm_kernel for indices [e0, e1) in steps of 4 (one
+// v_mfma_f64_16x16x4f64 k-group). Every load is unconditional: indices past
+// e1 are clamped to a valid column and their B value is zeroed at use, so the
+// loop body has no branches and each load is waited for only right before its
+// MFMAs. Gathered column offsets come through the scalar unit one step ahead.
+template <bool GATHER>
+__device__ __forceinline__ void gemm_accumulate(f64x4 (&C)[4][2], const double* __restrict__ A,
+                                                const double* __restrict__ B, const int64_t* __restrict__ gt,
+                                                const GemmProb& pb, const int32_t (&rows)[4], const int32_t (&cols)[2],
+                                                int kk, int32_t e0, int32_t e1) {
+  struct Cols { int64_t g[4]; };
+  auto gathers = [&](int32_t e) -> Cols {
+    Cols c{};
+    if (GATHER) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) c.g[j] = load_uniform(gt + min(e + j, e1 - 1));
+    }
+    return c;
+  };
+  auto load = [&](int32_t e, const Cols& gc, double (&a)[4], double (&b)[2]) {
+    const int32_t ec = min(e + kk, e1 - 1);
+    int64_t acol;
+    if (GATHER) {
+      acol = gc.g[0];
+      acol = kk == 1 ? gc.g[1] : acol;
+      acol = kk == 2 ? gc.g[2] : acol;
+      acol = kk == 3 ? gc.g[3] : acol;
+    } else {
+      acol = pb.a_off + (int64_t)ec * pb.lda;
+    }
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) a[rb] = A[acol + rows[rb]];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) b[cb] = B[(int64_t)cols[cb] * pb.ldb + ec];
+  };
+  auto mma = [&](int32_t e, const double (&a)[4], const double (&b)[2]) {
+    const bool ok = e + kk < e1;
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      const double bv = ok ? b[cb] : 0.0;
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) C[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb], bv, C[rb][cb], 0, 0, 0);
+    }
+  };
+  // two operand buffers, each loaded one step before its MFMAs
+  double a0[4], b0[2], a1[4], b1[2];
+  load(e0, gathers(e0), a0, b0);
+  Cols g1 = gathers(e0 + 4);
+  for (int32_t e = e0; e < e1; e += 8) {
+    load(e + 4, g1, a1, b1);
+    const Cols g0 = gathers(e + 8);
+    mma(e, a0, b0);
+    load(e + 8, g0, a0, b0);
+    g1 = gathers(e + 12);
+    mma(e + 4, a1, b1);
+  }
+}
+
+// C[M x N] = alpha * A[M x K] * B[K x N] for one 64 x 32 output tile over the
+// reduction range [k0, k1) of its task. v_mfma_f64_16x16x4f64 operands:
+// A lane l = (row l%16, k l/16), B lane l = (k l/16, col l%16), C lane l reg
+// r = (row 4r + l/16, col l%16). The four waves take consecutive quarters of
+// the reduction range (multiples of 4) and are summed in LDS in wave order,
+// so the result does not depend on scheduling.
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs G, int64_t task0) {
+  __shared__ double red[3][8][4][kWin];
+  const GemmTask tk = G.tasks[task0 + blockIdx.x];
+  const GemmProb pb = G.probs[tk.prob];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int32_t d0 = t * kWin;
-  // ext depths strictly decrease along ext (all are ancestors of b), so the
-  // ancestors reaching this window form a prefix of ext
-  int32_t lo = 0, hi = ch.next;
-  const int32_t* ed = A.ext_depth + ch.ext_begin;
-  while (lo < hi) {
-    const int32_t mid = (lo + hi) >> 1;
-    if (ed[mid] > d0) lo = mid + 1; else hi = mid;
-  }
-  const int32_t ne = lo;
-  const int32_t per = ((ne + 15) >> 4) << 2;  // multiple of 4 ancestors per wave
-  const int32_t e0 = min(ne, wave * per), e1 = min(ne, e0 + per);
-  // G (64 rows x kChunk cols) = Z[window, ext] * Cf[ext, chunk] with
-  // v_mfma_f64_16x16x4f64: A operand lane l = (row l%16, k l/16),
-  // B operand lane l = (k l/16, col l%16), C lane l reg r = (row 4r + l/16, col l%16).
-  constexpr int RB = kWin / 16, CB = kChunk / 16;
-  f64x4 C[RB][CB];
-#pragma unroll
-  for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb) C[rb][cb] = f64x4{0.0, 0.0, 0.0, 0.0};
   const int kk = lane >> 4, ii = lane & 15;
-  const double* __restrict__ cf = A.coef + ch.coef_begin;
-  const int64_t* __restrict__ eo = A.ext_off + ch.ext_begin;
-  // operands of the 4 ancestors starting at e; lanes past e1 read a valid
-  // address and contribute zero
-  auto load_step = [&](int32_t e, double (&a)[RB], double (&b)[CB]) {
-    const int32_t ek = e + kk;
-    const bool ok = ek < e1;
-    const int32_t ec = ok ? ek : e1 - 1;
-    const double* zc = A.store + eo[ec] + d0 + ii;
-    const double* bc = cf + (int64_t)ec * kChunk + ii;
+  const double* __restrict__ A = G.buf[pb.a_buf];
+  const double* __restrict__ B = G.buf[pb.b_buf] + pb.b_off;
+  const int32_t nk = tk.k1 - tk.k0;
+  const int32_t per = ((nk + 15) >> 4) << 2;
+  const int32_t e0 = tk.k0 + min(nk, wave * per);
+  const int32_t e1 = tk.k0 + min(nk, wave * per + per);
+  int32_t rows[4], cols[2];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) a[rb] = zc[16 * rb];
+  for (int rb = 0; rb < 4; ++rb) rows[rb] = min(tk.row0 + 16 * rb + ii, pb.M - 1);
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) b[cb] = bc[16 * cb];
+  for (int cb = 0; cb < 2; ++cb) cols[cb] = min(tk.col0 + 16 * cb + ii, pb.N - 1);
+  const int64_t* __restrict__ gt = G.gather + (pb.gather ? pb.aoff_begin : 0);
+  // operands of the 4 reduction indices starting at e. Every load is
+  // unconditional: indices past e1 are clamped to a valid column and their B
+  // value is zeroed at use, so the loop body has no branches and each load is
+  // waited for only right before its MFMAs.
+  f64x4 C[4][2];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) a[rb] = ok ? a[rb] : 0.0;
+  for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) b[cb] = ok ? b[cb] : 0.0;
-  };
+    for (int cb = 0; cb < 2; ++cb) C[rb][cb] = f64x4{0.0, 0.0, 0.0, 0.0};
   if (e0 < e1) {
-    double a[RB], b[CB];
-    load_step(e0, a, b);
-    for (int32_t e = e0; e < e1; e += 4) {
-      double an[RB], bn[CB];
-      const bool more = e + 4 < e1;
-      if (more) load_step(e + 4, an, bn);
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) C[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb], b[cb], C[rb][cb], 0, 0, 0);
-      if (more) {
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) a[rb] = an[rb];
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) b[cb] = bn[cb];
-      }
-    }
+    if (pb.gather) gemm_accumulate<true>(C, A, B, gt, pb, rows, cols, kk, e0, e1);
+    else gemm_accumulate<false>(C, A, B, gt, pb, rows, cols, kk, e0, e1);
   }
   if (wave > 0) {
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
+    for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb)
+      for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) red[wave - 1][rb * CB + cb][r][lane] = C[rb][cb][r];
+        for (int r = 0; r < 4; ++r) red[wave - 1][rb * 2 + cb][r][lane] = C[rb][cb][r];
   }
   __syncthreads();
   if (wave == 0) {
 #pragma unroll
     for (int w = 0; w < 3; ++w)
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
+      for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb)
+        for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) C[rb][cb][r] += red[w][rb * CB + cb][r][lane];
+          for (int r = 0; r < 4; ++r) C[rb][cb][r] += red[w][rb * 2 + cb][r][lane];
   }
   __syncthreads();
-  // wave 0 re-lays the sum out row-major (row = window depth, padded stride);
-  // every wave has finished reading the partial slabs at this point
-  double* rowm = &red[0][0][0][0];
-  constexpr int LD = kChunk + 1;
-  static_assert(kWin * LD <= 3 * (kChunk / 16 * 4) * 4 * kWin, "row-major tile must fit the reduction buffer");
+  constexpr int LD = kTileN + 1;
+  double* tile = &red[0][0][0][0];
   if (wave == 0) {
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
+    for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb)
+      for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) rowm[(16 * rb + 4 * r + kk) * LD + 16 * cb + ii] = C[rb][cb][r];
+        for (int r = 0; r < 4; ++r) tile[(16 * rb + 4 * r + kk) * LD + 16 * cb + ii] = C[rb][cb][r];
   }
   __syncthreads();
-  if (wave != 0) return;
-  double acc[kChunk];
-#pragma unroll
-  for (int j = 0; j < kChunk; ++j) acc[j] = rowm[lane * LD + j];
-  // the chunk's own unit-lower triangle, highest column first (eq 11)
-  const double* __restrict__ tr = A.tri + ch.tri_begin;
-  const int32_t wc = ch.b - ch.a + 1;
-  const int32_t d = d0 + lane;
-#pragma unroll
-  for (int j = kChunk - 1; j >= 0; --j) {
-    if (j < wc) {
-      const int32_t dep = ch.depth_b + (wc - 1 - j);  // depth of node a + j
-      if (d == dep - 1) acc[j] = A.top_isd[ch.top_a + j];
-#pragma unroll
-      for (int jj = 0; jj < j; ++jj) acc[jj] = fma(load_uniform(tr + j * kChunk + jj), acc[j], acc[jj]);
-      if (d0 < dep) A.store[A.top_off[ch.top_a + j] + d0 + lane] = acc[j];
-    }
+  double* __restrict__ Cm = G.buf[pb.c_buf] + pb.c_off;
+  for (int idx = threadIdx.x; idx < kTileM * kTileN; idx += 256) {
+    const int r = idx & (kTileM - 1), c = idx / kTileM;
+    const int32_t gr = tk.row0 + r, gc = tk.col0 + c;
+    if (gr < pb.M && gc < pb.N) Cm[(int64_t)gc * pb.ldc + gr] = pb.alpha * tile[r * LD + c];
+  }
+}
+
+// Inverse of one diagonal block (at most 64 x 64) of a chain's unit-lower
+// L_CC by forward substitution: lane j holds column j of the inverse.
+__global__ __launch_bounds__(64) void inv_base_kernel(SweepArgs A) {
+  __shared__ double Ls[kBase][kBase + 1];
+  __shared__ double Xs[kBase][kBase + 1];
+  const BaseBlock bb = A.base_blocks[blockIdx.x];
+  const Chain c = A.chains[bb.chain];
+  const int lane = threadIdx.x;
+  const int n = bb.size, lo = bb.lo;
+  const double* Lb = A.lcc + c.lcc_off + (int64_t)lo * c.ldl + lo;
+  for (int j = 0; j < n; ++j) Ls[lane][j] = lane < n ? Lb[(int64_t)j * c.ldl + lane] : 0.0;
+  __syncthreads();
+  for (int i = 0; i < n; ++i) {
+    double s = i == lane ? 1.0 : 0.0;
+    for (int k = 0; k < i; ++k) s = fma(-Ls[i][k], Xs[k][lane], s);
+    Xs[i][lane] = i >= lane ? s : 0.0;
+  }
+  __syncthreads();
+  double* Xb = A.X + c.x_off + (int64_t)lo * c.ldl + lo;
+  for (int j = 0; j < n; ++j)
+    if (lane < n) Xb[(int64_t)j * c.ldl + lane] = Xs[lane][j];
+}
+
+// Rows of a top column that lie inside its own chain (Z[C, C] = D^{-1/2} L_CC^{-1})
+// and the zero padding below the column's depth. One workgroup per top column.
+__global__ __launch_bounds__(256) void chain_rows_kernel(SweepArgs A) {
+  const int32_t k = blockIdx.x;
+  const Chain c = A.chains[A.top_chain[k]];
+  const int32_t j = A.top_node[k] - c.a;
+  const int64_t nrow = c.ld - c.dp;
+  double* col = A.store + c.store_base + (int64_t)j * c.ld + c.dp;
+  const double* xc = A.X + c.x_off + (int64_t)j * c.ldl;
+  for (int64_t r = threadIdx.x; r < nrow; r += 256) {
+    double v = 0.0;
+    if (r < c.w - j) v = A.isd[c.b - r] * xc[c.w - 1 - r];
+    col[r] = v;
   }
 }
 
@@ -243,9 +291,21 @@ __global__ __launch_bounds__(256) void zero_kernel(QueryArgs Q) {
 
 }  // namespace
 
-hipError_t launch_top_level(const SweepArgs& a, int64_t task0, int64_t ntasks, hipStream_t s) {
+hipError_t launch_gemm(const GemmArgs& g, int64_t task0, int64_t ntasks, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(top_chunk_kernel, dim3((unsigned)ntasks), dim3(256), 0, s, a, task0);
+  hipLaunchKernelGGL(gemm_kernel, dim3((unsigned)ntasks), dim3(256), 0, s, g, task0);
+  return hipGetLastError();
+}
+
+hipError_t launch_inv_base(const SweepArgs& a, hipStream_t s) {
+  if (a.nbase <= 0) return hipSuccess;
+  hipLaunchKernelGGL(inv_base_kernel, dim3((unsigned)a.nbase), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_chain_rows(const SweepArgs& a, int32_t ntop, hipStream_t s) {
+  if (ntop <= 0) return hipSuccess;
+  hipLaunchKernelGGL(chain_rows_kernel, dim3((unsigned)ntop), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -15,15 +15,23 @@
 
 namespace peers {
 
+// Generic FP64 GEMM over task lists (see GemmProb / GemmTask in host/plan.h).
+struct GemmArgs {
+  double* buf[BUF_COUNT];
+  const GemmProb* probs;
+  const GemmTask* tasks;
+  const int64_t* gather;
+};
+
 struct SweepArgs {
   // top tree
-  const int32_t* task_chunk;
-  const int32_t* task_win;
-  const TopChunk* chunks;
-  const int64_t* ext_off;
-  const int32_t* ext_depth;
-  const double* coef;
-  const double* tri;
+  const Chain* chains;
+  const BaseBlock* base_blocks;
+  int32_t nbase;
+  const int32_t* top_chain;
+  const int32_t* top_node;
+  const double* lcc;
+  double* X;
   const int64_t* top_off;
   const int32_t* top_depth;
   const double* top_isd;
@@ -58,7 +66,9 @@ struct QueryArgs {
   double* R;
 };
 
-hipError_t launch_top_level(const SweepArgs& a, int64_t task0, int64_t ntasks, hipStream_t s);
+hipError_t launch_gemm(const GemmArgs& g, int64_t task0, int64_t ntasks, hipStream_t s);
+hipError_t launch_inv_base(const SweepArgs& a, hipStream_t s);
+hipError_t launch_chain_rows(const SweepArgs& a, int32_t ntop, hipStream_t s);
 hipError_t launch_bottom(const SweepArgs& a, const QueryArgs& q, int64_t nwork, hipStream_t s);
 hipError_t launch_finish(const SweepArgs& a, const QueryArgs& q, hipStream_t s);
 

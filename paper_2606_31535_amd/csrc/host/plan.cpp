@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <functional>
 
 namespace peers {
 
@@ -35,82 +36,230 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
     if (P.small[i]) continue;
     P.top_index[i] = (int32_t)P.top_node.size();
     P.top_node.push_back(i);
-    P.top_off.push_back(P.store_elems);
+    P.top_off.push_back(-1);
     P.top_depth.push_back(S.depth[i]);
     P.top_isd.push_back(P.isd[i]);
-    P.store_elems += (int64_t)nwin_of(S.depth[i]) * kWin;
   }
   P.ntop = (int32_t)P.top_node.size();
 
-  // ---------------------------------------------------------------- top chunks
-  const int32_t ns = (int32_t)S.snptr.size() - 1;
-  std::vector<int32_t> chunk_of(N, -1);
-  for (int32_t s = ns - 1; s >= 0; --s) {
-    const int32_t f = S.snptr[s], l = S.snptr[s + 1] - 1;
-    if (P.small[l]) continue;
-    int32_t x = l;
-    while (x > f && !P.small[x - 1]) --x;
-    for (int32_t b = l; b >= x;) {
-      const int32_t a = std::max(x, b - kChunk + 1);
-      TopChunk c{};
-      c.a = a;
-      c.b = b;
-      c.depth_b = S.depth[b];
-      c.top_a = P.top_index[a];
-      const int64_t e0 = S.colptr[b], e1 = S.colptr[b + 1];
-      c.next = (int32_t)(e1 - e0);
-      c.ext_begin = (int64_t)P.ext_top.size();
-      for (int64_t p = e0; p < e1; ++p) {
-        const int32_t k = S.rowidx[p];
-        if (P.top_index[k] < 0) { set_error("plan: an ancestor of a top node is not top"); return E_INTERNAL; }
-        P.ext_top.push_back(P.top_index[k]);
-        P.ext_off.push_back(P.top_off[P.top_index[k]]);
-        P.ext_depth.push_back(S.depth[k]);
+  // ---------------------------------------------------------------- top chains
+  // maximal runs a..b of top nodes with parent(i) = i+1 (top indices of a run
+  // are consecutive because top nodes are numbered in increasing node order)
+  P.top_chain.assign(P.ntop, -1);
+  std::vector<int32_t> chain_of(N, -1);
+  for (int32_t t = 0; t < P.ntop;) {
+    const int32_t a = P.top_node[t];
+    int32_t b = a, t2 = t;
+    while (t2 + 1 < P.ntop && P.top_node[t2 + 1] == b + 1 && S.parent[b] == b + 1) { ++b; ++t2; }
+    Chain c{};
+    c.a = a;
+    c.b = b;
+    c.w = b - a + 1;
+    c.dp = S.parent[b] < 0 ? 0 : S.depth[S.parent[b]];
+    for (int32_t v = a; v <= b; ++v) {
+      chain_of[v] = (int32_t)P.chains.size();
+      P.top_chain[P.top_index[v]] = (int32_t)P.chains.size();
+    }
+    P.chains.push_back(c);
+    t = t2 + 1;
+  }
+  const int32_t nch = (int32_t)P.chains.size();
+  // levels (parents first: chains with larger node indices come later)
+  for (int32_t ci = nch - 1; ci >= 0; --ci) {
+    Chain& c = P.chains[ci];
+    const int32_t pb = S.parent[c.b];
+    c.level = pb < 0 ? 0 : P.chains[chain_of[pb]].level + 1;
+    P.nchain_levels = std::max(P.nchain_levels, c.level + 1);
+  }
+  // U_C, store layout, dense blocks
+  std::vector<int32_t> mark(N, -1), upos(N, -1);
+  int64_t lcc_elems = 0, luc_elems = 0;
+  P.store_elems = 0;
+  for (int32_t ci = 0; ci < nch; ++ci) {
+    Chain& c = P.chains[ci];
+    std::vector<int32_t> U;
+    for (int32_t v = c.a; v <= c.b; ++v)
+      for (int64_t p = S.colptr[v]; p < S.colptr[v + 1]; ++p) {
+        const int32_t r = S.rowidx[p];
+        if (r > c.b && mark[r] != ci) { mark[r] = ci; U.push_back(r); }
       }
-      const int32_t wc = b - a + 1;
-      c.coef_begin = (int64_t)P.coef.size();
-      P.coef.resize(P.coef.size() + (size_t)c.next * kChunk, 0.0);
-      for (int32_t j = 0; j < wc; ++j) {
-        const int64_t base = S.colptr[a + j] + (b - a - j);
-        for (int32_t e = 0; e < c.next; ++e) P.coef[c.coef_begin + (int64_t)e * kChunk + j] = -F.Lx[base + e];
-      }
-      c.tri_begin = (int64_t)P.tri.size();
-      P.tri.resize(P.tri.size() + (size_t)kChunk * kChunk, 0.0);
-      for (int32_t j = 0; j < wc; ++j)
-        for (int32_t jj = 0; jj < j; ++jj) {
-          const int64_t p = S.colptr[a + jj] + (j - jj - 1);
-          if (S.rowidx[p] != a + j) { set_error("plan: chunk is not a dense chain"); return E_INTERNAL; }
-          P.tri[c.tri_begin + (int64_t)j * kChunk + jj] = -F.Lx[p];
+    std::sort(U.begin(), U.end());
+    c.nU = (int32_t)U.size();
+    c.u_begin = (int64_t)P.u_off.size();
+    for (int32_t e = 0; e < c.nU; ++e) {
+      if (P.top_index[U[e]] < 0) { set_error("plan: an ancestor of a top node is not top"); return E_INTERNAL; }
+      P.u_depth.push_back(S.depth[U[e]]);
+      P.u_off.push_back(-1);  // filled once every chain has its store base
+    }
+    c.ld = (int64_t)nwin_of(c.dp + c.w) * kWin;
+    c.store_base = P.store_elems;
+    P.store_elems += c.ld * c.w;
+    for (int32_t j = 0; j < c.w; ++j) P.top_off[P.top_index[c.a + j]] = c.store_base + (int64_t)j * c.ld;
+    c.ldl = (int64_t)nwin_of(c.w) * kWin;
+    c.lcc_off = lcc_elems;
+    c.x_off = lcc_elems;
+    lcc_elems += c.ldl * c.w;
+    c.ldb = (int64_t)nwin_of(std::max(c.nU, 1)) * kWin;
+    c.bt_off = luc_elems;
+    c.luc_off = luc_elems;
+    luc_elems += c.nU > 0 ? c.ldb * c.w : 0;
+  }
+  // gather table: store offset of every U_C column (needs all store bases)
+  {
+    std::vector<int32_t> Ulist;
+    for (int32_t ci = 0; ci < nch; ++ci) {
+      const Chain& c = P.chains[ci];
+      Ulist.clear();
+      for (int32_t v = c.a; v <= c.b; ++v)
+        for (int64_t p = S.colptr[v]; p < S.colptr[v + 1]; ++p) {
+          const int32_t r = S.rowidx[p];
+          if (r > c.b) Ulist.push_back(r);
         }
-      // level: one more than the chunk holding b's parent
-      const int32_t pb = S.parent[b];
-      c.level = pb < 0 ? 0 : P.chunks[chunk_of[pb]].level + 1;
-      const int32_t cid = (int32_t)P.chunks.size();
-      for (int32_t v = a; v <= b; ++v) chunk_of[v] = cid;
-      P.chunks.push_back(c);
-      for (int32_t v = a; v <= b; ++v)
-        for (int64_t p = S.colptr[v]; p < S.colptr[v + 1]; ++p) P.f_top += S.depth[S.rowidx[p]];
-      b = a - 1;
+      std::sort(Ulist.begin(), Ulist.end());
+      Ulist.erase(std::unique(Ulist.begin(), Ulist.end()), Ulist.end());
+      if ((int32_t)Ulist.size() != c.nU) { set_error("plan: inconsistent U"); return E_INTERNAL; }
+      for (int32_t e = 0; e < c.nU; ++e) P.u_off[c.u_begin + e] = P.top_off[P.top_index[Ulist[e]]];
     }
   }
-  int32_t maxlev = -1;
-  for (const auto& c : P.chunks) maxlev = std::max(maxlev, c.level);
-  P.nlevels = maxlev + 1;
+  // dense L_CC (unit diagonal stored) and L_{U,C}, column-major
+  P.lcc.assign(lcc_elems, 0.0);
+  P.luc.assign(luc_elems, 0.0);
   {
-    std::vector<int64_t> cnt(P.nlevels + 1, 0);
-    for (const auto& c : P.chunks) cnt[c.level + 1] += nwin_of(S.depth[c.a]);
-    for (int32_t l = 0; l < P.nlevels; ++l) cnt[l + 1] += cnt[l];
-    P.level_ptr = cnt;
-    P.task_chunk.assign(cnt[P.nlevels], 0);
-    P.task_win.assign(cnt[P.nlevels], 0);
-    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
-    for (int32_t ci = 0; ci < (int32_t)P.chunks.size(); ++ci) {
-      const auto& c = P.chunks[ci];
-      const int32_t nw = nwin_of(S.depth[c.a]);
-      for (int32_t t = 0; t < nw; ++t) {
-        P.task_chunk[fill[c.level]] = ci;
-        P.task_win[fill[c.level]++] = t;
+    std::vector<int32_t> Ulist;
+    for (int32_t ci = 0; ci < nch; ++ci) {
+      const Chain& c = P.chains[ci];
+      Ulist.clear();
+      for (int32_t v = c.a; v <= c.b; ++v)
+        for (int64_t p = S.colptr[v]; p < S.colptr[v + 1]; ++p)
+          if (S.rowidx[p] > c.b) Ulist.push_back(S.rowidx[p]);
+      std::sort(Ulist.begin(), Ulist.end());
+      Ulist.erase(std::unique(Ulist.begin(), Ulist.end()), Ulist.end());
+      for (int32_t e = 0; e < c.nU; ++e) upos[Ulist[e]] = e;
+      for (int32_t j = 0; j < c.w; ++j) {
+        const int32_t v = c.a + j;
+        P.lcc[c.lcc_off + (int64_t)j * c.ldl + j] = 1.0;
+        for (int64_t p = S.colptr[v]; p < S.colptr[v + 1]; ++p) {
+          const int32_t r = S.rowidx[p];
+          if (r <= c.b) P.lcc[c.lcc_off + (int64_t)j * c.ldl + (r - c.a)] = F.Lx[p];
+          else P.luc[c.luc_off + (int64_t)j * c.ldb + upos[r]] = F.Lx[p];
+        }
+        for (int64_t p = S.colptr[v]; p < S.colptr[v + 1]; ++p) P.f_top += S.depth[S.rowidx[p]];
       }
+    }
+  }
+  P.x_elems = lcc_elems;
+  P.bt_elems = luc_elems;
+
+  // ---------------------------------------------------------------- GEMM task lists
+  auto add_tiles = [&](int32_t prob, int32_t M, int32_t Nn, auto krange) {
+    for (int32_t r0 = 0; r0 < M; r0 += kTileM)
+      for (int32_t c0 = 0; c0 < Nn; c0 += kTileN) {
+        int32_t k0, k1;
+        krange(r0, c0, k0, k1);
+        P.tasks.push_back(GemmTask{prob, r0, c0, k0, k1});
+      }
+  };
+  // upload: B_C = -L_{U,C} L_CC^{-1} (B operand lower triangular: k >= column)
+  P.bpre_begin = (int64_t)P.tasks.size();
+  for (int32_t ci = 0; ci < nch; ++ci) {
+    const Chain& c = P.chains[ci];
+    if (c.nU == 0) continue;
+    GemmProb g{};
+    g.a_buf = BUF_LUC; g.a_off = c.luc_off; g.lda = c.ldb; g.aoff_begin = -1; g.gather = 0;
+    g.b_buf = BUF_X; g.b_off = c.x_off; g.ldb = c.ldl;
+    g.c_buf = BUF_BT; g.c_off = c.bt_off; g.ldc = c.ldb;
+    g.M = c.nU; g.N = c.w; g.K = c.w; g.alpha = -1.0;
+    const int32_t pid = (int32_t)P.probs.size();
+    P.probs.push_back(g);
+    add_tiles(pid, g.M, g.N, [&](int32_t, int32_t c0, int32_t& k0, int32_t& k1) { k0 = c0; k1 = g.K; });
+    P.f_bpre += (double)c.nU * c.w * c.w / 2.0;
+  }
+  P.bpre_end = (int64_t)P.tasks.size();
+  // recursive blocked inverse of every L_CC: merge nodes by height
+  struct Merge { int32_t chain, lo, mid, hi; };
+  std::vector<std::vector<Merge>> by_height(1);
+  std::function<int(int32_t, int32_t, int32_t)> rec = [&](int32_t ci, int32_t lo, int32_t hi) -> int {
+    if (hi - lo <= kBase) {
+      P.base_blocks.push_back(BaseBlock{ci, lo, hi - lo});
+      return 0;
+    }
+    const int32_t nb = (hi - lo + kBase - 1) / kBase;
+    const int32_t mid = lo + (nb / 2) * kBase;
+    const int h = 1 + std::max(rec(ci, lo, mid), rec(ci, mid, hi));
+    if ((int)by_height.size() <= h) by_height.resize(h + 1);
+    by_height[h].push_back(Merge{ci, lo, mid, hi});
+    return h;
+  };
+  for (int32_t ci = 0; ci < nch; ++ci) rec(ci, 0, P.chains[ci].w);
+  P.inv_heights = (int32_t)by_height.size() - 1;
+  P.inv_T_ptr.assign(1, (int64_t)P.tasks.size());
+  P.inv_X_ptr.assign(1, (int64_t)P.tasks.size());
+  P.t_elems = 1;
+  for (int32_t h = 1; h <= P.inv_heights; ++h) {
+    int64_t toff = 0;
+    std::vector<int64_t> tof;
+    for (const Merge& mg : by_height[h]) {
+      const Chain& c = P.chains[mg.chain];
+      const int32_t n1 = mg.mid - mg.lo, n2 = mg.hi - mg.mid;
+      const int64_t ldt = (int64_t)nwin_of(n2) * kWin;
+      tof.push_back(toff);
+      GemmProb g{};
+      g.a_buf = BUF_LCC; g.a_off = c.lcc_off + (int64_t)mg.lo * c.ldl + mg.mid; g.lda = c.ldl; g.aoff_begin = -1;
+      g.b_buf = BUF_X; g.b_off = c.x_off + (int64_t)mg.lo * c.ldl + mg.lo; g.ldb = c.ldl;
+      g.c_buf = BUF_T; g.c_off = toff; g.ldc = ldt;
+      g.M = n2; g.N = n1; g.K = n1; g.alpha = 1.0;
+      const int32_t pid = (int32_t)P.probs.size();
+      P.probs.push_back(g);
+      add_tiles(pid, n2, n1, [&](int32_t, int32_t c0, int32_t& k0, int32_t& k1) { k0 = c0; k1 = n1; });
+      P.f_top_inv += (double)n2 * n1 * n1 / 2.0;
+      toff += ldt * n1;
+    }
+    P.t_elems = std::max(P.t_elems, toff);
+    P.inv_T_ptr.push_back((int64_t)P.tasks.size());
+    for (size_t q = 0; q < by_height[h].size(); ++q) {
+      const Merge& mg = by_height[h][q];
+      const Chain& c = P.chains[mg.chain];
+      const int32_t n1 = mg.mid - mg.lo, n2 = mg.hi - mg.mid;
+      const int64_t ldt = (int64_t)nwin_of(n2) * kWin;
+      GemmProb g{};
+      g.a_buf = BUF_X; g.a_off = c.x_off + (int64_t)mg.mid * c.ldl + mg.mid; g.lda = c.ldl; g.aoff_begin = -1;
+      g.b_buf = BUF_T; g.b_off = tof[q]; g.ldb = ldt;
+      g.c_buf = BUF_X; g.c_off = c.x_off + (int64_t)mg.lo * c.ldl + mg.mid; g.ldc = c.ldl;
+      g.M = n2; g.N = n1; g.K = n2; g.alpha = -1.0;
+      const int32_t pid = (int32_t)P.probs.size();
+      P.probs.push_back(g);
+      add_tiles(pid, n2, n1, [&](int32_t r0, int32_t, int32_t& k0, int32_t& k1) {
+        k0 = 0;
+        k1 = std::min(n2, r0 + kTileM);
+      });
+      P.f_top_inv += (double)n2 * n2 * n1 / 2.0;
+    }
+    P.inv_X_ptr.push_back((int64_t)P.tasks.size());
+  }
+  for (const BaseBlock& bb : P.base_blocks) P.f_top_inv += (double)bb.size * bb.size * bb.size / 6.0;
+  // per sweep, level by level: Z[0:dp, C] = Z[0:dp, U_C] B_C (rows r need U with depth > r)
+  P.t2_ptr.assign(1, (int64_t)P.tasks.size());
+  {
+    std::vector<std::vector<int32_t>> lev(P.nchain_levels);
+    for (int32_t ci = 0; ci < nch; ++ci) lev[P.chains[ci].level].push_back(ci);
+    for (int32_t l = 1; l < P.nchain_levels; ++l) {
+      for (int32_t ci : lev[l]) {
+        const Chain& c = P.chains[ci];
+        GemmProb g{};
+        g.a_buf = BUF_STORE; g.a_off = 0; g.lda = 0; g.aoff_begin = c.u_begin; g.gather = 1;
+        g.b_buf = BUF_BT; g.b_off = c.bt_off; g.ldb = c.ldb;
+        g.c_buf = BUF_STORE; g.c_off = c.store_base; g.ldc = c.ld;
+        g.M = c.dp; g.N = c.w; g.K = c.nU; g.alpha = 1.0;
+        const int32_t pid = (int32_t)P.probs.size();
+        P.probs.push_back(g);
+        const int32_t* ud = P.u_depth.data() + c.u_begin;
+        add_tiles(pid, g.M, g.N, [&](int32_t r0, int32_t, int32_t& k0, int32_t& k1) {
+          k0 = 0;
+          k1 = (int32_t)(std::lower_bound(ud, ud + c.nU, r0, std::greater<int32_t>()) - ud);  // depth > r0
+        });
+        for (int32_t e = 0; e < c.nU; ++e) P.f_top_gemm += (double)ud[e] * c.w;
+      }
+      P.t2_ptr.push_back((int64_t)P.tasks.size());
     }
   }
 

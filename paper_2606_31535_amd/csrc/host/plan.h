@@ -16,9 +16,19 @@
 //    keeping the column values of the current root path in an LDS stack
 //    indexed by local depth; nothing else of Z is kept.
 //  * the top tree (the separators of the nested dissection and everything
-//    above the bottom subtrees): its columns are produced by dense
-//    supernode chunks, level by level, into the "top store", which bottom
-//    subtrees read as the path values above their root.
+//    above the bottom subtrees). It is cut into chains: maximal runs of top
+//    nodes a..b with parent(i) = i+1. For a chain C with diagonal block L_CC
+//    and outside ancestors U_C (every row of L_{:,C} outside C), the rows of
+//    Z above C follow from eq 11 as one product
+//        Z[rows above C, C] = Z[rows above C, U_C] * B_C,
+//        B_C = -L_{U_C, C} L_CC^{-1}      (formed once per factor, on the GPU),
+//    and the rows inside C are Z[C, C] = D_C^{-1/2} L_CC^{-1}, produced every
+//    sweep by a recursive blocked triangular inverse. Every term is >= 0
+//    (-L_ki >= 0 and L^{-1} >= 0 for a grounded Laplacian), so these blocked
+//    forms add nonnegative terms only. Chains depend only on their ancestor
+//    chains, so the top tree is a handful of levels of dense FP64 GEMMs. The
+//    columns land in the "top store" (each top column over its whole depth),
+//    which bottom subtrees read as the path values above their root.
 #pragma once
 
 #include <cstdint>
@@ -29,20 +39,47 @@
 namespace peers {
 
 constexpr int kWin = 64;              // depths per window = wavefront lanes
-constexpr int kChunk = 32;            // top chunk width (columns per task)
+constexpr int kTileM = 64;            // GEMM output tile rows
+constexpr int kTileN = 32;            // GEMM output tile columns
+constexpr int kBase = 64;             // base block of the triangular inverse
 constexpr int kBottomMaxHeight = 64;  // LDS path stack slots per window
 constexpr int kBottomMaxNodes = 2048;
 constexpr int32_t kGroundCode = INT32_MIN;
 
-struct TopChunk {
-  int32_t a, b;          // node range [a, b], a chain inside one supernode
-  int32_t depth_b;       // depth of b (depth(a + j) = depth_b + b - a - j)
-  int32_t next;          // ext = struct(b): number of ancestors referenced
-  int64_t ext_begin;     // into ext_top / ext_depth
-  int64_t coef_begin;    // into coef: next rows of kChunk doubles
-  int64_t tri_begin;     // into tri: kChunk x kChunk
-  int32_t level;         // chunk depth in the chunk tree (root chunk = 0)
-  int32_t top_a;         // top index of node a (top indices of a..b are consecutive)
+// Device buffers a GEMM operand can live in.
+enum GemmBuf : int32_t { BUF_STORE = 0, BUF_LCC = 1, BUF_X = 2, BUF_T = 3, BUF_BT = 4, BUF_LUC = 5, BUF_COUNT = 6 };
+
+// C[M x N] = alpha * A[M x K] * B[K x N]; all column-major. Column k of A
+// starts at buffer[a_buf] + (gather ? gather_table[aoff_begin + k] : a_off + k * lda).
+struct GemmProb {
+  int64_t a_off, lda, aoff_begin;
+  int64_t b_off, ldb;
+  int64_t c_off, ldc;
+  int32_t M, N, K;
+  int32_t a_buf, b_buf, c_buf;
+  int32_t gather;
+  int32_t pad_;
+  double alpha;
+};
+
+// One 64 x 32 output tile of a problem, over reduction indices [k0, k1).
+struct GemmTask {
+  int32_t prob, row0, col0, k0, k1;
+};
+
+struct Chain {
+  int32_t a, b, w, dp;     // nodes a..b; dp = depth of parent(b) (rows above the chain)
+  int32_t level, nU;       // chain-tree depth; |U_C|
+  int64_t u_begin;         // into u_off / u_depth (U_C ascending = depth descending)
+  int64_t store_base, ld;  // column a+j of the store at store_base + j*ld, ld = roundup64(dp + w)
+  int64_t lcc_off, ldl;    // dense L_CC, column-major
+  int64_t x_off;           // L_CC^{-1} workspace, same shape as L_CC
+  int64_t bt_off, ldb;     // B_C, column-major |U| x w (ldb = roundup64(nU))
+  int64_t luc_off;         // dense L_{U,C}, column-major (upload only), ld = ldb
+};
+
+struct BaseBlock {
+  int32_t chain, lo, size;
 };
 
 struct FactorPlan {
@@ -52,20 +89,26 @@ struct FactorPlan {
   int32_t ntop = 0;
   std::vector<int32_t> top_index;   // per node: top index or -1
   std::vector<int32_t> top_node;    // per top index: node
-  std::vector<int64_t> top_off;     // per top index: element offset in the store (multiple of kWin)
+  std::vector<int64_t> top_off;     // per top index: element offset of its column in the store
   std::vector<int32_t> top_depth;   // per top index
   std::vector<double> top_isd;      // per top index: D^{-1/2}
+  std::vector<int32_t> top_chain;   // per top index: chain
   int64_t store_elems = 0;
-  std::vector<TopChunk> chunks;
-  std::vector<int32_t> ext_top;     // top index of each ext entry
-  std::vector<int64_t> ext_off;     // its store offset (top_off of ext_top)
-  std::vector<int32_t> ext_depth;
-  std::vector<double> coef;         // -L_{ext[e], a+j} at [coef_begin + e*kChunk + j]
-  std::vector<double> tri;          // -L_{a+j, a+jj} at [tri_begin + j*kChunk + jj], jj < j
-  std::vector<int64_t> level_ptr;   // top tasks grouped by level
-  std::vector<int32_t> task_chunk;  // (chunk, window) tasks, sorted by level
-  std::vector<int32_t> task_win;
-  int32_t nlevels = 0;
+  std::vector<Chain> chains;
+  int32_t nchain_levels = 0;
+  std::vector<int64_t> u_off;       // gather table: store offset of each U_C column
+  std::vector<int32_t> u_depth;
+  std::vector<double> lcc;          // dense chain blocks L_CC (unit diagonal stored)
+  std::vector<double> luc;          // dense L_{U,C} (upload only)
+  int64_t x_elems = 0, t_elems = 0, bt_elems = 0;
+  std::vector<BaseBlock> base_blocks;
+  std::vector<GemmProb> probs;
+  std::vector<GemmTask> tasks;
+  std::vector<int64_t> inv_T_ptr;   // per recursion height h >= 1: tasks of T = L21 X11
+  std::vector<int64_t> inv_X_ptr;   // per height: tasks of X21 = -X22 T
+  std::vector<int64_t> t2_ptr;      // per chain level: tasks of Z[rows, C] = Z[rows, U] B_C
+  int64_t bpre_begin = 0, bpre_end = 0;  // upload: B_C = -L_{U,C} L_CC^{-1}
+  int32_t inv_heights = 0;
   // bottom subtrees
   std::vector<char> small;          // per node
   std::vector<int32_t> lslot;       // per bottom node: local depth (LDS slot)
@@ -80,8 +123,8 @@ struct FactorPlan {
   std::vector<int32_t> bdepth;      // per node depth
   std::vector<double> isd;          // per node D^{-1/2}
   int32_t max_lslot = 0;
-  // work statistics
-  double f_top = 0, f_bottom_computed = 0;
+  // work statistics (FMAs)
+  double f_top = 0, f_top_gemm = 0, f_top_inv = 0, f_bpre = 0, f_bottom_computed = 0;
 };
 
 Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P);
