@@ -74,15 +74,12 @@ void DeviceHandle::release(uint64_t bytes) {
 Status upload_query_plan(FactorHandle& F, const QueryPlan& Q, DeviceQueryPlan& D, hipStream_t s) {
   Packer pk;
   pk.add(Q.bq_ptr, &D.args.bq_ptr);
-  pk.add(Q.bq_hicode, &D.args.bq_hicode);
-  pk.add(Q.bq_slot, &D.args.bq_slot);
-  pk.add(Q.bq_out, &D.args.bq_out);
-  pk.add(Q.bq_nwin, &D.args.bq_nwin);
+  pk.add(Q.bq, &D.args.bq);
   pk.add(Q.tq_lo, &D.args.tq_lo);
   pk.add(Q.tq_hi, &D.args.tq_hi);
   pk.add(Q.tq_out, &D.args.tq_out);
   pk.add(Q.zero_out, &D.args.zero_out);
-  D.args.nbq = (int64_t)Q.bq_out.size();
+  D.args.nbq = (int64_t)Q.bq.size();
   D.args.ntq = (int64_t)Q.tq_out.size();
   D.args.nzero = (int64_t)Q.zero_out.size();
   D.nslots = Q.nslots;
@@ -267,13 +264,10 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
   pk.add(P.bwork_task, &A.bwork_task);
   pk.add(P.bwork_win, &A.bwork_win);
   pk.add(P.btask_ptr, &A.btask_ptr);
-  pk.add(P.bnodes, &A.bnodes);
-  pk.add(P.bent_ptr, &A.bent_ptr);
-  pk.add(P.bent_src, &A.bent_src);
-  pk.add(P.bent_coef, &A.bent_coef);
-  pk.add(P.bdepth, &A.depth);
+  pk.add(P.btask_nwin, &A.btask_nwin);
+  pk.add(P.bnode, &A.bnode);
+  pk.add(P.bent, &A.bent);
   pk.add(P.isd, &A.isd);
-  pk.add(P.lslot, &A.lslot);
   A.nbase = (int32_t)P.base_blocks.size();
   F->resident_bytes = pk.total + (uint64_t)std::max<int64_t>(P.bt_elems, 1) * 8;
   F->store_bytes = (uint64_t)(std::max<int64_t>(P.store_elems, 1) + std::max<int64_t>(P.x_elems, 1) +
@@ -351,8 +345,8 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
   FactorPlan& Pm = *F->plan;
   std::vector<double>().swap(Pm.lcc);
   std::vector<double>().swap(Pm.luc);
-  std::vector<double>().swap(Pm.bent_coef);
-  std::vector<int32_t>().swap(Pm.bent_src);
+  std::vector<BEnt>().swap(Pm.bent);
+  std::vector<BNode>().swap(Pm.bnode);
   *out = reinterpret_cast<peers_factor>(F.release());
   return PEERS_OK;
 }

@@ -12,8 +12,10 @@
 //    visited in descending index, a topological order of every row's
 //    traversal; the values of the current root path live in an LDS stack
 //    indexed by local depth; values above the subtree come from the top
-//    store. Each query whose lower endpoint is the current node adds
-//    sum_d (z_u[d] - z_v[d])^2 over the window (eq 12) into its own slot.
+//    store. Per-node metadata and entries come through the scalar unit. Each
+//    query whose lower endpoint is the current node adds
+//    sum_d (z_u[d] - z_v[d])^2 over the window (eq 12) into its own slot
+//    (window-major, so the final ordered sum reads coalesced).
 //  * finish kernels: ordered sum of each bottom query's window slots, the
 //    queries whose lower endpoint is a top node (both columns are in the top
 //    store), and the pairs whose resistance is exactly zero.
@@ -23,6 +25,39 @@ namespace peers {
 
 namespace {
 
+// Wave-uniform load through the scalar unit (constant address space).
+template <class T>
+__device__ __forceinline__ T load_uniform(const T* p) {
+  return *(const __attribute__((address_space(4))) T*)p;
+}
+
+__device__ __forceinline__ BNode load_uniform(const BNode* p) {
+  BNode r;
+  r.ent = load_uniform(&p->ent);
+  r.n_lds = load_uniform(&p->n_lds);
+  r.n_top = load_uniform(&p->n_top);
+  r.lslot = load_uniform(&p->lslot);
+  r.depth = load_uniform(&p->depth);
+  r.node = load_uniform(&p->node);
+  r.isd = load_uniform(&p->isd);
+  return r;
+}
+
+__device__ __forceinline__ BEnt load_uniform(const BEnt* p) {
+  BEnt r;
+  r.ref = load_uniform(&p->ref);
+  r.coef = load_uniform(&p->coef);
+  return r;
+}
+
+__device__ __forceinline__ BQuery load_uniform(const BQuery* p) {
+  BQuery r;
+  r.hiref = load_uniform(&p->hiref);
+  r.out = load_uniform(&p->out);
+  r.nwin = load_uniform(&p->nwin);
+  return r;
+}
+
 __device__ __forceinline__ double wave_sum(double s) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
@@ -30,12 +65,6 @@ __device__ __forceinline__ double wave_sum(double s) {
 }
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-// Wave-uniform load through the scalar unit (constant address space).
-template <class T>
-__device__ __forceinline__ T load_uniform(const T* p) {
-  return *(const __attribute__((address_space(4))) T*)p;
-}
 
 // Reduction loop of gemm_kernel for indices [e0, e1) in steps of 4 (one
 // v_mfma_f64_16x16x4f64 k-group). Every load is unconditional: indices past
@@ -211,47 +240,79 @@ __global__ __launch_bounds__(256) void chain_rows_kernel(SweepArgs A) {
   }
 }
 
-__global__ __launch_bounds__(64) void bottom_kernel(SweepArgs A, QueryArgs Q) {
-  __shared__ double ps[kBottomMaxHeight][kWin];
+__global__ __launch_bounds__(64 * kBottomWaves) void bottom_kernel(SweepArgs A, QueryArgs Q) {
+  // one path stack per wavefront; the waves sweep the same subtree for
+  // consecutive windows and share its metadata through the scalar cache
+  __shared__ double pstack[kBottomWaves][kBottomMaxHeight][kWin];
   const int64_t w = blockIdx.x;
-  const int32_t task = A.bwork_task[w];
-  const int32_t t = A.bwork_win[w];
-  const int lane = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int32_t task = load_uniform(A.bwork_task + w);
+  const int32_t t = load_uniform(A.bwork_win + w) + wave;
+  const int32_t p0 = load_uniform(A.btask_ptr + task), p1 = load_uniform(A.btask_ptr + task + 1);
+  if (t >= load_uniform(A.btask_nwin + task)) return;
+  double (*ps)[kWin] = pstack[wave];
+  const int lane = threadIdx.x & 63;
   const int32_t d0 = t * kWin;
   const int32_t d = d0 + lane;
-  const int32_t p0 = A.btask_ptr[task], p1 = A.btask_ptr[task + 1];
+  constexpr int64_t kRefMask = (int64_t(1) << kRefShift) - 1;
+  BNode nxt = load_uniform(A.bnode + p0);
   for (int32_t p = p0; p < p1; ++p) {
-    const int32_t i = A.bnodes[p];
-    double acc = 0.0;
-    const int64_t e1 = A.bent_ptr[i + 1];
-    for (int64_t e = A.bent_ptr[i]; e < e1; ++e) {
-      const int32_t src = A.bent_src[e];
-      const double cf = A.bent_coef[e];
-      double v;
-      if (src >= 0) {
-        v = ps[src][lane];
-      } else {
-        const int32_t k = -(src + 1);
-        v = (d0 < A.top_depth[k]) ? A.store[A.top_off[k] + d0 + lane] : 0.0;
+    const BNode nd = nxt;
+    if (p + 1 < p1) nxt = load_uniform(A.bnode + p + 1);  // next record in flight during this node
+    const int32_t q0 = load_uniform(Q.bq_ptr + p), q1 = load_uniform(Q.bq_ptr + p + 1);
+    const BEnt* __restrict__ en = A.bent + nd.ent;
+    // up to four store (ancestor above the subtree) values requested first, so
+    // their latency overlaps the path-stack entries
+    double tv[4], tc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      tv[j] = 0.0;
+      tc[j] = 0.0;
+      if (j < nd.n_top) {
+        const BEnt be = load_uniform(en + nd.n_lds + j);
+        tc[j] = be.coef;
+        if (t < (int32_t)(be.ref & kRefMask)) tv[j] = A.store[(be.ref >> kRefShift) + d0 + lane];
       }
-      acc = fma(cf, v, acc);
     }
-    if (d == A.depth[i] - 1) acc = A.isd[i];
-    ps[A.lslot[i]][lane] = acc;
-    const int32_t q1 = Q.bq_ptr[i + 1];
-    for (int32_t q = Q.bq_ptr[i]; q < q1; ++q) {
-      if (t >= Q.bq_nwin[q]) continue;
-      const int32_t hc = Q.bq_hicode[q];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int32_t e = 0;
+    for (; e + 4 <= nd.n_lds; e += 4) {
+      const BEnt b0 = load_uniform(en + e), b1 = load_uniform(en + e + 1);
+      const BEnt b2 = load_uniform(en + e + 2), b3 = load_uniform(en + e + 3);
+      const double v0 = ps[b0.ref][lane], v1 = ps[b1.ref][lane], v2 = ps[b2.ref][lane], v3 = ps[b3.ref][lane];
+      a0 = fma(b0.coef, v0, a0);
+      a1 = fma(b1.coef, v1, a1);
+      a2 = fma(b2.coef, v2, a2);
+      a3 = fma(b3.coef, v3, a3);
+    }
+    for (; e < nd.n_lds; ++e) {
+      const BEnt b0 = load_uniform(en + e);
+      a0 = fma(b0.coef, ps[b0.ref][lane], a0);
+    }
+    double at = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) at = fma(tc[j], tv[j], at);
+    for (int32_t j = 4; j < nd.n_top; ++j) {
+      const BEnt be = load_uniform(en + nd.n_lds + j);
+      const double v = t < (int32_t)(be.ref & kRefMask) ? A.store[(be.ref >> kRefShift) + d0 + lane] : 0.0;
+      at = fma(be.coef, v, at);
+    }
+    double acc = ((a0 + a1) + (a2 + a3)) + at;
+    if (d == nd.depth - 1) acc = nd.isd;
+    ps[nd.lslot][lane] = acc;
+    for (int32_t j = q0; j < q1; ++j) {
+      const BQuery bq = load_uniform(Q.bq + j);
+      if (t >= bq.nwin) continue;
       double zh = 0.0;
-      if (hc >= 0) {
-        zh = ps[hc][lane];
-      } else if (hc != kGroundCode) {
-        const int32_t k = -(hc + 1);
-        zh = (d0 < A.top_depth[k]) ? A.store[A.top_off[k] + d0 + lane] : 0.0;
+      if (bq.hiref >= 0) {
+        zh = ps[bq.hiref][lane];
+      } else if (bq.hiref != kGroundRef) {
+        const int64_t r = -bq.hiref - 1;
+        if (t < (int32_t)(r & kRefMask)) zh = A.store[(r >> kRefShift) + d0 + lane];
       }
       const double df = acc - zh;
-      const double s = wave_sum(df * df);
-      if (lane == 0) Q.part[Q.bq_slot[q] + t] = s;
+      const double sq = wave_sum(df * df);
+      if (lane == 0) Q.part[(int64_t)t * Q.nbq + j] = sq;
     }
   }
 }
@@ -259,11 +320,10 @@ __global__ __launch_bounds__(64) void bottom_kernel(SweepArgs A, QueryArgs Q) {
 __global__ __launch_bounds__(256) void reduce_bottom_kernel(QueryArgs Q) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= Q.nbq) return;
-  const int64_t s0 = Q.bq_slot[j];
-  const int32_t nw = Q.bq_nwin[j];
+  const BQuery bq = Q.bq[j];
   double s = 0.0;
-  for (int32_t t = 0; t < nw; ++t) s += Q.part[s0 + t];
-  Q.R[Q.bq_out[j]] = s;
+  for (int32_t t = 0; t < bq.nwin; ++t) s += Q.part[(int64_t)t * Q.nbq + j];
+  Q.R[bq.out] = s;
 }
 
 __global__ __launch_bounds__(256) void top_query_kernel(SweepArgs A, QueryArgs Q) {
@@ -311,7 +371,7 @@ hipError_t launch_chain_rows(const SweepArgs& a, int32_t ntop, hipStream_t s) {
 
 hipError_t launch_bottom(const SweepArgs& a, const QueryArgs& q, int64_t nwork, hipStream_t s) {
   if (nwork <= 0) return hipSuccess;
-  hipLaunchKernelGGL(bottom_kernel, dim3((unsigned)nwork), dim3(64), 0, s, a, q);
+  hipLaunchKernelGGL(bottom_kernel, dim3((unsigned)nwork), dim3(64 * kBottomWaves), 0, s, a, q);
   return hipGetLastError();
 }
 

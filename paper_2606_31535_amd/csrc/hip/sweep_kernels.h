@@ -40,21 +40,15 @@ struct SweepArgs {
   const int32_t* bwork_task;
   const int32_t* bwork_win;
   const int32_t* btask_ptr;
-  const int32_t* bnodes;
-  const int64_t* bent_ptr;
-  const int32_t* bent_src;
-  const double* bent_coef;
-  const int32_t* depth;
+  const int32_t* btask_nwin;
+  const BNode* bnode;
+  const BEnt* bent;
   const double* isd;
-  const int32_t* lslot;
 };
 
 struct QueryArgs {
   const int32_t* bq_ptr;
-  const int32_t* bq_hicode;
-  const int64_t* bq_slot;
-  const int64_t* bq_out;
-  const int32_t* bq_nwin;
+  const BQuery* bq;
   int64_t nbq;
   const int32_t* tq_lo;
   const int32_t* tq_hi;

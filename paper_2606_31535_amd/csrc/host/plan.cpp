@@ -18,7 +18,6 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
   P.height = S.height;
   P.isd.resize(N);
   for (int32_t i = 0; i < N; ++i) P.isd[i] = 1.0 / std::sqrt(F.D[i]);
-  P.bdepth.assign(S.depth.begin(), S.depth.end());
   // subtree size and height
   std::vector<int32_t> size(N, 1), hsub(N, 1);
   for (int32_t i = 0; i < N; ++i) {
@@ -271,11 +270,16 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
     P.lslot[i] = (p < 0 || !P.small[p]) ? 0 : P.lslot[p] + 1;
     P.max_lslot = std::max(P.max_lslot, P.lslot[i]);
   }
+  auto topref = [&](int32_t k) -> int64_t {
+    const int32_t t = P.top_index[k];
+    return (P.top_off[t] << kRefShift) | (int64_t)nwin_of(P.top_depth[t]);
+  };
+  if ((P.store_elems >> (62 - kRefShift)) != 0) { set_error("plan: store too large for packed references"); return E_INTERNAL; }
   P.btask_ptr.assign(1, 0);
   int32_t cur = 0, curmaxd = 0;
   auto close_task = [&]() {
     if (cur == 0) return;
-    P.btask_ptr.push_back((int32_t)P.bnodes.size());
+    P.btask_ptr.push_back((int32_t)P.bnode.size());
     P.btask_nwin.push_back(nwin_of(curmaxd));
     cur = 0;
     curmaxd = 0;
@@ -287,38 +291,38 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
     const int32_t sz = r - S.first[r] + 1;
     if (cur > 0 && cur + sz > kBottomMaxNodes) close_task();
     for (int32_t v = r; v >= S.first[r]; --v) {
-      P.bnodes.push_back(v);
+      BNode bn{};
+      bn.node = v;
+      bn.lslot = P.lslot[v];
+      bn.depth = S.depth[v];
+      bn.isd = P.isd[v];
+      bn.ent = (int64_t)P.bent.size();
+      for (int64_t q = S.colptr[v]; q < S.colptr[v + 1]; ++q) {
+        const int32_t k = S.rowidx[q];
+        if (P.small[k]) { P.bent.push_back(BEnt{P.lslot[k], -F.Lx[q]}); ++bn.n_lds; }
+      }
+      for (int64_t q = S.colptr[v]; q < S.colptr[v + 1]; ++q) {
+        const int32_t k = S.rowidx[q];
+        if (!P.small[k]) { P.bent.push_back(BEnt{topref(k), -F.Lx[q]}); ++bn.n_top; }
+      }
+      P.bnode.push_back(bn);
+      P.bnode_node.push_back(v);
       curmaxd = std::max(curmaxd, S.depth[v]);
     }
     cur += sz;
   }
   close_task();
+  // padding so fixed-width scalar reads past the last node stay in bounds
+  for (int j = 0; j < 4; ++j) P.bent.push_back(BEnt{0, 0.0});
   const int32_t nbt = (int32_t)P.btask_nwin.size();
   for (int32_t t = 0; t < nbt; ++t)
-    for (int32_t w = 0; w < P.btask_nwin[t]; ++w) {
+    for (int32_t w = 0; w < P.btask_nwin[t]; w += kBottomWaves) {
       P.bwork_task.push_back(t);
       P.bwork_win.push_back(w);
     }
-  P.bent_ptr.assign(N + 1, 0);
-  for (int32_t i = 0; i < N; ++i)
-    P.bent_ptr[i + 1] = P.bent_ptr[i] + (P.small[i] ? S.colptr[i + 1] - S.colptr[i] : 0);
-  P.bent_src.resize(P.bent_ptr[N]);
-  P.bent_coef.resize(P.bent_ptr[N]);
-  for (int32_t i = 0; i < N; ++i) {
-    if (!P.small[i]) continue;
-    int64_t q = P.bent_ptr[i];
-    for (int64_t p = S.colptr[i]; p < S.colptr[i + 1]; ++p, ++q) {
-      const int32_t k = S.rowidx[p];
-      P.bent_src[q] = P.small[k] ? P.lslot[k] : -(P.top_index[k] + 1);
-      P.bent_coef[q] = -F.Lx[p];
-    }
-  }
   for (int32_t t = 0; t < nbt; ++t) {
     int64_t nnz = 0;
-    for (int32_t k = P.btask_ptr[t]; k < P.btask_ptr[t + 1]; ++k) {
-      const int32_t v = P.bnodes[k];
-      nnz += S.colptr[v + 1] - S.colptr[v];
-    }
+    for (int32_t k = P.btask_ptr[t]; k < P.btask_ptr[t + 1]; ++k) nnz += P.bnode[k].n_lds + P.bnode[k].n_top;
     P.f_bottom_computed += (double)nnz * kWin * P.btask_nwin[t];
   }
   return OK;
@@ -329,7 +333,11 @@ Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int
   const int32_t N = P.N;
   Q = QueryPlan();
   Q.q = q;
-  Q.bq_ptr.assign(N + 1, 0);
+  // bottom position of every bottom node
+  std::vector<int32_t> pos(N, -1);
+  const int32_t nbn = (int32_t)P.bnode_node.size();
+  for (int32_t k = 0; k < nbn; ++k) pos[P.bnode_node[k]] = k;
+  Q.bq_ptr.assign(nbn + 1, 0);
   std::vector<int32_t> lo_of(q, -2), hi_of(q, -1);
   for (int64_t k = 0; k < q; ++k) {
     const int32_t x = a[k], y = b[k];
@@ -341,36 +349,33 @@ Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int
     if (hi >= 0 && first[hi] > lo) { Q.n_general++; continue; }
     lo_of[k] = lo;
     hi_of[k] = hi;
-    if (P.small[lo]) Q.bq_ptr[lo + 1]++;
+    if (P.small[lo]) Q.bq_ptr[pos[lo] + 1]++;
     else {
       Q.tq_lo.push_back(P.top_index[lo]);
       Q.tq_hi.push_back(hi < 0 ? -1 : P.top_index[hi]);
       Q.tq_out.push_back(k);
     }
   }
-  for (int32_t i = 0; i < N; ++i) Q.bq_ptr[i + 1] += Q.bq_ptr[i];
-  const int64_t nb = Q.bq_ptr[N];
-  Q.bq_hicode.resize(nb);
-  Q.bq_out.resize(nb);
-  Q.bq_slot.resize(nb);
-  Q.bq_nwin.resize(nb);
+  for (int32_t i = 0; i < nbn; ++i) Q.bq_ptr[i + 1] += Q.bq_ptr[i];
+  const int64_t nb = Q.bq_ptr[nbn];
+  Q.bq.resize(nb);
   std::vector<int32_t> fill(Q.bq_ptr.begin(), Q.bq_ptr.end() - 1);
   for (int64_t k = 0; k < q; ++k) {
     const int32_t lo = lo_of[k];
     if (lo < 0 || !P.small[lo]) continue;
     const int32_t hi = hi_of[k];
-    const int32_t j = fill[lo]++;
-    Q.bq_out[j] = k;
-    Q.bq_hicode[j] = hi < 0 ? kGroundCode : (P.small[hi] ? P.lslot[hi] : -(P.top_index[hi] + 1));
-  }
-  int64_t slot = 0;
-  for (int32_t i = 0; i < N; ++i)
-    for (int32_t j = Q.bq_ptr[i]; j < Q.bq_ptr[i + 1]; ++j) {
-      Q.bq_slot[j] = slot;
-      Q.bq_nwin[j] = nwin_of(depth[i]);
-      slot += Q.bq_nwin[j];
+    BQuery& bq = Q.bq[fill[pos[lo]]++];
+    bq.out = k;
+    bq.nwin = nwin_of(depth[lo]);
+    if (hi < 0) bq.hiref = kGroundRef;
+    else if (P.small[hi]) bq.hiref = P.lslot[hi];
+    else {
+      const int32_t t = P.top_index[hi];
+      bq.hiref = -(((P.top_off[t] << kRefShift) | (int64_t)nwin_of(P.top_depth[t])) + 1);
     }
-  Q.nslots = slot;
+    Q.max_nwin = std::max(Q.max_nwin, bq.nwin);
+  }
+  Q.nslots = (int64_t)Q.max_nwin * nb;
   return OK;
 }
 

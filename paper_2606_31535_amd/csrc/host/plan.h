@@ -42,8 +42,9 @@ constexpr int kWin = 64;              // depths per window = wavefront lanes
 constexpr int kTileM = 64;            // GEMM output tile rows
 constexpr int kTileN = 32;            // GEMM output tile columns
 constexpr int kBase = 64;             // base block of the triangular inverse
-constexpr int kBottomMaxHeight = 64;  // LDS path stack slots per window
-constexpr int kBottomMaxNodes = 2048;
+constexpr int kBottomMaxHeight = 16;  // LDS path stack slots per window
+constexpr int kBottomMaxNodes = 512;
+constexpr int kBottomWaves = 4;       // windows per bottom workgroup (one per wavefront)
 constexpr int32_t kGroundCode = INT32_MIN;
 
 // Device buffers a GEMM operand can live in.
@@ -82,6 +83,23 @@ struct BaseBlock {
   int32_t chain, lo, size;
 };
 
+// A bottom node in its task's processing order.
+struct BNode {
+  int64_t ent;          // first entry in bent: n_lds path-stack entries, then n_top store entries
+  int32_t n_lds, n_top;
+  int32_t lslot, depth;
+  int32_t node, pad_;
+  double isd;           // D^{-1/2}
+};
+
+// One entry -L_ki of a bottom column. ref = LDS slot for path-stack entries;
+// for top-store entries ref = (store offset << 12) | windows of column k.
+struct BEnt {
+  int64_t ref;
+  double coef;
+};
+constexpr int kRefShift = 12;
+
 struct FactorPlan {
   int32_t N = 0;
   int32_t height = 0;
@@ -112,15 +130,13 @@ struct FactorPlan {
   // bottom subtrees
   std::vector<char> small;          // per node
   std::vector<int32_t> lslot;       // per bottom node: local depth (LDS slot)
-  std::vector<int32_t> btask_ptr;   // per bottom task: range in bnodes
-  std::vector<int32_t> bnodes;      // processing order (descending within each subtree)
+  std::vector<int32_t> btask_ptr;   // per bottom task: range in bnode
+  std::vector<BNode> bnode;         // processing order (descending within each subtree)
+  std::vector<int32_t> bnode_node;  // node of each processing position (kept on the host)
+  std::vector<BEnt> bent;
   std::vector<int32_t> btask_nwin;  // windows per task
-  std::vector<int32_t> bwork_task;  // (task, window) work items
+  std::vector<int32_t> bwork_task;  // (task, first window) work items of kBottomWaves windows
   std::vector<int32_t> bwork_win;
-  std::vector<int64_t> bent_ptr;    // per node (N+1): entries of bottom nodes only
-  std::vector<int32_t> bent_src;    // >= 0: LDS slot; < 0: -(top index + 1)
-  std::vector<double> bent_coef;    // -L_ki
-  std::vector<int32_t> bdepth;      // per node depth
   std::vector<double> isd;          // per node D^{-1/2}
   int32_t max_lslot = 0;
   // work statistics (FMAs)
@@ -129,15 +145,23 @@ struct FactorPlan {
 
 Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P);
 
+// A query whose lower endpoint is a bottom node.
+struct BQuery {
+  int64_t hiref;   // LDS slot (>= 0), (store offset << 12 | windows) - 1 encoded negative, or ground
+  int64_t out;     // output index
+  int32_t nwin;    // windows of the lower endpoint's column
+  int32_t pad_;
+};
+constexpr int64_t kGroundRef = INT64_MIN;
+
 // Query plan for a list of pairs in reduced-permuted indices.
 struct QueryPlan {
   int64_t q = 0;
-  // bottom queries bucketed by lower endpoint
-  std::vector<int32_t> bq_ptr;     // N+1
-  std::vector<int32_t> bq_hicode;  // LDS slot, -(top+1), or kGroundCode
-  std::vector<int64_t> bq_slot;    // first partial slot
-  std::vector<int64_t> bq_out;     // output index
-  std::vector<int32_t> bq_nwin;    // windows (partials) of the query
+  // bottom queries bucketed by lower endpoint, in the order of the bottom
+  // nodes' processing positions (FactorPlan::bnode)
+  std::vector<int32_t> bq_ptr;     // #bottom positions + 1
+  std::vector<BQuery> bq;          // bucket order; partial of window t at part[t * nbq + j]
+  int32_t max_nwin = 0;
   int64_t nslots = 0;
   // top queries
   std::vector<int32_t> tq_lo, tq_hi;  // top indices (hi -1 = ground)
