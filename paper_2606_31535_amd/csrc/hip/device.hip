@@ -270,7 +270,7 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
   pk.add(P.isd, &A.isd);
   A.nbase = (int32_t)P.base_blocks.size();
   F->resident_bytes = pk.total + (uint64_t)std::max<int64_t>(P.bt_elems, 1) * 8;
-  F->store_bytes = (uint64_t)(std::max<int64_t>(P.store_elems, 1) + std::max<int64_t>(P.x_elems, 1) +
+  F->store_bytes = (uint64_t)(std::max<int64_t>(P.store_elems, kWin) + std::max<int64_t>(P.x_elems, 1) +
                               std::max<int64_t>(P.t_elems, 1)) * 8;
   const uint64_t luc_bytes = (uint64_t)std::max<int64_t>(P.bt_elems, 1) * 8;
   st = D->reserve(F->resident_bytes + F->store_bytes + luc_bytes);
@@ -278,7 +278,7 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
   F->reserved = F->resident_bytes + F->store_bytes;
   he = hipMalloc(&F->base, pk.total);
   if (he != hipSuccess) { D->release(luc_bytes); return (peers_status)hip_fail(he, "hipMalloc(factor)"); }
-  he = hipMalloc(&F->store, (size_t)std::max<int64_t>(P.store_elems, 1) * 8);
+  he = hipMalloc(&F->store, (size_t)std::max<int64_t>(P.store_elems, kWin) * 8);
   if (he == hipSuccess) he = hipMalloc(&F->xbuf, (size_t)std::max<int64_t>(P.x_elems, 1) * 8);
   if (he == hipSuccess) he = hipMalloc(&F->tbuf, (size_t)std::max<int64_t>(P.t_elems, 1) * 8);
   if (he == hipSuccess) he = hipMalloc(&F->btbuf, (size_t)std::max<int64_t>(P.bt_elems, 1) * 8);

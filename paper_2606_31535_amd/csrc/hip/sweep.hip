@@ -58,10 +58,28 @@ __device__ __forceinline__ BQuery load_uniform(const BQuery* p) {
   return r;
 }
 
-__device__ __forceinline__ double wave_sum(double s) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  return s;
+// One DPP move of a double within rows of 16 lanes (quad_perm / row mirrors).
+template <int CTRL>
+__device__ __forceinline__ double dpp(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes, in a fixed order, without LDS traffic: butterflies
+// inside each row of 16 (quad_perm [1,0,3,2], [2,3,0,1], row_half_mirror,
+// row_mirror), then the four row sums combined as (r0 + r1) + (r2 + r3).
+// The result is wave-uniform.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp<0xB1>(v);
+  v += dpp<0x4E>(v);
+  v += dpp<0x141>(v);
+  v += dpp<0x140>(v);
+  auto lane_value = [&](int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+  };
+  return (lane_value(0) + lane_value(16)) + (lane_value(32) + lane_value(48));
 }
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -252,6 +270,10 @@ __global__ __launch_bounds__(64 * kBottomWaves) void bottom_kernel(SweepArgs A, 
   if (t >= load_uniform(A.btask_nwin + task)) return;
   double (*ps)[kWin] = pstack[wave];
   const int lane = threadIdx.x & 63;
+  // path-stack entry lists are padded to multiples of 4 with zero
+  // coefficients on slot 0, so every slot must hold a finite value
+#pragma unroll
+  for (int k = 0; k < kBottomMaxHeight; ++k) ps[k][lane] = 0.0;
   const int32_t d0 = t * kWin;
   const int32_t d = d0 + lane;
   constexpr int64_t kRefMask = (int64_t(1) << kRefShift) - 1;
@@ -275,8 +297,7 @@ __global__ __launch_bounds__(64 * kBottomWaves) void bottom_kernel(SweepArgs A, 
       }
     }
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int32_t e = 0;
-    for (; e + 4 <= nd.n_lds; e += 4) {
+    for (int32_t e = 0; e < nd.n_lds; e += 4) {  // n_lds is a multiple of 4
       const BEnt b0 = load_uniform(en + e), b1 = load_uniform(en + e + 1);
       const BEnt b2 = load_uniform(en + e + 2), b3 = load_uniform(en + e + 3);
       const double v0 = ps[b0.ref][lane], v1 = ps[b1.ref][lane], v2 = ps[b2.ref][lane], v3 = ps[b3.ref][lane];
@@ -284,10 +305,6 @@ __global__ __launch_bounds__(64 * kBottomWaves) void bottom_kernel(SweepArgs A, 
       a1 = fma(b1.coef, v1, a1);
       a2 = fma(b2.coef, v2, a2);
       a3 = fma(b3.coef, v3, a3);
-    }
-    for (; e < nd.n_lds; ++e) {
-      const BEnt b0 = load_uniform(en + e);
-      a0 = fma(b0.coef, ps[b0.ref][lane], a0);
     }
     double at = 0.0;
 #pragma unroll

@@ -301,6 +301,7 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
         const int32_t k = S.rowidx[q];
         if (P.small[k]) { P.bent.push_back(BEnt{P.lslot[k], -F.Lx[q]}); ++bn.n_lds; }
       }
+      while (bn.n_lds % 4) { P.bent.push_back(BEnt{0, 0.0}); ++bn.n_lds; }  // zero terms on slot 0
       for (int64_t q = S.colptr[v]; q < S.colptr[v + 1]; ++q) {
         const int32_t k = S.rowidx[q];
         if (!P.small[k]) { P.bent.push_back(BEnt{topref(k), -F.Lx[q]}); ++bn.n_top; }

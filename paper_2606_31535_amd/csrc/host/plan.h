@@ -92,7 +92,8 @@ struct BNode {
   double isd;           // D^{-1/2}
 };
 
-// One entry -L_ki of a bottom column. ref = LDS slot for path-stack entries;
+// One entry -L_ki of a bottom column (path-stack entries are padded to a
+// multiple of 4 with zero terms on slot 0). ref = LDS slot for path-stack entries;
 // for top-store entries ref = (store offset << 12) | windows of column k.
 struct BEnt {
   int64_t ref;
