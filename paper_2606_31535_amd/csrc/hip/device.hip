@@ -299,6 +299,8 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
   // zero the triangular-inverse workspace once (its upper blocks are never written)
   // and the transfer blocks' padding; then B_C = -L_{U,C} L_CC^{-1} on the GPU
   he = hipMemsetAsync(F->xbuf, 0, (size_t)std::max<int64_t>(P.x_elems, 1) * 8, s);
+  // the store's leading zero block (windows past a column's depth read it)
+  if (he == hipSuccess) he = hipMemsetAsync(F->store, 0, (size_t)kStoreZeroBlock * 8, s);
   if (he == hipSuccess) he = hipMemsetAsync(F->btbuf, 0, (size_t)std::max<int64_t>(P.bt_elems, 1) * 8, s);
   if (he == hipSuccess && !P.luc.empty())
     he = hipMemcpyAsync(lucbuf, P.luc.data(), P.luc.size() * 8, hipMemcpyHostToDevice, s);

@@ -10,12 +10,13 @@
 //    ancestor columns gathered straight from the top store.
 //  * bottom_kernel: one wavefront per (bottom subtree task, window). Nodes are
 //    visited in descending index, a topological order of every row's
-//    traversal; the values of the current root path live in an LDS stack
+//    traversal; the values of the current root path live in a register stack
 //    indexed by local depth; values above the subtree come from the top
-//    store. Per-node metadata and entries come through the scalar unit. Each
-//    query whose lower endpoint is the current node adds
-//    sum_d (z_u[d] - z_v[d])^2 over the window (eq 12) into its own slot
-//    (window-major, so the final ordered sum reads coalesced).
+//    store, requested one node ahead. Per-node records come through the
+//    scalar unit. Each query whose lower endpoint is the current node sums
+//    (z_u[d] - z_v[d])^2 over the window (eq 12); the sums are collected one
+//    query per lane and stored 64 at a time into window-major slots, so the
+//    final ordered sum reads coalesced.
 //  * finish kernels: ordered sum of each bottom query's window slots, the
 //    queries whose lower endpoint is a top node (both columns are in the top
 //    store), and the pairs whose resistance is exactly zero.
@@ -33,13 +34,18 @@ __device__ __forceinline__ T load_uniform(const T* p) {
 
 __device__ __forceinline__ BNode load_uniform(const BNode* p) {
   BNode r;
-  r.ent = load_uniform(&p->ent);
-  r.n_lds = load_uniform(&p->n_lds);
-  r.n_top = load_uniform(&p->n_top);
-  r.lslot = load_uniform(&p->lslot);
-  r.depth = load_uniform(&p->depth);
-  r.node = load_uniform(&p->node);
   r.isd = load_uniform(&p->isd);
+#pragma unroll
+  for (int e = 0; e < 3; ++e) r.lc[e] = load_uniform(&p->lc[e]);
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    r.tref[e] = load_uniform(&p->tref[e]);
+    r.tc[e] = load_uniform(&p->tc[e]);
+  }
+  r.slots = load_uniform(&p->slots);
+  r.depth = load_uniform(&p->depth);
+  r.ent = load_uniform(&p->ent);
+  r.n_more = load_uniform(&p->n_more);
   return r;
 }
 
@@ -61,10 +67,15 @@ __device__ __forceinline__ BQuery load_uniform(const BQuery* p) {
 // One DPP move of a double within rows of 16 lanes (quad_perm / row mirrors).
 template <int CTRL>
 __device__ __forceinline__ double dpp(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, true);
   return __hiloint2double(hi, lo);
 }
+
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima). Placed right
+// after a load taken on a rare branch, so that the branch's merge point does
+// not have to drain the loads that are prefetched for the next node.
+__device__ __forceinline__ void wait_vector_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // Sum over the 64 lanes, in a fixed order, without LDS traffic: butterflies
 // inside each row of 16 (quad_perm [1,0,3,2], [2,3,0,1], row_half_mirror,
@@ -259,79 +270,104 @@ __global__ __launch_bounds__(256) void chain_rows_kernel(SweepArgs A) {
 }
 
 __global__ __launch_bounds__(64 * kBottomWaves) void bottom_kernel(SweepArgs A, QueryArgs Q) {
-  // one path stack per wavefront; the waves sweep the same subtree for
-  // consecutive windows and share its metadata through the scalar cache
-  __shared__ double pstack[kBottomWaves][kBottomMaxHeight][kWin];
+  // the waves of a workgroup sweep the same subtree for consecutive windows
+  // and share its records through the scalar cache
   const int64_t w = blockIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int32_t task = load_uniform(A.bwork_task + w);
   const int32_t t = load_uniform(A.bwork_win + w) + wave;
   const int32_t p0 = load_uniform(A.btask_ptr + task), p1 = load_uniform(A.btask_ptr + task + 1);
   if (t >= load_uniform(A.btask_nwin + task)) return;
-  double (*ps)[kWin] = pstack[wave];
   const int lane = threadIdx.x & 63;
-  // path-stack entry lists are padded to multiples of 4 with zero
-  // coefficients on slot 0, so every slot must hold a finite value
-#pragma unroll
-  for (int k = 0; k < kBottomMaxHeight; ++k) ps[k][lane] = 0.0;
   const int32_t d0 = t * kWin;
   const int32_t d = d0 + lane;
   constexpr int64_t kRefMask = (int64_t(1) << kRefShift) - 1;
-  BNode nxt = load_uniform(A.bnode + p0);
-  for (int32_t p = p0; p < p1; ++p) {
-    const BNode nd = nxt;
-    if (p + 1 < p1) nxt = load_uniform(A.bnode + p + 1);  // next record in flight during this node
+  // Value of a top column at this lane's depth. Windows past the column's
+  // depth read the store's leading zero block, so the load is unconditional.
+  const double* __restrict__ zs = A.store + lane;
+  auto top_value = [&](int64_t ref) -> double {
+    const int64_t off = t < (int32_t)(ref & kRefMask) ? (ref >> kRefShift) + d0 : 0;
+    return zs[off];
+  };
+  // values of the current root path inside the subtree, by local depth
+  // (register-resident; every slot index is wave-uniform)
+  double ps[kBottomMaxHeight];
+#pragma unroll
+  for (int k = 0; k < kBottomMaxHeight; ++k) ps[k] = 0.0;
+  // window sums of the task's queries: lane j - jb holds query j's, stored
+  // 64 at a time into the window-major partial slots
+  const int32_t jend = load_uniform(Q.bq_ptr + p1);
+  int32_t jb = load_uniform(Q.bq_ptr + p0);
+  double qbuf = 0.0;
+  auto flush = [&](int32_t count) {
+    if (lane < count) Q.part[(int64_t)t * Q.nbq + jb + lane] = qbuf;
+  };
+
+  // Software pipeline over the subtree's nodes: while node p is computed,
+  // the store values of node p+1 and the record of node p+2 are in flight.
+  BNode cur = load_uniform(A.bnode + p0);
+  BNode nxt = load_uniform(A.bnode + p0 + 1);
+  double va0 = top_value(cur.tref[0]), va1 = top_value(cur.tref[1]);
+  double vb0 = 0.0, vb1 = 0.0;
+  auto step = [&](int32_t p, const double& u0, const double& u1, double& n0, double& n1) {
+    const BNode nx2 = load_uniform(A.bnode + p + 2);
+    n0 = top_value(nxt.tref[0]);
+    n1 = top_value(nxt.tref[1]);
     const int32_t q0 = load_uniform(Q.bq_ptr + p), q1 = load_uniform(Q.bq_ptr + p + 1);
-    const BEnt* __restrict__ en = A.bent + nd.ent;
-    // up to four store (ancestor above the subtree) values requested first, so
-    // their latency overlaps the path-stack entries
-    double tv[4], tc[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      tv[j] = 0.0;
-      tc[j] = 0.0;
-      if (j < nd.n_top) {
-        const BEnt be = load_uniform(en + nd.n_lds + j);
-        tc[j] = be.coef;
-        if (t < (int32_t)(be.ref & kRefMask)) tv[j] = A.store[(be.ref >> kRefShift) + d0 + lane];
-      }
+    // eq 11: entries on the path stack, then entries in the top store
+    const int32_t sl = cur.slots;
+    double a = cur.lc[0] * ps[sl & 15];
+    a = fma(cur.lc[1], ps[(sl >> 4) & 15], a);
+    a = fma(cur.lc[2], ps[(sl >> 8) & 15], a);
+    const int32_t n_lds_more = cur.n_more & 0xffff, n_top_more = cur.n_more >> 16;
+    for (int32_t e = 0; e < n_lds_more; ++e) {
+      const BEnt be = load_uniform(A.bent + cur.ent + e);
+      a = fma(be.coef, ps[be.ref & 15], a);
     }
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    for (int32_t e = 0; e < nd.n_lds; e += 4) {  // n_lds is a multiple of 4
-      const BEnt b0 = load_uniform(en + e), b1 = load_uniform(en + e + 1);
-      const BEnt b2 = load_uniform(en + e + 2), b3 = load_uniform(en + e + 3);
-      const double v0 = ps[b0.ref][lane], v1 = ps[b1.ref][lane], v2 = ps[b2.ref][lane], v3 = ps[b3.ref][lane];
-      a0 = fma(b0.coef, v0, a0);
-      a1 = fma(b1.coef, v1, a1);
-      a2 = fma(b2.coef, v2, a2);
-      a3 = fma(b3.coef, v3, a3);
-    }
-    double at = 0.0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) at = fma(tc[j], tv[j], at);
-    for (int32_t j = 4; j < nd.n_top; ++j) {
-      const BEnt be = load_uniform(en + nd.n_lds + j);
-      const double v = t < (int32_t)(be.ref & kRefMask) ? A.store[(be.ref >> kRefShift) + d0 + lane] : 0.0;
+    double at = fma(cur.tc[1], u1, cur.tc[0] * u0);
+    for (int32_t e = 0; e < n_top_more; ++e) {
+      const BEnt be = load_uniform(A.bent + cur.ent + n_lds_more + e);
+      const double v = top_value(be.ref);
+      wait_vector_loads();
       at = fma(be.coef, v, at);
     }
-    double acc = ((a0 + a1) + (a2 + a3)) + at;
-    if (d == nd.depth - 1) acc = nd.isd;
-    ps[nd.lslot][lane] = acc;
-    for (int32_t j = q0; j < q1; ++j) {
-      const BQuery bq = load_uniform(Q.bq + j);
-      if (t >= bq.nwin) continue;
-      double zh = 0.0;
-      if (bq.hiref >= 0) {
-        zh = ps[bq.hiref][lane];
-      } else if (bq.hiref != kGroundRef) {
-        const int64_t r = -bq.hiref - 1;
-        if (t < (int32_t)(r & kRefMask)) zh = A.store[(r >> kRefShift) + d0 + lane];
+    double acc = a + at;
+    if (d == cur.depth - 1) acc = cur.isd;
+    ps[(sl >> 12) & 15] = acc;
+    // eq 12 over this window for the queries whose lower endpoint is this node
+    if (t < (cur.depth + kWin - 1) / kWin) {
+      for (int32_t j = q0; j < q1; ++j) {
+        const int64_t h = load_uniform(&Q.bq[j].hiref);
+        double zh;
+        if (h >= 0) zh = ps[h & 15];
+        else if (h == kInlineTopRef) zh = u0;
+        else if (h == kInlineTopRef - 1) zh = u1;
+        else if (h == kGroundRef) zh = 0.0;
+        else {
+          zh = top_value(-h - kStoreRefBias);
+          wait_vector_loads();
+        }
+        const double df = acc - zh;
+        const double sq = wave_sum(df * df);
+        while (j - jb >= kWin) {
+          flush(kWin);
+          jb += kWin;
+        }
+        qbuf = lane == j - jb ? sq : qbuf;
       }
-      const double df = acc - zh;
-      const double sq = wave_sum(df * df);
-      if (lane == 0) Q.part[(int64_t)t * Q.nbq + j] = sq;
     }
+    cur = nxt;
+    nxt = nx2;
+  };
+  for (int32_t p = p0; p < p1; p += 2) {
+    step(p, va0, va1, vb0, vb1);
+    if (p + 1 < p1) step(p + 1, vb0, vb1, va0, va1);
   }
+  while (jend - jb > kWin) {
+    flush(kWin);
+    jb += kWin;
+  }
+  flush(jend - jb);
 }
 
 __global__ __launch_bounds__(256) void reduce_bottom_kernel(QueryArgs Q) {

@@ -73,7 +73,7 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
   // U_C, store layout, dense blocks
   std::vector<int32_t> mark(N, -1), upos(N, -1);
   int64_t lcc_elems = 0, luc_elems = 0;
-  P.store_elems = 0;
+  P.store_elems = kStoreZeroBlock;  // leading zero block
   for (int32_t ci = 0; ci < nch; ++ci) {
     Chain& c = P.chains[ci];
     std::vector<int32_t> U;
@@ -292,20 +292,44 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
     if (cur > 0 && cur + sz > kBottomMaxNodes) close_task();
     for (int32_t v = r; v >= S.first[r]; --v) {
       BNode bn{};
-      bn.node = v;
-      bn.lslot = P.lslot[v];
-      bn.depth = S.depth[v];
       bn.isd = P.isd[v];
-      bn.ent = (int64_t)P.bent.size();
+      bn.depth = S.depth[v];
+      bn.slots = P.lslot[v] << 12;
+      int32_t tinl[2] = {-1, -1};
+      std::vector<BEnt> more_lds, more_top;
+      int32_t nl = 0, nt = 0;
       for (int64_t q = S.colptr[v]; q < S.colptr[v + 1]; ++q) {
         const int32_t k = S.rowidx[q];
-        if (P.small[k]) { P.bent.push_back(BEnt{P.lslot[k], -F.Lx[q]}); ++bn.n_lds; }
+        const double c = -F.Lx[q];
+        if (P.small[k]) {
+          if (nl < 3) {
+            bn.lc[nl] = c;
+            bn.slots |= P.lslot[k] << (4 * nl);
+          } else {
+            more_lds.push_back(BEnt{P.lslot[k], c});
+          }
+          ++nl;
+        } else {
+          if (nt < 2) {
+            bn.tref[nt] = topref(k);
+            bn.tc[nt] = c;
+            tinl[nt] = k;
+          } else {
+            more_top.push_back(BEnt{topref(k), c});
+          }
+          ++nt;
+        }
       }
-      while (bn.n_lds % 4) { P.bent.push_back(BEnt{0, 0.0}); ++bn.n_lds; }  // zero terms on slot 0
-      for (int64_t q = S.colptr[v]; q < S.colptr[v + 1]; ++q) {
-        const int32_t k = S.rowidx[q];
-        if (!P.small[k]) { P.bent.push_back(BEnt{topref(k), -F.Lx[q]}); ++bn.n_top; }
+      if (more_top.size() > 32767 || P.bent.size() + more_lds.size() + more_top.size() > (size_t)INT32_MAX) {
+        set_error("plan: bottom column too long for the node record");
+        return E_INTERNAL;
       }
+      bn.ent = (int32_t)P.bent.size();
+      bn.n_more = (int32_t)more_lds.size() | ((int32_t)more_top.size() << 16);
+      P.bent.insert(P.bent.end(), more_lds.begin(), more_lds.end());
+      P.bent.insert(P.bent.end(), more_top.begin(), more_top.end());
+      P.bnode_tinl.push_back(tinl[0]);
+      P.bnode_tinl.push_back(tinl[1]);
       P.bnode.push_back(bn);
       P.bnode_node.push_back(v);
       curmaxd = std::max(curmaxd, S.depth[v]);
@@ -313,18 +337,29 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
     cur += sz;
   }
   close_task();
-  // padding so fixed-width scalar reads past the last node stay in bounds
-  for (int j = 0; j < 4; ++j) P.bent.push_back(BEnt{0, 0.0});
+  // the sweep reads the records of the next two positions ahead of time
+  P.bnode.push_back(BNode{});
+  P.bnode.push_back(BNode{});
+  P.bent.push_back(BEnt{0, 0.0});
   const int32_t nbt = (int32_t)P.btask_nwin.size();
   for (int32_t t = 0; t < nbt; ++t)
     for (int32_t w = 0; w < P.btask_nwin[t]; w += kBottomWaves) {
       P.bwork_task.push_back(t);
       P.bwork_win.push_back(w);
     }
-  for (int32_t t = 0; t < nbt; ++t) {
-    int64_t nnz = 0;
-    for (int32_t k = P.btask_ptr[t]; k < P.btask_ptr[t + 1]; ++k) nnz += P.bnode[k].n_lds + P.bnode[k].n_top;
-    P.f_bottom_computed += (double)nnz * kWin * P.btask_nwin[t];
+  P.max_btask_nwin = 0;
+  {
+    double fb = 0;
+    for (int32_t t = 0; t < nbt; ++t) {
+      P.max_btask_nwin = std::max(P.max_btask_nwin, P.btask_nwin[t]);
+      int64_t nnz = 0;
+      for (int32_t k = P.btask_ptr[t]; k < P.btask_ptr[t + 1]; ++k) {
+        const int32_t v = P.bnode_node[k];
+        nnz += S.colptr[v + 1] - S.colptr[v];
+      }
+      fb += (double)nnz * kWin * P.btask_nwin[t];
+    }
+    P.f_bottom_computed = fb;
   }
   return OK;
 }
@@ -368,15 +403,20 @@ Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int
     BQuery& bq = Q.bq[fill[pos[lo]]++];
     bq.out = k;
     bq.nwin = nwin_of(depth[lo]);
+    const int32_t ps = pos[lo];
     if (hi < 0) bq.hiref = kGroundRef;
     else if (P.small[hi]) bq.hiref = P.lslot[hi];
+    else if (P.bnode_tinl[2 * ps] == hi) bq.hiref = kInlineTopRef;
+    else if (P.bnode_tinl[2 * ps + 1] == hi) bq.hiref = kInlineTopRef - 1;
     else {
       const int32_t t = P.top_index[hi];
-      bq.hiref = -(((P.top_off[t] << kRefShift) | (int64_t)nwin_of(P.top_depth[t])) + 1);
+      bq.hiref = -(((P.top_off[t] << kRefShift) | (int64_t)nwin_of(P.top_depth[t])) + kStoreRefBias);
     }
     Q.max_nwin = std::max(Q.max_nwin, bq.nwin);
   }
-  Q.nslots = (int64_t)Q.max_nwin * nb;
+  // a sweep window writes the slots of all its task's queries (those of
+  // windows past a query's column are never read)
+  Q.nslots = (int64_t)std::max(Q.max_nwin, P.max_btask_nwin) * nb;
   return OK;
 }
 

@@ -42,7 +42,7 @@ constexpr int kWin = 64;              // depths per window = wavefront lanes
 constexpr int kTileM = 64;            // GEMM output tile rows
 constexpr int kTileN = 32;            // GEMM output tile columns
 constexpr int kBase = 64;             // base block of the triangular inverse
-constexpr int kBottomMaxHeight = 16;  // LDS path stack slots per window
+constexpr int kBottomMaxHeight = 16;  // path-stack slots (registers) per window
 constexpr int kBottomMaxNodes = 512;
 constexpr int kBottomWaves = 4;       // windows per bottom workgroup (one per wavefront)
 constexpr int32_t kGroundCode = INT32_MIN;
@@ -83,18 +83,25 @@ struct BaseBlock {
   int32_t chain, lo, size;
 };
 
-// A bottom node in its task's processing order.
+// A bottom node in its task's processing order: one 80-byte record read by
+// the scalar unit. The first three path-stack entries and the first two
+// top-store entries of column i are inline; further ones are in bent (the
+// path-stack ones first). Absent inline entries have coefficient 0 (slot 0,
+// store reference 0).
 struct BNode {
-  int64_t ent;          // first entry in bent: n_lds path-stack entries, then n_top store entries
-  int32_t n_lds, n_top;
-  int32_t lslot, depth;
-  int32_t node, pad_;
-  double isd;           // D^{-1/2}
+  double isd;                      // D_i^{-1/2}
+  double lc[3];                    // -L_ki of the inline path-stack entries
+  int64_t tref[2];                 // inline store entries: (store offset << 12) | windows of column k
+  double tc[2];                    // their -L_ki
+  int32_t slots;                   // bits 4e..4e+3: slot of inline entry e; bits 12..15: own slot
+  int32_t depth;
+  int32_t ent;                     // first overflow entry in bent
+  int32_t n_more;                  // overflow path-stack entries (bits 0..15), then store entries (16..31)
 };
+static_assert(sizeof(BNode) == 80, "BNode is read as one 80-byte scalar record");
 
-// One entry -L_ki of a bottom column (path-stack entries are padded to a
-// multiple of 4 with zero terms on slot 0). ref = LDS slot for path-stack entries;
-// for top-store entries ref = (store offset << 12) | windows of column k.
+// An overflow entry -L_ki of a bottom column: ref = path-stack slot, or
+// (store offset << 12) | windows of column k for a top-store entry.
 struct BEnt {
   int64_t ref;
   double coef;
@@ -134,8 +141,10 @@ struct FactorPlan {
   std::vector<int32_t> btask_ptr;   // per bottom task: range in bnode
   std::vector<BNode> bnode;         // processing order (descending within each subtree)
   std::vector<int32_t> bnode_node;  // node of each processing position (kept on the host)
+  std::vector<int32_t> bnode_tinl;  // per position: the two inline top entries' nodes (-1 if absent)
   std::vector<BEnt> bent;
   std::vector<int32_t> btask_nwin;  // windows per task
+  int32_t max_btask_nwin = 0;
   std::vector<int32_t> bwork_task;  // (task, first window) work items of kBottomWaves windows
   std::vector<int32_t> bwork_win;
   std::vector<double> isd;          // per node D^{-1/2}
@@ -148,12 +157,22 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P);
 
 // A query whose lower endpoint is a bottom node.
 struct BQuery {
-  int64_t hiref;   // LDS slot (>= 0), (store offset << 12 | windows) - 1 encoded negative, or ground
+  int64_t hiref;   // see kInlineTopRef
   int64_t out;     // output index
   int32_t nwin;    // windows of the lower endpoint's column
   int32_t pad_;
 };
+// BQuery::hiref: the higher endpoint's column in the lower endpoint's sweep.
+//   >= 0            path-stack slot (the higher endpoint is in the same subtree)
+//   -1, -2          the lower endpoint's inline top-store entry 0 / 1
+//   kGroundRef      the ground (z = 0)
+//   other negative  -(store reference) - 3
 constexpr int64_t kGroundRef = INT64_MIN;
+constexpr int64_t kInlineTopRef = -1;
+constexpr int64_t kStoreRefBias = 3;
+// The first kWin elements of the top store are zero; loads of windows past a
+// column's depth are pointed there.
+constexpr int64_t kStoreZeroBlock = kWin;
 
 // Query plan for a list of pairs in reduced-permuted indices.
 struct QueryPlan {
