@@ -61,6 +61,61 @@ def cpu_baseline(g, sample: int, seed: int = 11):
     }, sel, R
 
 
+KERNEL_SOURCES = ("paper_2606_31535_amd/csrc/hip/sweep.hip", "paper_2606_31535_amd/csrc/hip/sweep_kernels.h",
+                  "paper_2606_31535_amd/csrc/host/plan.cpp", "paper_2606_31535_amd/csrc/host/plan.h")
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the sources that decide what the sweep kernels read and write."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None.
+
+    The summary (profiles/<kernel>_<workload>_traffic.txt) holds the
+    FETCH_SIZE/WRITE_SIZE readings scaled by the copy-kernel calibration and
+    the source hash they were taken at; a summary of other sources is ignored.
+    """
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(nbytes: int, reps: int = 5) -> None:
+    """Plain device-to-device copy of a known size (for scaling HBM byte counters)."""
+    import torch
+    n = nbytes // 8
+    src = torch.arange(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "reps": reps + 1,
+                      "ms_per_copy": round(dt * 1e3, 4), "GB_per_s_read_plus_write": round(2 * n * 8 / dt / 1e9, 1)}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,11 +124,17 @@ def main():
     ap.add_argument("--workload", default="C3", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-sample", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (how it would shard is in the design "
               "notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     import torch
     import paper_2606_31535_amd as P
@@ -112,14 +173,15 @@ def main():
     ph = {k: float(np.mean([p[k] for p in phases])) for k in ("top_ms", "bottom_ms", "finish_ms", "total_ms")}
     tm = phases[-1]
     if ph["top_ms"] >= ph["bottom_ms"]:
-        kname, ms, flops, nl = "top_chunk_kernel", ph["top_ms"], tm["top_flops"], tm["top_launches"]
+        kname, ms, flops, nl = "gemm_kernel", ph["top_ms"], tm["top_flops"], tm["top_launches"]
         bound = "mfma"
     else:
         kname, ms, flops, nl = "bottom_kernel", ph["bottom_ms"], tm["bottom_flops"], tm["bottom_launches"]
         bound = "alu"
     achieved = flops / (ms * 1e-3) / 1e12
     roofline = {"bound": bound, "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP64_TFLOPS, 5), "traffic": None,
+                "frac": round(achieved / PEAK_FP64_TFLOPS, 5),
+                "traffic": recorded_traffic(kname, args.workload), "source_hash": kernel_source_hash(),
                 "kernel": kname, "launches_per_step": nl, "phase_ms": round(ms, 4),
                 "algorithmic_flops": flops}
 

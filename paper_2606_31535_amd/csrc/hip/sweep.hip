@@ -105,12 +105,16 @@ __device__ __forceinline__ void gemm_accumulate(f64x4 (&C)[4][2], const double* 
                                                 const double* __restrict__ B, const int64_t* __restrict__ gt,
                                                 const GemmProb& pb, const int32_t (&rows)[4], const int32_t (&cols)[2],
                                                 int kk, int32_t e0, int32_t e1) {
-  struct Cols { int64_t g[4]; };
+  // four separate scalars (an array here would be indexed per lane and
+  // placed in scratch memory)
+  struct Cols { int64_t g0, g1, g2, g3; };
   auto gathers = [&](int32_t e) -> Cols {
-    Cols c{};
+    Cols c{0, 0, 0, 0};
     if (GATHER) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) c.g[j] = load_uniform(gt + min(e + j, e1 - 1));
+      c.g0 = load_uniform(gt + min(e, e1 - 1));
+      c.g1 = load_uniform(gt + min(e + 1, e1 - 1));
+      c.g2 = load_uniform(gt + min(e + 2, e1 - 1));
+      c.g3 = load_uniform(gt + min(e + 3, e1 - 1));
     }
     return c;
   };
@@ -118,10 +122,9 @@ __device__ __forceinline__ void gemm_accumulate(f64x4 (&C)[4][2], const double* 
     const int32_t ec = min(e + kk, e1 - 1);
     int64_t acol;
     if (GATHER) {
-      acol = gc.g[0];
-      acol = kk == 1 ? gc.g[1] : acol;
-      acol = kk == 2 ? gc.g[2] : acol;
-      acol = kk == 3 ? gc.g[3] : acol;
+      const int64_t lo = (kk & 1) ? gc.g1 : gc.g0;
+      const int64_t hi = (kk & 1) ? gc.g3 : gc.g2;
+      acol = (kk & 2) ? hi : lo;
     } else {
       acol = pb.a_off + (int64_t)ec * pb.lda;
     }
