@@ -135,8 +135,8 @@ enum {
  * (milliseconds; 0 for phases that did not run). */
 typedef struct {
   double top_ms;      /* top tree: separator chains (dense blocks) */
-  double bottom_ms;   /* bottom subtrees: path sweep with LDS path stacks */
-  double finish_ms;   /* ordered window reduction, top-node queries, zero pairs */
+  double bottom_ms;   /* bottom subtrees: path sweep with register path stacks */
+  double finish_ms;   /* ordered window reduction, top-node queries, zero pairs, non-ancestor pairs */
   double total_ms;
   int32_t top_launches;
   int32_t bottom_launches;
@@ -153,7 +153,18 @@ peers_status peers_query_all_edges(peers_factor f, double* R_out, uint32_t flags
 
 /* Resistances for q arbitrary pairs given in original ids (eq 4 and eq 12):
  * pairs with u == v give +0.0, pairs with the ground use the grounded case.
- * Errors: NODE_RANGE for an id outside [0, n). */
+ * A pair whose endpoints are ancestor-related in the elimination tree is
+ * accumulated at its lower endpoint during the sweep; any other pair is split
+ * at the lowest common ancestor c of its endpoints (rows above c are shared by
+ * both columns, rows below are not):
+ *   R = sum_{d < depth(c)} (z_u[d] - z_v[d])^2 + sum_{d >= depth(c)} (z_u[d]^2 + z_v[d]^2),
+ * with the bottom-subtree columns staged during the sweep. Only the subtrees
+ * that hold an endpoint are swept. qu, qv: q ids each (host, or device with
+ * PEERS_IN_DEVICE); R_out: q doubles (host, or device with PEERS_OUT_DEVICE),
+ * in query order. Blocks until the results are in R_out (host output) or
+ * enqueued (device output without PEERS_SYNC).
+ * Errors: NODE_RANGE for an id outside [0, n); OVER_BUDGET when the plan and
+ * workspace do not fit the device budget. */
 peers_status peers_query(peers_factor f, int64_t q, const int32_t* qu, const int32_t* qv, double* R_out,
                          uint32_t flags, void* hip_stream);
 

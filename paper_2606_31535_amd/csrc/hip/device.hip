@@ -73,6 +73,9 @@ void DeviceHandle::release(uint64_t bytes) {
 
 Status upload_query_plan(FactorHandle& F, const QueryPlan& Q, DeviceQueryPlan& D, hipStream_t s) {
   Packer pk;
+  pk.add(Q.work_task, &D.args.work_task);
+  pk.add(Q.work_win, &D.args.work_win);
+  pk.add(Q.gp, &D.args.gp);
   pk.add(Q.bq_ptr, &D.args.bq_ptr);
   pk.add(Q.bq, &D.args.bq);
   pk.add(Q.tq_lo, &D.args.tq_lo);
@@ -82,7 +85,10 @@ Status upload_query_plan(FactorHandle& F, const QueryPlan& Q, DeviceQueryPlan& D
   D.args.nbq = (int64_t)Q.bq.size();
   D.args.ntq = (int64_t)Q.tq_out.size();
   D.args.nzero = (int64_t)Q.zero_out.size();
+  D.args.nwork = (int64_t)Q.work_task.size();
+  D.args.ngp = (int64_t)Q.gp.size();
   D.nslots = Q.nslots;
+  D.stage_elems = Q.stage_elems;
   D.q = Q.q;
   D.bytes = pk.total;
   Status st = F.dev->reserve(D.bytes);
@@ -98,26 +104,31 @@ void free_query_plan(FactorHandle& F, DeviceQueryPlan& D) {
   D.bytes = 0;
 }
 
-Status ensure_workspace(FactorHandle& F, int64_t nslots, int64_t nres) {
-  const uint64_t need_part = (uint64_t)std::max<int64_t>(nslots, 1) * 8;
-  const uint64_t need_res = (uint64_t)std::max<int64_t>(nres, 1) * 8;
-  if (need_part > F.part_bytes) {
-    if (F.part) { (void)hipFree(F.part); F.dev->release(F.part_bytes); F.part = nullptr; F.part_bytes = 0; }
-    Status st = F.dev->reserve(need_part);
-    if (st != OK) return st;
-    hipError_t e = hipMalloc(&F.part, need_part);
-    if (e != hipSuccess) { F.dev->release(need_part); return hip_fail(e, "hipMalloc(partials)"); }
-    F.part_bytes = need_part;
+// Grows one workspace buffer of the factor to at least `need` bytes.
+static Status grow(FactorHandle& F, void*& buf, uint64_t& have, uint64_t need, const char* what) {
+  if (need <= have) return OK;
+  if (buf) {
+    (void)hipFree(buf);
+    F.dev->release(have);
+    buf = nullptr;
+    have = 0;
   }
-  if (need_res > F.res_bytes) {
-    if (F.res) { (void)hipFree(F.res); F.dev->release(F.res_bytes); F.res = nullptr; F.res_bytes = 0; }
-    Status st = F.dev->reserve(need_res);
-    if (st != OK) return st;
-    hipError_t e = hipMalloc(&F.res, need_res);
-    if (e != hipSuccess) { F.dev->release(need_res); return hip_fail(e, "hipMalloc(results)"); }
-    F.res_bytes = need_res;
+  Status st = F.dev->reserve(need);
+  if (st != OK) return st;
+  hipError_t e = hipMalloc(&buf, need);
+  if (e != hipSuccess) {
+    F.dev->release(need);
+    return hip_fail(e, what);
   }
+  have = need;
   return OK;
+}
+
+Status ensure_workspace(FactorHandle& F, int64_t nslots, int64_t nres, int64_t nstage) {
+  Status st = grow(F, F.part, F.part_bytes, (uint64_t)std::max<int64_t>(nslots, 1) * 8, "hipMalloc(partials)");
+  if (st == OK) st = grow(F, F.res, F.res_bytes, (uint64_t)std::max<int64_t>(nres, 1) * 8, "hipMalloc(results)");
+  if (st == OK) st = grow(F, F.stage, F.stage_bytes, (uint64_t)std::max<int64_t>(nstage, 1) * 8, "hipMalloc(staging)");
+  return st;
 }
 
 // L_CC^{-1} of every top chain into F.X: 64 x 64 diagonal inverses, then per
@@ -137,6 +148,7 @@ static Status run_chain_inverse(FactorHandle& F, hipStream_t s, int32_t& launche
 Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t s, bool profile) {
   QueryArgs q = D.args;
   q.part = (double*)F.part;
+  q.stage = (double*)F.stage;
   q.R = R_dev;
   const FactorPlan& P = *F.plan;
   if (profile && !F.ev[0])
@@ -154,8 +166,8 @@ Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t
   }
   F.top_launches = launches;
   if (profile) HIP_TRY(hipEventRecord(F.ev[1], s));
-  HIP_TRY(launch_bottom(F.sweep, q, (int64_t)P.bwork_task.size(), s));
-  F.bottom_launches = P.bwork_task.empty() ? 0 : 1;
+  HIP_TRY(launch_bottom(F.sweep, q, s));
+  F.bottom_launches = q.nwork > 0 ? 1 : 0;
   if (profile) HIP_TRY(hipEventRecord(F.ev[2], s));
   HIP_TRY(launch_finish(F.sweep, q, s));
   if (profile) HIP_TRY(hipEventRecord(F.ev[3], s));
@@ -164,7 +176,7 @@ Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t
 
 Status build_query_plan_handle(const FactorHandle& F, int64_t q, const int32_t* a, const int32_t* b,
                                QueryPlan& Q) {
-  return build_query_plan(F.first, F.depth, *F.plan, q, a, b, Q);
+  return build_query_plan(F.first, F.depth, *F.plan, q, a, b, Q, &F.anc);
 }
 
 // Reduced-permuted index of an original node id (-1 for the ground).
@@ -227,6 +239,7 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
   F->iperm = G.sym.iperm;
   F->first = G.sym.first;
   F->depth = G.sym.depth;
+  F->anc.build(G.sym.parent, G.sym.depth);
   F->plan.reset(new FactorPlan());
   Status st = build_plan(G.sym, G.num, *F->plan);
   if (st != OK) return (peers_status)st;
@@ -261,8 +274,6 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
   pk.add(P.top_off, &A.top_off);
   pk.add(P.top_depth, &A.top_depth);
   pk.add(P.top_isd, &A.top_isd);
-  pk.add(P.bwork_task, &A.bwork_task);
-  pk.add(P.bwork_win, &A.bwork_win);
   pk.add(P.btask_ptr, &A.btask_ptr);
   pk.add(P.btask_nwin, &A.btask_nwin);
   pk.add(P.bnode, &A.bnode);
@@ -323,7 +334,7 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
   D->release(luc_bytes);
   GA.buf[BUF_LUC] = nullptr;
   if (st != OK) return (peers_status)st;
-  st = ensure_workspace(*F, F->edges.nslots, F->m);
+  st = ensure_workspace(*F, F->edges.nslots, F->m, F->edges.stage_elems);
   if (st != OK) return (peers_status)st;
   he = hipStreamSynchronize(s);
   if (he != hipSuccess) return (peers_status)hip_fail(he, "hipStreamSynchronize(upload)");
@@ -368,7 +379,8 @@ void peers_factor_release(peers_factor f) {
     if (e) (void)hipEventDestroy(e);
   if (F->part) (void)hipFree(F->part);
   if (F->res) (void)hipFree(F->res);
-  F->dev->release(F->reserved + F->part_bytes + F->res_bytes);
+  if (F->stage) (void)hipFree(F->stage);
+  F->dev->release(F->reserved + F->part_bytes + F->res_bytes + F->stage_bytes);
   delete F;
 }
 
@@ -376,7 +388,7 @@ peers_status peers_factor_footprint(peers_factor f, uint64_t* resident_bytes, ui
   if (!f) { set_error("null factor"); return PEERS_E_INVALID_ARG; }
   auto* F = reinterpret_cast<FactorHandle*>(f);
   if (resident_bytes) *resident_bytes = F->resident_bytes + F->edges.bytes;
-  if (workspace_bytes) *workspace_bytes = F->store_bytes + F->part_bytes + F->res_bytes;
+  if (workspace_bytes) *workspace_bytes = F->store_bytes + F->part_bytes + F->res_bytes + F->stage_bytes;
   return PEERS_OK;
 }
 
@@ -464,14 +476,10 @@ peers_status peers_query(peers_factor f, int64_t q, const int32_t* qu, const int
   QueryPlan Q;
   Status st = build_query_plan_handle(*F, q, a.data(), b.data(), Q);
   if (st != OK) return (peers_status)st;
-  if (Q.n_general) {
-    set_error(std::to_string(Q.n_general) + " pairs are not ancestor-related in the elimination tree");
-    return PEERS_E_UNSUPPORTED;
-  }
   DeviceQueryPlan DQ;
   st = upload_query_plan(*F, Q, DQ, s);
   if (st != OK) return (peers_status)st;
-  st = ensure_workspace(*F, DQ.nslots, q);
+  st = ensure_workspace(*F, DQ.nslots, q, DQ.stage_elems);
   if (st == OK) {
     const bool dev_out = flags & PEERS_OUT_DEVICE;
     double* Rd = dev_out ? R_out : (double*)F->res;

@@ -27,6 +27,7 @@ struct DeviceQueryPlan {
   uint64_t bytes = 0;
   QueryArgs args{};
   int64_t nslots = 0;
+  int64_t stage_elems = 0;
   int64_t q = 0;
 };
 
@@ -37,6 +38,7 @@ struct FactorHandle {
   int32_t N = 0;
   std::vector<int32_t> iperm;  // reduced id -> permuted index
   std::vector<int32_t> first, depth;
+  AncestorTable anc;  // lowest common ancestors for non-ancestor pairs
   std::unique_ptr<FactorPlan> plan;
   SweepArgs sweep{};
   GemmArgs gemm{};
@@ -48,7 +50,8 @@ struct FactorHandle {
   double t_transform = 0;
   void* part = nullptr;
   void* res = nullptr;
-  uint64_t resident_bytes = 0, store_bytes = 0, part_bytes = 0, res_bytes = 0, reserved = 0;
+  void* stage = nullptr;  // staged bottom columns of non-ancestor pairs
+  uint64_t resident_bytes = 0, store_bytes = 0, part_bytes = 0, res_bytes = 0, stage_bytes = 0, reserved = 0;
   DeviceQueryPlan edges;  // all-edge queries, resident
   std::mutex mu;          // one sweep at a time per factor (shared top store)
   // per-phase timing of the last profiled sweep
@@ -61,7 +64,7 @@ struct FactorHandle {
 Status hip_fail(hipError_t e, const char* what);
 Status upload_query_plan(FactorHandle& F, const QueryPlan& Q, DeviceQueryPlan& D, hipStream_t s);
 void free_query_plan(FactorHandle& F, DeviceQueryPlan& D);
-Status ensure_workspace(FactorHandle& F, int64_t nslots, int64_t nres);
+Status ensure_workspace(FactorHandle& F, int64_t nslots, int64_t nres, int64_t nstage);
 Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t s, bool profile);
 Status build_query_plan_handle(const FactorHandle& F, int64_t q, const int32_t* a, const int32_t* b,
                                QueryPlan& Q);

@@ -277,8 +277,8 @@ __global__ __launch_bounds__(64 * kBottomWaves) void bottom_kernel(SweepArgs A, 
   // and share its records through the scalar cache
   const int64_t w = blockIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int32_t task = load_uniform(A.bwork_task + w);
-  const int32_t t = load_uniform(A.bwork_win + w) + wave;
+  const int32_t task = load_uniform(Q.work_task + w);
+  const int32_t t = load_uniform(Q.work_win + w) + wave;
   const int32_t p0 = load_uniform(A.btask_ptr + task), p1 = load_uniform(A.btask_ptr + task + 1);
   if (t >= load_uniform(A.btask_nwin + task)) return;
   const int lane = threadIdx.x & 63;
@@ -341,6 +341,11 @@ __global__ __launch_bounds__(64 * kBottomWaves) void bottom_kernel(SweepArgs A, 
     if (t < (cur.depth + kWin - 1) / kWin) {
       for (int32_t j = q0; j < q1; ++j) {
         const int64_t h = load_uniform(&Q.bq[j].hiref);
+        if (h == kStageRef) {
+          // this node's column is one side of a non-ancestor pair
+          Q.stage[load_uniform(&Q.bq[j].out) + d] = acc;
+          continue;
+        }
         double zh;
         if (h >= 0) zh = ps[h & 15];
         else if (h == kInlineTopRef) zh = u0;
@@ -377,9 +382,38 @@ __global__ __launch_bounds__(256) void reduce_bottom_kernel(QueryArgs Q) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= Q.nbq) return;
   const BQuery bq = Q.bq[j];
+  if (bq.hiref == kStageRef) return;
   double s = 0.0;
   for (int32_t t = 0; t < bq.nwin; ++t) s += Q.part[(int64_t)t * Q.nbq + j];
   Q.R[bq.out] = s;
+}
+
+// Pairs whose endpoints are not ancestor-related (eq 12 over the union of the
+// two root paths): rows above the lowest common ancestor are shared, so
+//   R = sum_{d < dl} (z_a[d] - z_b[d])^2 + sum_{d >= dl} z_a[d]^2 + sum_{d >= dl} z_b[d]^2.
+// One wavefront per pair, lanes over depths, fixed order.
+__global__ __launch_bounds__(256) void general_pair_kernel(SweepArgs A, QueryArgs Q) {
+  const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (p >= Q.ngp) return;
+  const GPair g = Q.gp[p];
+  const double* za = (g.a_stage ? Q.stage : A.store) + g.a_off;
+  const double* zb = (g.b_stage ? Q.stage : A.store) + g.b_off;
+  const int32_t dm = max(g.da, g.db);
+  double s = 0.0;
+  for (int32_t d = lane; d < dm; d += kWin) {
+    const double va = d < g.da ? za[d] : 0.0;
+    const double vb = d < g.db ? zb[d] : 0.0;
+    if (d < g.dl) {
+      const double t = va - vb;
+      s = fma(t, t, s);
+    } else {
+      s = fma(va, va, s);
+      s = fma(vb, vb, s);
+    }
+  }
+  s = wave_sum(s);
+  if (lane == 0) Q.R[g.out] = s;
 }
 
 __global__ __launch_bounds__(256) void top_query_kernel(SweepArgs A, QueryArgs Q) {
@@ -425,9 +459,9 @@ hipError_t launch_chain_rows(const SweepArgs& a, int32_t ntop, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_bottom(const SweepArgs& a, const QueryArgs& q, int64_t nwork, hipStream_t s) {
-  if (nwork <= 0) return hipSuccess;
-  hipLaunchKernelGGL(bottom_kernel, dim3((unsigned)nwork), dim3(64 * kBottomWaves), 0, s, a, q);
+hipError_t launch_bottom(const SweepArgs& a, const QueryArgs& q, hipStream_t s) {
+  if (q.nwork <= 0) return hipSuccess;
+  hipLaunchKernelGGL(bottom_kernel, dim3((unsigned)q.nwork), dim3(64 * kBottomWaves), 0, s, a, q);
   return hipGetLastError();
 }
 
@@ -438,6 +472,8 @@ hipError_t launch_finish(const SweepArgs& a, const QueryArgs& q, hipStream_t s) 
     hipLaunchKernelGGL(top_query_kernel, dim3((unsigned)((q.ntq + 3) / 4)), dim3(256), 0, s, a, q);
   if (q.nzero > 0)
     hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((q.nzero + 255) / 256)), dim3(256), 0, s, q);
+  if (q.ngp > 0)
+    hipLaunchKernelGGL(general_pair_kernel, dim3((unsigned)((q.ngp + 3) / 4)), dim3(256), 0, s, a, q);
   return hipGetLastError();
 }
 

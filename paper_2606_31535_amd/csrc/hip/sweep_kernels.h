@@ -37,8 +37,6 @@ struct SweepArgs {
   const double* top_isd;
   double* store;
   // bottom subtrees
-  const int32_t* bwork_task;
-  const int32_t* bwork_win;
   const int32_t* btask_ptr;
   const int32_t* btask_nwin;
   const BNode* bnode;
@@ -47,6 +45,10 @@ struct SweepArgs {
 };
 
 struct QueryArgs {
+  // bottom work items of this plan: (task, first window)
+  const int32_t* work_task;
+  const int32_t* work_win;
+  int64_t nwork;
   const int32_t* bq_ptr;
   const BQuery* bq;
   int64_t nbq;
@@ -56,6 +58,9 @@ struct QueryArgs {
   int64_t ntq;
   const int64_t* zero_out;
   int64_t nzero;
+  const GPair* gp;
+  int64_t ngp;
+  double* stage;  // staged bottom columns of non-ancestor pairs
   double* part;
   double* R;
 };
@@ -63,7 +68,7 @@ struct QueryArgs {
 hipError_t launch_gemm(const GemmArgs& g, int64_t task0, int64_t ntasks, hipStream_t s);
 hipError_t launch_inv_base(const SweepArgs& a, hipStream_t s);
 hipError_t launch_chain_rows(const SweepArgs& a, int32_t ntop, hipStream_t s);
-hipError_t launch_bottom(const SweepArgs& a, const QueryArgs& q, int64_t nwork, hipStream_t s);
+hipError_t launch_bottom(const SweepArgs& a, const QueryArgs& q, hipStream_t s);
 hipError_t launch_finish(const SweepArgs& a, const QueryArgs& q, hipStream_t s);
 
 }  // namespace peers

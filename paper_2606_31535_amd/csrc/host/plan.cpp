@@ -342,11 +342,9 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
   P.bnode.push_back(BNode{});
   P.bent.push_back(BEnt{0, 0.0});
   const int32_t nbt = (int32_t)P.btask_nwin.size();
+  P.bpos_task.assign(P.bnode_node.size(), 0);
   for (int32_t t = 0; t < nbt; ++t)
-    for (int32_t w = 0; w < P.btask_nwin[t]; w += kBottomWaves) {
-      P.bwork_task.push_back(t);
-      P.bwork_win.push_back(w);
-    }
+    for (int32_t k = P.btask_ptr[t]; k < P.btask_ptr[t + 1]; ++k) P.bpos_task[k] = t;
   P.max_btask_nwin = 0;
   {
     double fb = 0;
@@ -364,8 +362,42 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
   return OK;
 }
 
+void AncestorTable::build(const std::vector<int32_t>& parent, const std::vector<int32_t>& depth_in) {
+  N = (int32_t)parent.size();
+  depth = depth_in;
+  int32_t h = 1;
+  for (int32_t i = 0; i < N; ++i) h = std::max(h, depth[i]);
+  levels = 1;
+  while ((1 << levels) < h) ++levels;
+  up.assign((size_t)levels * N, -1);
+  for (int32_t i = 0; i < N; ++i) up[i] = parent[i];
+  for (int32_t l = 1; l < levels; ++l)
+    for (int32_t i = 0; i < N; ++i) {
+      const int32_t m = up[(size_t)(l - 1) * N + i];
+      up[(size_t)l * N + i] = m < 0 ? -1 : up[(size_t)(l - 1) * N + m];
+    }
+}
+
+int32_t AncestorTable::lca(int32_t a, int32_t b) const {
+  if (depth[a] < depth[b]) std::swap(a, b);
+  for (int32_t l = levels - 1; l >= 0; --l) {
+    const int32_t m = up[(size_t)l * N + a];
+    if (m >= 0 && depth[m] >= depth[b]) a = m;
+  }
+  if (a == b) return a;
+  for (int32_t l = levels - 1; l >= 0; --l) {
+    const int32_t ma = up[(size_t)l * N + a], mb = up[(size_t)l * N + b];
+    if (ma != mb) {
+      a = ma;
+      b = mb;
+    }
+  }
+  return up[a];  // -1 when a and b are roots of different trees
+}
+
 Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int32_t>& depth,
-                        const FactorPlan& P, int64_t q, const int32_t* a, const int32_t* b, QueryPlan& Q) {
+                        const FactorPlan& P, int64_t q, const int32_t* a, const int32_t* b, QueryPlan& Q,
+                        const AncestorTable* anc) {
   const int32_t N = P.N;
   Q = QueryPlan();
   Q.q = q;
@@ -375,6 +407,22 @@ Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int
   for (int32_t k = 0; k < nbn; ++k) pos[P.bnode_node[k]] = k;
   Q.bq_ptr.assign(nbn + 1, 0);
   std::vector<int32_t> lo_of(q, -2), hi_of(q, -1);
+  std::vector<char> general(q, 0);
+  std::vector<int64_t> stage_of;  // per node: staging offset of its column, -1 if not staged
+  auto column = [&](int32_t x, int64_t& off, int32_t& staged) {
+    if (!P.small[x]) {
+      off = P.top_off[P.top_index[x]];
+      staged = 0;
+      return;
+    }
+    if (stage_of[x] < 0) {
+      stage_of[x] = Q.stage_elems;
+      Q.stage_elems += (int64_t)nwin_of(depth[x]) * kWin;
+      Q.bq_ptr[pos[x] + 1]++;  // one staging entry at the node
+    }
+    off = stage_of[x];
+    staged = 1;
+  };
   for (int64_t k = 0; k < q; ++k) {
     const int32_t x = a[k], y = b[k];
     if (x == y) { Q.zero_out.push_back(k); continue; }
@@ -382,7 +430,22 @@ Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int
     if (x < 0) { lo = y; hi = -1; }
     else if (y < 0) { lo = x; hi = -1; }
     else { lo = std::min(x, y); hi = std::max(x, y); }
-    if (hi >= 0 && first[hi] > lo) { Q.n_general++; continue; }
+    if (hi >= 0 && first[hi] > lo) {
+      Q.n_general++;
+      if (!anc) continue;
+      if (stage_of.empty()) stage_of.assign(N, -1);
+      GPair g{};
+      column(lo, g.a_off, g.a_stage);
+      column(hi, g.b_off, g.b_stage);
+      g.da = depth[lo];
+      g.db = depth[hi];
+      const int32_t c = anc->lca(lo, hi);
+      g.dl = c < 0 ? 0 : depth[c];
+      g.out = k;
+      Q.gp.push_back(g);
+      general[k] = 1;
+      continue;
+    }
     lo_of[k] = lo;
     hi_of[k] = hi;
     if (P.small[lo]) Q.bq_ptr[pos[lo] + 1]++;
@@ -396,6 +459,16 @@ Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int
   const int64_t nb = Q.bq_ptr[nbn];
   Q.bq.resize(nb);
   std::vector<int32_t> fill(Q.bq_ptr.begin(), Q.bq_ptr.end() - 1);
+  // staging entries first within their node's bucket
+  if (!stage_of.empty())
+    for (int32_t x = 0; x < N; ++x) {
+      if (stage_of[x] < 0) continue;
+      BQuery& bq = Q.bq[fill[pos[x]]++];
+      bq.hiref = kStageRef;
+      bq.out = stage_of[x];
+      bq.nwin = nwin_of(depth[x]);
+      Q.max_nwin = std::max(Q.max_nwin, bq.nwin);
+    }
   for (int64_t k = 0; k < q; ++k) {
     const int32_t lo = lo_of[k];
     if (lo < 0 || !P.small[lo]) continue;
@@ -417,6 +490,15 @@ Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int
   // a sweep window writes the slots of all its task's queries (those of
   // windows past a query's column are never read)
   Q.nslots = (int64_t)std::max(Q.max_nwin, P.max_btask_nwin) * nb;
+  // work list: the tasks with at least one bucket entry, every window
+  const int32_t nbt = (int32_t)P.btask_nwin.size();
+  for (int32_t t = 0; t < nbt; ++t) {
+    if (Q.bq_ptr[P.btask_ptr[t + 1]] == Q.bq_ptr[P.btask_ptr[t]]) continue;
+    for (int32_t w = 0; w < P.btask_nwin[t]; w += kBottomWaves) {
+      Q.work_task.push_back(t);
+      Q.work_win.push_back(w);
+    }
+  }
   return OK;
 }
 

@@ -144,9 +144,8 @@ struct FactorPlan {
   std::vector<int32_t> bnode_tinl;  // per position: the two inline top entries' nodes (-1 if absent)
   std::vector<BEnt> bent;
   std::vector<int32_t> btask_nwin;  // windows per task
+  std::vector<int32_t> bpos_task;   // per processing position: its task
   int32_t max_btask_nwin = 0;
-  std::vector<int32_t> bwork_task;  // (task, first window) work items of kBottomWaves windows
-  std::vector<int32_t> bwork_win;
   std::vector<double> isd;          // per node D^{-1/2}
   int32_t max_lslot = 0;
   // work statistics (FMAs)
@@ -166,13 +165,37 @@ struct BQuery {
 //   >= 0            path-stack slot (the higher endpoint is in the same subtree)
 //   -1, -2          the lower endpoint's inline top-store entry 0 / 1
 //   kGroundRef      the ground (z = 0)
+//   kStageRef       not a pair: the sweep writes the node's column to the
+//                   staging buffer at element offset `out` (non-ancestor pairs)
 //   other negative  -(store reference) - 3
 constexpr int64_t kGroundRef = INT64_MIN;
+constexpr int64_t kStageRef = INT64_MIN + 1;
 constexpr int64_t kInlineTopRef = -1;
 constexpr int64_t kStoreRefBias = 3;
 // The first kWin elements of the top store are zero; loads of windows past a
 // column's depth are pointed there.
 constexpr int64_t kStoreZeroBlock = kWin;
+
+// A pair whose endpoints are not ancestor-related: both columns are read
+// whole after the sweep (top store, or the staging buffer for bottom nodes)
+// and split at their lowest common ancestor.
+struct GPair {
+  int64_t a_off, b_off;   // element offsets of the two columns
+  int32_t da, db;         // their depths
+  int32_t dl;             // depth of the lowest common ancestor (0: none)
+  int32_t a_stage, b_stage;  // 1: the column is in the staging buffer, 0: in the top store
+  int32_t pad_;
+  int64_t out;
+};
+
+// Lowest common ancestors in the elimination tree by binary lifting.
+struct AncestorTable {
+  int32_t N = 0, levels = 0;
+  std::vector<int32_t> up;     // up[l * N + i] = 2^l-th ancestor of i (-1 past the root)
+  std::vector<int32_t> depth;  // root = 1
+  void build(const std::vector<int32_t>& parent, const std::vector<int32_t>& depth_in);
+  int32_t lca(int32_t a, int32_t b) const;  // -1 if a and b are in different trees
+};
 
 // Query plan for a list of pairs in reduced-permuted indices.
 struct QueryPlan {
@@ -188,12 +211,21 @@ struct QueryPlan {
   std::vector<int64_t> tq_out;
   // pairs with R = 0
   std::vector<int64_t> zero_out;
-  int64_t n_general = 0;  // pairs whose endpoints are not ancestor-related
+  // pairs whose endpoints are not ancestor-related
+  std::vector<GPair> gp;
+  int64_t stage_elems = 0;
+  int64_t n_general = 0;
+  // bottom work items (task, first window): only the subtrees that hold a
+  // lower endpoint or a staged column are swept
+  std::vector<int32_t> work_task, work_win;
 };
 
 // a, b: permuted node indices (-1 = ground), per query; out = query number.
 // first/depth: subtree ranges and depths of the postordered elimination tree.
+// anc: ancestor table for non-ancestor pairs; without it such pairs are only
+// counted (n_general) and left out of the plan.
 Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int32_t>& depth,
-                        const FactorPlan& P, int64_t q, const int32_t* a, const int32_t* b, QueryPlan& Q);
+                        const FactorPlan& P, int64_t q, const int32_t* a, const int32_t* b, QueryPlan& Q,
+                        const AncestorTable* anc = nullptr);
 
 }  // namespace peers

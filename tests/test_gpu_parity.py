@@ -137,6 +137,55 @@ def test_pair_queries_ancestor_and_ground(dev):
         P.peers_graph_destroy(h)
 
 
+def test_general_pairs_vs_dense_oracle(dev):
+    # pairs of every kind: non-ancestor pairs (split at the lowest common
+    # ancestor), ancestor pairs, ground pairs and self pairs, on a mesh and on
+    # an unstructured graph (graph ordering, no coordinates)
+    for g in (synth.mesh2d(24, 20, seed=9), synth.random_connected(900, 2500, seed=21, wlog=1)):
+        rng = synth.rng_for(77)
+        k = 1500
+        qu = rng.integers(0, g.n, k).astype(np.int32)
+        qv = rng.integers(0, g.n, k).astype(np.int32)
+        qv[:20] = g.ground
+        qv[20:30] = qu[20:30]
+        h, f = _factor(dev, g)
+        try:
+            R = np.full(k, np.nan)
+            P.peers_query(f, qu, qv, R)
+            Ro = dense.resistances(g, qu, qv)
+            err = _relerr(R, Ro)
+            print(f"{g.name}: {k} random pairs, max rel err {err:.3e}")
+            assert err <= TOL
+            # a request of a few pairs sweeps only their subtrees and returns
+            # the same bits as inside the large request
+            sel = np.array([3, 50, 400, 999, 1400])
+            Rs = np.full(len(sel), np.nan)
+            P.peers_query(f, qu[sel], qv[sel], Rs)
+            assert np.array_equal(Rs.view(np.int64), R[sel].view(np.int64))
+        finally:
+            P.peers_factor_release(f)
+            P.peers_graph_destroy(h)
+
+
+def test_general_pairs_pdn_vs_sparse_oracle(dev):
+    g = synth.pdn_multilayer(side=60, layers=4, seed=7, long_frac=0.002)
+    rng = synth.rng_for(78)
+    k = 300
+    qu = rng.integers(0, g.n, k).astype(np.int32)
+    qv = rng.integers(0, g.n, k).astype(np.int32)
+    h, f = _factor(dev, g)
+    try:
+        R = np.full(k, np.nan)
+        P.peers_query(f, qu, qv, R)
+    finally:
+        P.peers_factor_release(f)
+        P.peers_graph_destroy(h)
+    Ro = sparse.SparseOracle(g).resistances(qu, qv)
+    err = _relerr(R, Ro)
+    print(f"pdn 14400: {k} random pairs, max rel err {err:.3e}")
+    assert err <= TOL
+
+
 def test_device_output_and_determinism(dev):
     import torch
     g = synth.pdn_multilayer(side=64, layers=4, seed=3)
