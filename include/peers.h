@@ -168,12 +168,40 @@ peers_status peers_query_all_edges(peers_factor f, double* R_out, uint32_t flags
 peers_status peers_query(peers_factor f, int64_t q, const int32_t* qu, const int32_t* qv, double* R_out,
                          uint32_t flags, void* hip_stream);
 
-/* Batched form: nb resident factors answered in one launch sequence; each
- * result is bit-identical to the same query run alone. qu[i]/qv[i] may be NULL
- * for all-edge queries of factor i (then q[i] is ignored). */
+/* Batched form (many graphs of uneven size): the sweeps of nb resident
+ * factors on one device run as one sequence of grouped launches, one launch
+ * per step of the sweep covering that step of every factor, captured as a HIP
+ * graph. Each result is bit-identical to the same query run alone
+ * (peers_query / peers_query_all_edges on that factor).
+ *   f[i]: distinct factors on device d; qu[i]/qv[i]: q[i] pairs of original
+ *   ids (host, or device with PEERS_IN_DEVICE), or NULL for all edges of
+ *   factor i (q[i] ignored, R_out[i] gets m_i values in edge order);
+ *   R_out[i]: host, or device with PEERS_OUT_DEVICE.
+ * The first call for a set of factors and outputs times the candidate
+ * schedules of the bottom step (subtree work items to workgroups) and keeps
+ * the fastest; all-edge batches keep their captured graph and replay it on
+ * later calls with the same factors and outputs (released factors and grown
+ * workspaces drop it). Blocks until done unless every entry is all-edge with
+ * device output and PEERS_SYNC is not set.
+ * Errors: INVALID_ARG (null, duplicate factor, factor of another device),
+ * NODE_RANGE, OVER_BUDGET. */
 peers_status peers_batch_query(peers_device d, int32_t nb, const peers_factor* f, const int64_t* q,
                                const int32_t* const* qu, const int32_t* const* qv, double* const* R_out,
                                uint32_t flags, void* hip_stream);
+
+/* What the last batch on this device ran. */
+typedef struct {
+  int32_t factors;
+  int32_t stages;            /* grouped launches in the captured graph */
+  int64_t bottom_items;      /* bottom work items (subtree task x 4 windows) */
+  int32_t schedule;          /* bottom schedule chosen by the autotuner */
+  int32_t candidates;
+  double candidate_ms[8];    /* measured bottom-step time of each candidate */
+  char schedule_name[96];
+  int32_t graph_reused;      /* 1 if the call replayed a cached graph */
+  double last_ms;            /* graph execution time of the call (0 if not synchronized) */
+} peers_batch_info;
+peers_status peers_batch_last_info(peers_device d, peers_batch_info* out);
 
 /* Served form: thread-safe asynchronous requests with continuous batching. */
 typedef struct {

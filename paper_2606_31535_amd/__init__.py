@@ -61,6 +61,18 @@ class peers_sweep_timings(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class peers_batch_info(C.Structure):
+    _fields_ = [("factors", C.c_int32), ("stages", C.c_int32), ("bottom_items", C.c_int64),
+                ("schedule", C.c_int32), ("candidates", C.c_int32), ("candidate_ms", C.c_double * 8),
+                ("schedule_name", C.c_char * 96), ("graph_reused", C.c_int32), ("last_ms", C.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["candidate_ms"] = list(self.candidate_ms)[: self.candidates]
+        d["schedule_name"] = self.schedule_name.decode()
+        return d
+
+
 class peers_server_opts(C.Structure):
     _fields_ = [("max_batch_pairs", C.c_int32), ("max_wait_us", C.c_int32),
                 ("queue_capacity", C.c_int32), ("streams", C.c_int32)]
@@ -99,6 +111,7 @@ SIGNATURES = {
     "peers_query": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, C.c_uint32, _vp]),
     "peers_batch_query": (C.c_int, [_vp, C.c_int32, C.POINTER(_vp), _i64p, C.POINTER(_vp),
                                     C.POINTER(_vp), C.POINTER(_vp), C.c_uint32, _vp]),
+    "peers_batch_last_info": (C.c_int, [_vp, C.POINTER(peers_batch_info)]),
     "peers_server_start": (C.c_int, [_vp, C.POINTER(peers_server_opts), C.POINTER(_vp)]),
     "peers_server_submit": (C.c_int, [_vp, _vp, C.c_int64, _i32p, _i32p, _f64p, C.POINTER(C.c_uint64)]),
     "peers_server_wait": (C.c_int, [_vp, C.c_uint64, C.c_int64, C.POINTER(C.c_int)]),
@@ -291,27 +304,42 @@ def peers_query(f, qu, qv, R_out, flags=0, stream=None):
 
 
 def peers_batch_query(d, factors, qus, qvs, R_outs, flags=0, stream=None):
+    """Batched sweep of several factors; qus[i] None means all edges of factor i."""
     nb = len(factors)
     fa = (_vp * nb)(*factors)
     qa = (C.c_int64 * nb)()
     ua = (_vp * nb)()
     va = (_vp * nb)()
     ra = (_vp * nb)()
+    devs = set()
     for i in range(nb):
         if qus[i] is None:
             ua[i] = None
             va[i] = None
             qa[i] = 0
         else:
-            ua[i] = _buf_ptr(qus[i])[0]
-            va[i] = _buf_ptr(qvs[i])[0]
+            pu, du = _buf_ptr(qus[i])
+            pv, dv = _buf_ptr(qvs[i])
+            if du or dv:
+                flags |= PEERS_IN_DEVICE
+            ua[i] = pu
+            va[i] = pv
             qa[i] = int(qus[i].shape[0])
         p, dev = _buf_ptr(R_outs[i])
         ra[i] = p
+        devs.add(dev)
         if dev:
             flags |= PEERS_OUT_DEVICE
+    if len(devs) > 1:
+        raise ValueError("all outputs of a batch must be host arrays or all device tensors")
     _check(lib().peers_batch_query(d, nb, fa, qa, ua, va, ra, flags, _stream_handle(stream)), "peers_batch_query")
     return R_outs
+
+
+def peers_batch_last_info(d) -> dict:
+    o = peers_batch_info()
+    _check(lib().peers_batch_last_info(d, C.byref(o)), "peers_batch_last_info")
+    return o.as_dict()
 
 
 def peers_server_start(d, max_batch_pairs=0, max_wait_us=0, queue_capacity=0, streams=0):

@@ -1,0 +1,450 @@
+// Batched form: the sweeps of many resident factors run as one sequence of
+// grouped launches (one launch per step of the sweep, covering that step of
+// every factor), captured once as a HIP graph and replayed. Each factor's
+// arithmetic is exactly that of its own sweep, so every result is
+// bit-identical to the same query run alone.
+//
+// The bottom step's schedule (the order in which subtree work items are
+// handed to workgroups, and whether workgroups are one per item or a
+// persistent grid looping over items) is picked by timing the candidates on
+// the first call of a batch and kept with the captured graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <list>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <string>
+
+#include "../../../include/peers.h"
+#include "device_handle.h"
+#include "sweep_kernels.h"
+
+namespace peers {
+
+namespace {
+
+struct Entry {
+  FactorHandle* F = nullptr;
+  DeviceQueryPlan* plan = nullptr;  // the factor's all-edge plan or `own`
+  DeviceQueryPlan own;
+  double* R_dev = nullptr;
+  double* R_host = nullptr;
+  int64_t q = 0;
+};
+
+struct Stage {
+  int kind;
+  int64_t off, n, grid;
+};
+
+constexpr int kSchedules = 4;
+const char* const kScheduleNames[kSchedules] = {"natural order, one workgroup per item",
+                                               "largest first, one workgroup per item",
+                                               "largest first, persistent 8 workgroups per CU",
+                                               "largest first, persistent 4 workgroups per CU"};
+
+}  // namespace
+
+// A built batch: argument blocks, item maps and stages in device memory, and
+// the captured graph.
+struct BatchExec {
+  std::vector<const FactorHandle*> factors;
+  std::vector<const void*> key;
+  DeviceHandle* dev = nullptr;
+  void* mem = nullptr;
+  uint64_t bytes = 0;
+  FactorArgs* fa = nullptr;
+  GroupItem* items = nullptr;
+  std::vector<Stage> stages;               // bottom stage index: bottom_stage
+  int bottom_stage = -1;
+  int64_t bottom_off[kSchedules] = {0, 0, 0, 0};
+  int64_t bottom_grid[kSchedules] = {0, 0, 0, 0};
+  int64_t bottom_n = 0;
+  int schedule = -1;
+  double cand_ms[kSchedules] = {0, 0, 0, 0};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t replays = 0;
+  ~BatchExec() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (mem) {
+      (void)hipFree(mem);
+      dev->release(bytes);
+    }
+  }
+};
+
+struct BatchCache {
+  std::list<std::unique_ptr<BatchExec>> execs;  // most recent first
+  peers_batch_info last{};
+};
+
+void batch_cache_free(DeviceHandle& D) {
+  std::lock_guard<std::mutex> g(D.batch_mu);
+  delete D.batches;
+  D.batches = nullptr;
+}
+
+void batch_cache_forget(DeviceHandle& D, const FactorHandle* F) {
+  std::lock_guard<std::mutex> g(D.batch_mu);
+  if (!D.batches) return;
+  auto& L = D.batches->execs;
+  for (auto it = L.begin(); it != L.end();) {
+    if (std::find((*it)->factors.begin(), (*it)->factors.end(), F) != (*it)->factors.end()) it = L.erase(it);
+    else ++it;
+  }
+}
+
+namespace {
+
+constexpr size_t kMaxCached = 4;
+
+Status build_exec(DeviceHandle& D, std::vector<Entry>& E, BatchExec& X) {
+  const int32_t nb = (int32_t)E.size();
+  std::vector<FactorArgs> fargs(nb);
+  for (int32_t i = 0; i < nb; ++i) {
+    FactorHandle& F = *E[i].F;
+    fargs[i].g = F.gemm;
+    fargs[i].a = F.sweep;
+    fargs[i].q = E[i].plan->args;
+    fargs[i].q.part = (double*)F.part;
+    fargs[i].q.stage = (double*)F.stage;
+    fargs[i].q.R = E[i].R_dev;
+    X.factors.push_back(&F);
+  }
+  std::vector<GroupItem> items;
+  auto stage = [&](int kind, int64_t grid_cap, auto&& per_factor) {
+    Stage st{kind, (int64_t)items.size(), 0, 0};
+    for (int32_t i = 0; i < nb; ++i) per_factor(i);
+    st.n = (int64_t)items.size() - st.off;
+    st.grid = grid_cap > 0 ? grid_cap : st.n;
+    if (st.n > 0) X.stages.push_back(st);
+  };
+  auto range = [&](int32_t i, int64_t a, int64_t b) {
+    for (int64_t t = a; t < b; ++t) items.push_back(GroupItem{i, 0, t});
+  };
+  int32_t hmax = 0, lmax = 0;
+  for (int32_t i = 0; i < nb; ++i) {
+    hmax = std::max(hmax, E[i].F->plan->inv_heights);
+    lmax = std::max(lmax, (int32_t)E[i].F->plan->t2_ptr.size() - 1);
+  }
+  // top tree: L_CC^{-1} (base blocks, then T and X per recursion height),
+  // chain-internal rows, then the chain levels
+  stage(GK_INV_BASE, 0, [&](int32_t i) { range(i, 0, (int64_t)E[i].F->plan->base_blocks.size()); });
+  for (int32_t h = 1; h <= hmax; ++h) {
+    stage(GK_GEMM, 0, [&](int32_t i) {
+      const FactorPlan& P = *E[i].F->plan;
+      if (h <= P.inv_heights) range(i, P.inv_X_ptr[h - 1], P.inv_T_ptr[h]);
+    });
+    stage(GK_GEMM, 0, [&](int32_t i) {
+      const FactorPlan& P = *E[i].F->plan;
+      if (h <= P.inv_heights) range(i, P.inv_T_ptr[h], P.inv_X_ptr[h]);
+    });
+  }
+  stage(GK_CHAIN_ROWS, 0, [&](int32_t i) { range(i, 0, E[i].F->plan->ntop); });
+  for (int32_t l = 0; l < lmax; ++l)
+    stage(GK_GEMM, 0, [&](int32_t i) {
+      const FactorPlan& P = *E[i].F->plan;
+      if (l + 1 < (int32_t)P.t2_ptr.size()) range(i, P.t2_ptr[l], P.t2_ptr[l + 1]);
+    });
+  // bottom subtrees: one item list per candidate schedule
+  {
+    std::vector<GroupItem> nat;
+    std::vector<double> cost;
+    for (int32_t i = 0; i < nb; ++i) {
+      const FactorPlan& P = *E[i].F->plan;
+      const DeviceQueryPlan& Q = *E[i].plan;
+      for (size_t w = 0; w < Q.work_task.size(); ++w) {
+        const int32_t t = Q.work_task[w];
+        const double nodes = P.btask_ptr[t + 1] - P.btask_ptr[t];
+        const double wins = std::min(kBottomWaves, P.btask_nwin[t] - Q.work_win[w]);
+        nat.push_back(GroupItem{i, 0, (int64_t)w});
+        cost.push_back(nodes * wins);
+      }
+    }
+    std::vector<int64_t> ord(nat.size());
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) { return cost[x] > cost[y]; });
+    X.bottom_n = (int64_t)nat.size();
+    for (int c = 0; c < kSchedules; ++c) {
+      X.bottom_off[c] = (int64_t)items.size();
+      if (c == 0) items.insert(items.end(), nat.begin(), nat.end());
+      else
+        for (int64_t k : ord) items.push_back(nat[k]);
+      X.bottom_grid[c] = c == 2 ? 8 * (int64_t)D.cus : c == 3 ? 4 * (int64_t)D.cus : X.bottom_n;
+    }
+    if (X.bottom_n > 0) {
+      X.bottom_stage = (int)X.stages.size();
+      X.stages.push_back(Stage{GK_BOTTOM, X.bottom_off[1], X.bottom_n, X.bottom_n});
+    }
+  }
+  // finish: ordered window sums, top-node pairs, zero pairs, non-ancestor pairs
+  auto blocks = [](int64_t n, int64_t per) { return (n + per - 1) / per; };
+  stage(GK_REDUCE, 0, [&](int32_t i) { range(i, 0, blocks(E[i].plan->args.nbq, kReduceBlock)); });
+  stage(GK_TOP_QUERY, 0, [&](int32_t i) { range(i, 0, blocks(E[i].plan->args.ntq, kTopQueryBlock)); });
+  stage(GK_ZERO, 0, [&](int32_t i) { range(i, 0, blocks(E[i].plan->args.nzero, kZeroBlock)); });
+  stage(GK_GENERAL, 0, [&](int32_t i) { range(i, 0, blocks(E[i].plan->args.ngp, kGeneralBlock)); });
+
+  const uint64_t fa_bytes = (uint64_t)nb * sizeof(FactorArgs);
+  const uint64_t it_off = (fa_bytes + 255) / 256 * 256;
+  X.bytes = it_off + std::max<uint64_t>(items.size(), 1) * sizeof(GroupItem);
+  Status st = D.reserve(X.bytes);
+  if (st != OK) { X.bytes = 0; return st; }
+  X.dev = &D;
+  hipError_t e = hipMalloc(&X.mem, X.bytes);
+  if (e != hipSuccess) { D.release(X.bytes); X.bytes = 0; X.mem = nullptr; return hip_fail(e, "hipMalloc(batch)"); }
+  X.fa = (FactorArgs*)X.mem;
+  X.items = (GroupItem*)((char*)X.mem + it_off);
+  e = hipMemcpy(X.fa, fargs.data(), fa_bytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !items.empty())
+    e = hipMemcpy(X.items, items.data(), items.size() * sizeof(GroupItem), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "batch upload");
+  return OK;
+}
+
+Status launch_stage(const BatchExec& X, const Stage& st, hipStream_t s) {
+  hipError_t e = launch_grouped(st.kind, X.fa, X.items + st.off, st.n, st.grid, s);
+  if (e != hipSuccess) return hip_fail(e, "grouped launch");
+  return OK;
+}
+
+Status launch_all(const BatchExec& X, hipStream_t s) {
+  for (const Stage& st : X.stages) {
+    Status r = launch_stage(X, st, s);
+    if (r != OK) return r;
+  }
+  return OK;
+}
+
+// Times each bottom schedule (after one pass of the top steps, which the
+// bottom step only reads) and keeps the fastest.
+Status autotune(BatchExec& X, hipStream_t s) {
+  if (X.bottom_stage < 0) {
+    X.schedule = 0;
+    return OK;
+  }
+  for (int k = 0; k < X.bottom_stage; ++k) {
+    Status r = launch_stage(X, X.stages[k], s);
+    if (r != OK) return r;
+  }
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipError_t ce = hipEventCreate(&ev[0]);
+  if (ce == hipSuccess) ce = hipEventCreate(&ev[1]);
+  if (ce != hipSuccess) {
+    if (ev[0]) (void)hipEventDestroy(ev[0]);
+    return hip_fail(ce, "hipEventCreate");
+  }
+  Status r = OK;
+  double best = 1e300;
+  for (int c = 0; c < kSchedules && r == OK; ++c) {
+    const Stage st{GK_BOTTOM, X.bottom_off[c], X.bottom_n, X.bottom_grid[c]};
+    double tmin = 1e300;
+    for (int rep = 0; rep < 2 && r == OK; ++rep) {
+      hipError_t e = hipEventRecord(ev[0], s);
+      if (e == hipSuccess) r = launch_stage(X, st, s);
+      if (r == OK && e == hipSuccess) e = hipEventRecord(ev[1], s);
+      if (r == OK && e == hipSuccess) e = hipEventSynchronize(ev[1]);
+      float ms = 0;
+      if (r == OK && e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+      if (e != hipSuccess) r = hip_fail(e, "autotune timing");
+      tmin = std::min(tmin, (double)ms);
+    }
+    X.cand_ms[c] = tmin;
+    if (tmin < best) {
+      best = tmin;
+      X.schedule = c;
+    }
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (r != OK) return r;
+  Stage& bs = X.stages[X.bottom_stage];
+  bs.off = X.bottom_off[X.schedule];
+  bs.grid = X.bottom_grid[X.schedule];
+  return OK;
+}
+
+Status capture(BatchExec& X, hipStream_t s) {
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamCreate(capture)");
+  Status r = OK;
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) r = hip_fail(e, "hipStreamBeginCapture");
+  if (r == OK) {
+    r = launch_all(X, cs);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    if (r == OK && e != hipSuccess) r = hip_fail(e, "hipStreamEndCapture");
+    X.graph = g;
+  }
+  if (r == OK) {
+    e = hipGraphInstantiate(&X.exec, X.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) r = hip_fail(e, "hipGraphInstantiate");
+  }
+  (void)hipStreamDestroy(cs);
+  (void)s;
+  return r;
+}
+
+}  // namespace
+
+}  // namespace peers
+
+using namespace peers;
+
+extern "C" {
+
+peers_status peers_batch_query(peers_device d, int32_t nb, const peers_factor* f, const int64_t* q,
+                               const int32_t* const* qu, const int32_t* const* qv, double* const* R_out,
+                               uint32_t flags, void* hip_stream) {
+  if (!d || nb < 0 || (nb > 0 && (!f || !R_out))) { set_error("null argument"); return PEERS_E_INVALID_ARG; }
+  if (nb == 0) return PEERS_OK;
+  auto* D = reinterpret_cast<DeviceHandle*>(d);
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipError_t he = hipSetDevice(D->ordinal);
+  if (he != hipSuccess) return (peers_status)hip_fail(he, "hipSetDevice");
+  std::vector<Entry> E(nb);
+  std::vector<FactorHandle*> order;
+  bool all_edges = true;
+  for (int32_t i = 0; i < nb; ++i) {
+    auto* F = reinterpret_cast<FactorHandle*>(f[i]);
+    if (!F || F->dev != D) { set_error("factor " + std::to_string(i) + " is null or on another device"); return PEERS_E_INVALID_ARG; }
+    const bool edges = !qu || !qv || !qu[i] || !qv[i];
+    if (!edges && (!q || q[i] < 0)) { set_error("negative pair count"); return PEERS_E_INVALID_ARG; }
+    E[i].F = F;
+    E[i].q = edges ? F->m : q[i];
+    if (E[i].q > 0 && !R_out[i]) { set_error("null output " + std::to_string(i)); return PEERS_E_INVALID_ARG; }
+    all_edges = all_edges && edges;
+    order.push_back(F);
+  }
+  std::sort(order.begin(), order.end());
+  if (std::adjacent_find(order.begin(), order.end()) != order.end()) {
+    set_error("a factor appears twice in one batch");
+    return PEERS_E_INVALID_ARG;
+  }
+  // one sweep at a time per factor: lock every factor, in address order
+  std::vector<std::unique_lock<std::mutex>> locks;
+  for (FactorHandle* F : order) locks.emplace_back(F->mu);
+
+  const bool dev_out = flags & PEERS_OUT_DEVICE;
+  Status st = OK;
+  for (int32_t i = 0; i < nb && st == OK; ++i) {
+    Entry& e = E[i];
+    const bool edges = !qu || !qv || !qu[i] || !qv[i];
+    if (edges) {
+      e.plan = &e.F->edges;
+    } else {
+      std::vector<int32_t> hu, hv;
+      const int32_t* u = qu[i];
+      const int32_t* v = qv[i];
+      if ((flags & PEERS_IN_DEVICE) && e.q > 0) {
+        hu.resize(e.q);
+        hv.resize(e.q);
+        he = hipMemcpy(hu.data(), qu[i], sizeof(int32_t) * e.q, hipMemcpyDeviceToHost);
+        if (he == hipSuccess) he = hipMemcpy(hv.data(), qv[i], sizeof(int32_t) * e.q, hipMemcpyDeviceToHost);
+        if (he != hipSuccess) { st = hip_fail(he, "copy query pairs"); break; }
+        u = hu.data();
+        v = hv.data();
+      }
+      st = plan_for_pairs(*e.F, e.q, u, v, e.own, s);
+      if (st != OK) break;
+      e.plan = &e.own;
+    }
+    st = ensure_workspace(*e.F, e.plan->nslots, e.q, e.plan->stage_elems);
+    e.R_dev = dev_out ? R_out[i] : (double*)e.F->res;
+    e.R_host = dev_out ? nullptr : R_out[i];
+  }
+  if (st == OK) {
+    he = hipStreamSynchronize(s);  // plan uploads complete before the graph reads them
+    if (he != hipSuccess) st = hip_fail(he, "hipStreamSynchronize(plans)");
+  }
+
+  std::lock_guard<std::mutex> bg(D->batch_mu);
+  if (!D->batches) D->batches = new BatchCache();
+  BatchCache& C = *D->batches;
+  BatchExec* X = nullptr;
+  std::unique_ptr<BatchExec> owned;
+  std::vector<const void*> key;
+  for (auto& e : E) {
+    key.push_back(e.F);
+    key.push_back(e.R_dev);
+  }
+  bool reused = false;
+  if (st == OK && all_edges) {
+    for (auto it = C.execs.begin(); it != C.execs.end(); ++it)
+      if ((*it)->key == key) {
+        C.execs.splice(C.execs.begin(), C.execs, it);
+        X = C.execs.front().get();
+        reused = true;
+        break;
+      }
+  }
+  if (st == OK && !X) {
+    owned.reset(new BatchExec());
+    owned->key = key;
+    st = build_exec(*D, E, *owned);
+    if (st == OK) st = autotune(*owned, s);
+    if (st == OK) st = capture(*owned, s);
+    if (st == OK) X = owned.get();
+  }
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  float total_ms = 0;
+  if (st == OK) {
+    (void)hipEventCreate(&ev[0]);
+    (void)hipEventCreate(&ev[1]);
+    (void)hipEventRecord(ev[0], s);
+    he = hipGraphLaunch(X->exec, s);
+    if (he != hipSuccess) st = hip_fail(he, "hipGraphLaunch");
+    (void)hipEventRecord(ev[1], s);
+    ++X->replays;
+  }
+  for (int32_t i = 0; i < nb && st == OK; ++i)
+    if (E[i].R_host && E[i].q > 0) {
+      he = hipMemcpyAsync(E[i].R_host, E[i].R_dev, sizeof(double) * E[i].q, hipMemcpyDeviceToHost, s);
+      if (he != hipSuccess) st = hip_fail(he, "hipMemcpyAsync(results)");
+    }
+  const bool must_sync = !dev_out || (flags & PEERS_SYNC) || !all_edges;
+  if (must_sync) {
+    he = hipStreamSynchronize(s);
+    if (st == OK && he != hipSuccess) st = hip_fail(he, "hipStreamSynchronize");
+  }
+  if (st == OK) {
+    peers_batch_info& I = C.last;
+    I = peers_batch_info{};
+    I.factors = nb;
+    I.stages = (int32_t)X->stages.size();
+    I.bottom_items = X->bottom_n;
+    I.schedule = X->schedule;
+    I.candidates = kSchedules;
+    for (int c = 0; c < kSchedules; ++c) I.candidate_ms[c] = X->cand_ms[c];
+    std::snprintf(I.schedule_name, sizeof(I.schedule_name), "%s", kScheduleNames[std::max(0, X->schedule)]);
+    I.graph_reused = reused ? 1 : 0;
+    if (must_sync && hipEventElapsedTime(&total_ms, ev[0], ev[1]) == hipSuccess) I.last_ms = total_ms;
+  }
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (owned && st == OK && all_edges) {
+    C.execs.push_front(std::move(owned));
+    while (C.execs.size() > kMaxCached) C.execs.pop_back();
+  }
+  if (st != OK) (void)hipStreamSynchronize(s);
+  owned.reset();  // per-call graphs (their plans die with this call)
+  for (auto& e : E) free_query_plan(*e.F, e.own);
+  return (peers_status)st;
+}
+
+peers_status peers_batch_last_info(peers_device d, peers_batch_info* out) {
+  if (!d || !out) { set_error("null argument"); return PEERS_E_INVALID_ARG; }
+  auto* D = reinterpret_cast<DeviceHandle*>(d);
+  std::lock_guard<std::mutex> g(D->batch_mu);
+  *out = D->batches ? D->batches->last : peers_batch_info{};
+  return PEERS_OK;
+}
+
+}  // extern "C"

@@ -89,6 +89,8 @@ Status upload_query_plan(FactorHandle& F, const QueryPlan& Q, DeviceQueryPlan& D
   D.args.ngp = (int64_t)Q.gp.size();
   D.nslots = Q.nslots;
   D.stage_elems = Q.stage_elems;
+  D.work_task = Q.work_task;
+  D.work_win = Q.work_win;
   D.q = Q.q;
   D.bytes = pk.total;
   Status st = F.dev->reserve(D.bytes);
@@ -107,6 +109,8 @@ void free_query_plan(FactorHandle& F, DeviceQueryPlan& D) {
 // Grows one workspace buffer of the factor to at least `need` bytes.
 static Status grow(FactorHandle& F, void*& buf, uint64_t& have, uint64_t need, const char* what) {
   if (need <= have) return OK;
+  // captured batches hold this factor's workspace addresses
+  batch_cache_forget(*F.dev, &F);
   if (buf) {
     (void)hipFree(buf);
     F.dev->release(have);
@@ -179,10 +183,22 @@ Status build_query_plan_handle(const FactorHandle& F, int64_t q, const int32_t* 
   return build_query_plan(F.first, F.depth, *F.plan, q, a, b, Q, &F.anc);
 }
 
-// Reduced-permuted index of an original node id (-1 for the ground).
-inline int32_t perm_index(const FactorHandle& F, int32_t x) {
-  if (x == F.ground) return -1;
-  return F.iperm[x < F.ground ? x : x - 1];
+Status plan_for_pairs(FactorHandle& F, int64_t q, const int32_t* u, const int32_t* v, DeviceQueryPlan& DQ,
+                      hipStream_t s) {
+  std::vector<int32_t> a(q), b(q);
+  for (int64_t k = 0; k < q; ++k) {
+    if (u[k] < 0 || u[k] >= F.n || v[k] < 0 || v[k] >= F.n) {
+      set_error("query " + std::to_string(k) + " has a node id outside [0, n)");
+      return E_NODE_RANGE;
+    }
+    a[k] = perm_index(F, u[k]);
+    b[k] = perm_index(F, v[k]);
+    if (u[k] == v[k]) a[k] = b[k];
+  }
+  QueryPlan Q;
+  Status st = build_query_plan_handle(F, q, a.data(), b.data(), Q);
+  if (st != OK) return st;
+  return upload_query_plan(F, Q, DQ, s);
 }
 
 }  // namespace peers
@@ -205,13 +221,20 @@ peers_status peers_device_open(int32_t ordinal, uint64_t hbm_budget_bytes, peers
   if (e != hipSuccess) return (peers_status)hip_fail(e, "hipMemGetInfo");
   auto* D = new DeviceHandle();
   D->ordinal = ordinal;
+  if (hipDeviceGetAttribute(&D->cus, hipDeviceAttributeMultiprocessorCount, ordinal) != hipSuccess || D->cus <= 0)
+    D->cus = 256;
   D->total = total;
   D->budget = hbm_budget_bytes ? std::min<uint64_t>(hbm_budget_bytes, total) : (uint64_t)(0.9 * (double)total);
   *out = reinterpret_cast<peers_device>(D);
   return PEERS_OK;
 }
 
-void peers_device_close(peers_device d) { delete reinterpret_cast<DeviceHandle*>(d); }
+void peers_device_close(peers_device d) {
+  if (!d) return;
+  auto* D = reinterpret_cast<DeviceHandle*>(d);
+  batch_cache_free(*D);
+  delete D;
+}
 
 peers_status peers_device_usage(peers_device d, uint64_t* used, uint64_t* budget) {
   if (!d) { set_error("null device"); return PEERS_E_INVALID_ARG; }
@@ -369,6 +392,7 @@ void peers_factor_release(peers_factor f) {
   auto* F = reinterpret_cast<FactorHandle*>(f);
   (void)hipSetDevice(F->dev->ordinal);
   (void)hipDeviceSynchronize();
+  batch_cache_forget(*F->dev, F);
   free_query_plan(*F, F->edges);
   if (F->base) (void)hipFree(F->base);
   if (F->store) (void)hipFree(F->store);
@@ -463,21 +487,8 @@ peers_status peers_query(peers_factor f, int64_t q, const int32_t* qu, const int
     u = hu.data();
     v = hv.data();
   }
-  std::vector<int32_t> a(q), b(q);
-  for (int64_t k = 0; k < q; ++k) {
-    if (u[k] < 0 || u[k] >= F->n || v[k] < 0 || v[k] >= F->n) {
-      set_error("query " + std::to_string(k) + " has a node id outside [0, n)");
-      return PEERS_E_NODE_RANGE;
-    }
-    a[k] = perm_index(*F, u[k]);
-    b[k] = perm_index(*F, v[k]);
-    if (u[k] == v[k]) a[k] = b[k];
-  }
-  QueryPlan Q;
-  Status st = build_query_plan_handle(*F, q, a.data(), b.data(), Q);
-  if (st != OK) return (peers_status)st;
   DeviceQueryPlan DQ;
-  st = upload_query_plan(*F, Q, DQ, s);
+  Status st = plan_for_pairs(*F, q, u, v, DQ, s);
   if (st != OK) return (peers_status)st;
   st = ensure_workspace(*F, DQ.nslots, q, DQ.stage_elems);
   if (st == OK) {

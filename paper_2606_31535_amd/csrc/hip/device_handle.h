@@ -12,15 +12,24 @@
 
 namespace peers {
 
+struct BatchCache;   // captured batch launches (batch.hip)
+struct FactorHandle;
+
 struct DeviceHandle {
   int32_t ordinal = 0;
+  int32_t cus = 0;
   uint64_t total = 0;
   uint64_t budget = 0;
   uint64_t used = 0;
   std::mutex mu;
   Status reserve(uint64_t bytes);
   void release(uint64_t bytes);
+  BatchCache* batches = nullptr;  // guarded by batch_mu
+  std::mutex batch_mu;
 };
+
+void batch_cache_free(DeviceHandle& D);
+void batch_cache_forget(DeviceHandle& D, const FactorHandle* F);
 
 struct DeviceQueryPlan {
   void* base = nullptr;
@@ -29,6 +38,7 @@ struct DeviceQueryPlan {
   int64_t nslots = 0;
   int64_t stage_elems = 0;
   int64_t q = 0;
+  std::vector<int32_t> work_task, work_win;  // host copies (batch schedules)
 };
 
 struct FactorHandle {
@@ -68,5 +78,14 @@ Status ensure_workspace(FactorHandle& F, int64_t nslots, int64_t nres, int64_t n
 Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t s, bool profile);
 Status build_query_plan_handle(const FactorHandle& F, int64_t q, const int32_t* a, const int32_t* b,
                                QueryPlan& Q);
+// Validates q pairs of original ids, builds their plan and uploads it.
+Status plan_for_pairs(FactorHandle& F, int64_t q, const int32_t* u, const int32_t* v, DeviceQueryPlan& D,
+                      hipStream_t s);
+
+// Reduced-permuted index of an original node id (-1 for the ground).
+inline int32_t perm_index(const FactorHandle& F, int32_t x) {
+  if (x == F.ground) return -1;
+  return F.iperm[x < F.ground ? x : x - 1];
+}
 
 }  // namespace peers

@@ -5,11 +5,6 @@
 using namespace peers;
 
 extern "C" {
-peers_status peers_batch_query(peers_device, int32_t, const peers_factor*, const int64_t*, const int32_t* const*,
-                               const int32_t* const*, double* const*, uint32_t, void*) {
-  set_error("not built yet");
-  return PEERS_E_UNSUPPORTED;
-}
 peers_status peers_server_start(peers_device, const peers_server_opts*, peers_server*) { return PEERS_E_UNSUPPORTED; }
 peers_status peers_server_submit(peers_server, peers_factor, int64_t, const int32_t*, const int32_t*, double*,
                                  uint64_t*) { return PEERS_E_UNSUPPORTED; }

@@ -162,15 +162,20 @@ __device__ __forceinline__ void gemm_accumulate(f64x4 (&C)[4][2], const double* 
 // r = (row 4r + l/16, col l%16). The four waves take consecutive quarters of
 // the reduction range (multiples of 4) and are summed in LDS in wave order,
 // so the result does not depend on scheduling.
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs G, int64_t task0) {
-  __shared__ double red[3][8][4][kWin];
-  const GemmTask tk = G.tasks[task0 + blockIdx.x];
-  const GemmProb pb = G.probs[tk.prob];
+typedef double GemmRed[3][8][4][kWin];
+
+// Gp points at the argument block in kernel-argument or global memory; its
+// buffer table is read with uniform loads at the problem's (uniform) index.
+__device__ __forceinline__ void gemm_body(const GemmArgs* Gp, int64_t task, GemmRed& red) {
+  const GemmTask* tasks = load_uniform(&Gp->tasks);
+  const GemmProb* probs = load_uniform(&Gp->probs);
+  const GemmTask tk = tasks[task];
+  const GemmProb pb = probs[tk.prob];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int kk = lane >> 4, ii = lane & 15;
-  const double* __restrict__ A = G.buf[pb.a_buf];
-  const double* __restrict__ B = G.buf[pb.b_buf] + pb.b_off;
+  const double* __restrict__ A = load_uniform(&Gp->buf[pb.a_buf]);
+  const double* __restrict__ B = load_uniform(&Gp->buf[pb.b_buf]) + pb.b_off;
   const int32_t nk = tk.k1 - tk.k0;
   const int32_t per = ((nk + 15) >> 4) << 2;
   const int32_t e0 = tk.k0 + min(nk, wave * per);
@@ -180,7 +185,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs G, int64_t task0) {
   for (int rb = 0; rb < 4; ++rb) rows[rb] = min(tk.row0 + 16 * rb + ii, pb.M - 1);
 #pragma unroll
   for (int cb = 0; cb < 2; ++cb) cols[cb] = min(tk.col0 + 16 * cb + ii, pb.N - 1);
-  const int64_t* __restrict__ gt = G.gather + (pb.gather ? pb.aoff_begin : 0);
+  const int64_t* __restrict__ gt = load_uniform(&Gp->gather) + (pb.gather ? pb.aoff_begin : 0);
   // operands of the 4 reduction indices starting at e. Every load is
   // unconditional: indices past e1 are clamped to a valid column and their B
   // value is zeroed at use, so the loop body has no branches and each load is
@@ -225,7 +230,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs G, int64_t task0) {
         for (int r = 0; r < 4; ++r) tile[(16 * rb + 4 * r + kk) * LD + 16 * cb + ii] = C[rb][cb][r];
   }
   __syncthreads();
-  double* __restrict__ Cm = G.buf[pb.c_buf] + pb.c_off;
+  double* __restrict__ Cm = load_uniform(&Gp->buf[pb.c_buf]) + pb.c_off;
   for (int idx = threadIdx.x; idx < kTileM * kTileN; idx += 256) {
     const int r = idx & (kTileM - 1), c = idx / kTileM;
     const int32_t gr = tk.row0 + r, gc = tk.col0 + c;
@@ -233,12 +238,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs G, int64_t task0) {
   }
 }
 
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs G, int64_t task0) {
+  __shared__ GemmRed red;
+  gemm_body(&G, task0 + blockIdx.x, red);
+}
+
 // Inverse of one diagonal block (at most 64 x 64) of a chain's unit-lower
 // L_CC by forward substitution: lane j holds column j of the inverse.
-__global__ __launch_bounds__(64) void inv_base_kernel(SweepArgs A) {
-  __shared__ double Ls[kBase][kBase + 1];
-  __shared__ double Xs[kBase][kBase + 1];
-  const BaseBlock bb = A.base_blocks[blockIdx.x];
+typedef double BaseTile[kBase][kBase + 1];
+
+__device__ __forceinline__ void inv_base_body(const SweepArgs& A, int64_t blk, BaseTile& Ls, BaseTile& Xs) {
+  const BaseBlock bb = A.base_blocks[blk];
   const Chain c = A.chains[bb.chain];
   const int lane = threadIdx.x;
   const int n = bb.size, lo = bb.lo;
@@ -256,10 +266,14 @@ __global__ __launch_bounds__(64) void inv_base_kernel(SweepArgs A) {
     if (lane < n) Xb[(int64_t)j * c.ldl + lane] = Xs[lane][j];
 }
 
+__global__ __launch_bounds__(64) void inv_base_kernel(SweepArgs A) {
+  __shared__ BaseTile Ls, Xs;
+  inv_base_body(A, blockIdx.x, Ls, Xs);
+}
+
 // Rows of a top column that lie inside its own chain (Z[C, C] = D^{-1/2} L_CC^{-1})
 // and the zero padding below the column's depth. One workgroup per top column.
-__global__ __launch_bounds__(256) void chain_rows_kernel(SweepArgs A) {
-  const int32_t k = blockIdx.x;
+__device__ __forceinline__ void chain_rows_body(const SweepArgs& A, int64_t k) {
   const Chain c = A.chains[A.top_chain[k]];
   const int32_t j = A.top_node[k] - c.a;
   const int64_t nrow = c.ld - c.dp;
@@ -272,10 +286,11 @@ __global__ __launch_bounds__(256) void chain_rows_kernel(SweepArgs A) {
   }
 }
 
-__global__ __launch_bounds__(64 * kBottomWaves) void bottom_kernel(SweepArgs A, QueryArgs Q) {
+__global__ __launch_bounds__(256) void chain_rows_kernel(SweepArgs A) { chain_rows_body(A, blockIdx.x); }
+
+__device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs& Q, int64_t w) {
   // the waves of a workgroup sweep the same subtree for consecutive windows
   // and share its records through the scalar cache
-  const int64_t w = blockIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int32_t task = load_uniform(Q.work_task + w);
   const int32_t t = load_uniform(Q.work_win + w) + wave;
@@ -378,8 +393,12 @@ __global__ __launch_bounds__(64 * kBottomWaves) void bottom_kernel(SweepArgs A, 
   flush(jend - jb);
 }
 
-__global__ __launch_bounds__(256) void reduce_bottom_kernel(QueryArgs Q) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(64 * kBottomWaves) void bottom_kernel(SweepArgs A, QueryArgs Q) {
+  bottom_body(A, Q, blockIdx.x);
+}
+
+__device__ __forceinline__ void reduce_body(const QueryArgs& Q, int64_t blk) {
+  const int64_t j = blk * 256 + threadIdx.x;
   if (j >= Q.nbq) return;
   const BQuery bq = Q.bq[j];
   if (bq.hiref == kStageRef) return;
@@ -388,12 +407,14 @@ __global__ __launch_bounds__(256) void reduce_bottom_kernel(QueryArgs Q) {
   Q.R[bq.out] = s;
 }
 
+__global__ __launch_bounds__(256) void reduce_bottom_kernel(QueryArgs Q) { reduce_body(Q, blockIdx.x); }
+
 // Pairs whose endpoints are not ancestor-related (eq 12 over the union of the
 // two root paths): rows above the lowest common ancestor are shared, so
 //   R = sum_{d < dl} (z_a[d] - z_b[d])^2 + sum_{d >= dl} z_a[d]^2 + sum_{d >= dl} z_b[d]^2.
 // One wavefront per pair, lanes over depths, fixed order.
-__global__ __launch_bounds__(256) void general_pair_kernel(SweepArgs A, QueryArgs Q) {
-  const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+__device__ __forceinline__ void general_pair_body(const SweepArgs& A, const QueryArgs& Q, int64_t blk) {
+  const int64_t p = blk * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (p >= Q.ngp) return;
   const GPair g = Q.gp[p];
@@ -416,8 +437,12 @@ __global__ __launch_bounds__(256) void general_pair_kernel(SweepArgs A, QueryArg
   if (lane == 0) Q.R[g.out] = s;
 }
 
-__global__ __launch_bounds__(256) void top_query_kernel(SweepArgs A, QueryArgs Q) {
-  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+__global__ __launch_bounds__(256) void general_pair_kernel(SweepArgs A, QueryArgs Q) {
+  general_pair_body(A, Q, blockIdx.x);
+}
+
+__device__ __forceinline__ void top_query_body(const SweepArgs& A, const QueryArgs& Q, int64_t blk) {
+  const int64_t q = blk * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (q >= Q.ntq) return;
   const int32_t lo = Q.tq_lo[q], hi = Q.tq_hi[q];
@@ -434,12 +459,99 @@ __global__ __launch_bounds__(256) void top_query_kernel(SweepArgs A, QueryArgs Q
   if (lane == 0) Q.R[Q.tq_out[q]] = s;
 }
 
-__global__ __launch_bounds__(256) void zero_kernel(QueryArgs Q) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void top_query_kernel(SweepArgs A, QueryArgs Q) { top_query_body(A, Q, blockIdx.x); }
+
+__device__ __forceinline__ void zero_body(const QueryArgs& Q, int64_t blk) {
+  const int64_t j = blk * 256 + threadIdx.x;
   if (j < Q.nzero) Q.R[Q.zero_out[j]] = 0.0;
 }
 
+__global__ __launch_bounds__(256) void zero_kernel(QueryArgs Q) { zero_body(Q, blockIdx.x); }
+
+// ---------------------------------------------------------------- grouped launches
+// One launch covers the same step of many factors: item i of the map names a
+// factor's argument block and the item's index within that factor's own
+// launch of the step. A grid smaller than the item count makes the workgroups
+// loop over items with a fixed stride (persistent form). Every item computes
+// exactly what it computes in the factor's own launch.
+
+template <class T>
+__device__ __forceinline__ T load_struct(const T* p) {
+  static_assert(sizeof(T) % 8 == 0, "argument blocks are whole 8-byte words");
+  uint64_t w[sizeof(T) / 8];
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 8); ++i) w[i] = load_uniform((const uint64_t*)p + i);
+  T r;
+  __builtin_memcpy(&r, w, sizeof(T));
+  return r;
+}
+
+__global__ __launch_bounds__(256) void grouped_gemm_kernel(const FactorArgs* __restrict__ fa,
+                                                           const GroupItem* __restrict__ items, int64_t nitems) {
+  __shared__ GemmRed red;
+  for (int64_t i = blockIdx.x; i < nitems; i += gridDim.x) {
+    const int32_t f = load_uniform(&items[i].fa);
+    const int64_t local = load_uniform(&items[i].local);
+    gemm_body(&fa[f].g, local, red);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(64) void grouped_inv_base_kernel(const FactorArgs* __restrict__ fa,
+                                                              const GroupItem* __restrict__ items, int64_t nitems) {
+  __shared__ BaseTile Ls, Xs;
+  for (int64_t i = blockIdx.x; i < nitems; i += gridDim.x) {
+    const int32_t f = load_uniform(&items[i].fa);
+    const int64_t local = load_uniform(&items[i].local);
+    const SweepArgs A = load_struct(&fa[f].a);
+    inv_base_body(A, local, Ls, Xs);
+    __syncthreads();
+  }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void grouped_kernel(const FactorArgs* __restrict__ fa,
+                                                      const GroupItem* __restrict__ items, int64_t nitems) {
+  for (int64_t i = blockIdx.x; i < nitems; i += gridDim.x) {
+    const int32_t f = load_uniform(&items[i].fa);
+    const int64_t local = load_uniform(&items[i].local);
+    if constexpr (KIND == GK_CHAIN_ROWS) {
+      chain_rows_body(load_struct(&fa[f].a), local);
+    } else if constexpr (KIND == GK_BOTTOM) {
+      bottom_body(load_struct(&fa[f].a), load_struct(&fa[f].q), local);
+    } else if constexpr (KIND == GK_REDUCE) {
+      reduce_body(load_struct(&fa[f].q), local);
+    } else if constexpr (KIND == GK_TOP_QUERY) {
+      top_query_body(load_struct(&fa[f].a), load_struct(&fa[f].q), local);
+    } else if constexpr (KIND == GK_ZERO) {
+      zero_body(load_struct(&fa[f].q), local);
+    } else if constexpr (KIND == GK_GENERAL) {
+      general_pair_body(load_struct(&fa[f].a), load_struct(&fa[f].q), local);
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_grouped(int kind, const FactorArgs* fa, const GroupItem* items, int64_t nitems, int64_t grid,
+                          hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  const dim3 g((unsigned)std::max<int64_t>(1, std::min(grid, nitems)));
+  switch (kind) {
+    case GK_GEMM: hipLaunchKernelGGL(grouped_gemm_kernel, g, dim3(256), 0, s, fa, items, nitems); break;
+    case GK_INV_BASE: hipLaunchKernelGGL(grouped_inv_base_kernel, g, dim3(64), 0, s, fa, items, nitems); break;
+    case GK_CHAIN_ROWS: hipLaunchKernelGGL(grouped_kernel<GK_CHAIN_ROWS>, g, dim3(256), 0, s, fa, items, nitems); break;
+    case GK_BOTTOM:
+      hipLaunchKernelGGL(grouped_kernel<GK_BOTTOM>, g, dim3(64 * kBottomWaves), 0, s, fa, items, nitems);
+      break;
+    case GK_REDUCE: hipLaunchKernelGGL(grouped_kernel<GK_REDUCE>, g, dim3(256), 0, s, fa, items, nitems); break;
+    case GK_TOP_QUERY: hipLaunchKernelGGL(grouped_kernel<GK_TOP_QUERY>, g, dim3(256), 0, s, fa, items, nitems); break;
+    case GK_ZERO: hipLaunchKernelGGL(grouped_kernel<GK_ZERO>, g, dim3(256), 0, s, fa, items, nitems); break;
+    case GK_GENERAL: hipLaunchKernelGGL(grouped_kernel<GK_GENERAL>, g, dim3(256), 0, s, fa, items, nitems); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_gemm(const GemmArgs& g, int64_t task0, int64_t ntasks, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;

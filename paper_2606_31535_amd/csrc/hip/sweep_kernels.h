@@ -65,6 +65,32 @@ struct QueryArgs {
   double* R;
 };
 
+// Everything one factor's sweep reads, for grouped launches over many factors.
+struct FactorArgs {
+  GemmArgs g;
+  SweepArgs a;
+  QueryArgs q;
+};
+
+// One workgroup item of a grouped launch: a factor's argument block and the
+// item's index in that factor's own launch of the same step (GEMM task, base
+// block, top column, bottom work item, or finish block).
+struct GroupItem {
+  int32_t fa;
+  int32_t pad_;
+  int64_t local;
+};
+
+enum GroupKind : int {
+  GK_GEMM = 0, GK_INV_BASE = 1, GK_CHAIN_ROWS = 2, GK_BOTTOM = 3,
+  GK_REDUCE = 4, GK_TOP_QUERY = 5, GK_ZERO = 6, GK_GENERAL = 7
+};
+
+// Items per finish block of each kind (threads or wavefronts per item).
+constexpr int kReduceBlock = 256, kTopQueryBlock = 4, kZeroBlock = 256, kGeneralBlock = 4;
+
+hipError_t launch_grouped(int kind, const FactorArgs* fa, const GroupItem* items, int64_t nitems, int64_t grid,
+                          hipStream_t s);
 hipError_t launch_gemm(const GemmArgs& g, int64_t task0, int64_t ntasks, hipStream_t s);
 hipError_t launch_inv_base(const SweepArgs& a, hipStream_t s);
 hipError_t launch_chain_rows(const SweepArgs& a, int32_t ntop, hipStream_t s);
