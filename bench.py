@@ -196,12 +196,144 @@ def bench_batch(args):
     print(json.dumps(out))
 
 
+SERVED_SIDES = (128, 181, 222, 256, 320, 384, 448, 500)
+
+
+def bench_served(args):
+    """Served form: 8 resident PDN factors, Poisson requests of 1..100k pairs.
+
+    Saturation throughput is measured with the whole trace submitted at once;
+    then the same kind of trace is replayed in real time at 25/50/90% of the
+    saturation request rate. The baseline serves each request alone, one at a
+    time (measured service times, first-come first-served over the same
+    arrival times).
+    """
+    import threading
+    import torch
+    import paper_2606_31535_amd as P
+    t0 = time.time()
+    graphs = [synth.pdn_multilayer(side=sd, layers=4, seed=50000 + i) for i, sd in enumerate(SERVED_SIDES)]
+    t_gen = time.time() - t0
+    t0 = time.time()
+    hs = [P.peers_graph_create(g.n, g.eu, g.ev, g.w, g.ground, coords=g.coords) for g in graphs]
+    t_prep = time.time() - t0
+    dev = P.peers_device_open(0)
+    t0 = time.time()
+    fs = [P.peers_factor_upload(dev, h) for h in hs]
+    torch.cuda.synchronize()
+    t_upload = time.time() - t0
+    used, budget = P.peers_device_usage(dev)
+    nreq = args.served_requests
+
+    def serve(trace, realtime):
+        srv = P.peers_server_start(dev, max_batch_pairs=1 << 20, max_wait_us=500, streams=2)
+        outs = [np.empty(len(r["qu"])) for r in trace]
+        tickets = [None] * len(trace)
+        keep = []
+        start = time.perf_counter()
+
+        def submitter():
+            for i, r in enumerate(trace):
+                if realtime:
+                    delay = r["t"] - (time.perf_counter() - start)
+                    if delay > 0:
+                        time.sleep(delay)
+                t, k = P.peers_server_submit(srv, fs[r["graph"]], r["qu"], r["qv"], outs[i])
+                keep.append(k)
+                tickets[i] = t
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        th.join()
+        for t in tickets:
+            st, res = P.peers_server_wait(srv, t, -1)
+            assert st == 0 and res == 0, (st, res)
+        wall = time.perf_counter() - start
+        stats = P.peers_server_stats_get(srv)
+        P.peers_server_stop(srv)
+        return outs, wall, stats
+
+    # warm the factors' workspaces and the server arenas
+    serve(synth.served_trace(graphs, 16, qps=1e9, seed=7), False)
+    sat_trace = synth.served_trace(graphs, nreq, qps=1e9, seed=synth.CONFIG_SEEDS["C5"])
+    pairs = sum(len(r["qu"]) for r in sat_trace)
+    outs, wall, st_sat = serve(sat_trace, False)
+    sat_rps, sat_qps = pairs / wall, nreq / wall
+    # one request at a time: service time of each request alone
+    service = []
+    same = True
+    for r, o in zip(sat_trace, outs):
+        R = np.empty(len(r["qu"]))
+        t1 = time.perf_counter()
+        P.peers_query(fs[r["graph"]], r["qu"], r["qv"], R)
+        service.append(time.perf_counter() - t1)
+        same = same and np.array_equal(R.view(np.int64), o.view(np.int64))
+    alone_rps = pairs / sum(service)
+
+    def fcfs(trace, svc):
+        free, lat = 0.0, []
+        for r, sv in zip(trace, svc):
+            begin = max(free, r["t"])
+            free = begin + sv
+            lat.append(free - r["t"])
+        return np.array(lat)
+
+    levels = []
+    for frac in (0.25, 0.5, 0.9):
+        tr = synth.served_trace(graphs, nreq, qps=frac * sat_qps, seed=synth.CONFIG_SEEDS["C5"] + 1)
+        _, wall, st = serve(tr, True)
+        # the one-at-a-time baseline over the same arrivals: each request's
+        # service time measured alone
+        svc = []
+        for r in tr:
+            R = np.empty(len(r["qu"]))
+            t1 = time.perf_counter()
+            P.peers_query(fs[r["graph"]], r["qu"], r["qv"], R)
+            svc.append(time.perf_counter() - t1)
+        lat = fcfs(tr, svc) * 1e6
+        npairs = sum(len(r["qu"]) for r in tr)
+        levels.append({"load": frac, "qps": round(frac * sat_qps, 2), "requests": nreq,
+                       "resistances_per_s": round(npairs / wall, 1),
+                       "p50_us": round(st["p50_us"], 1), "p99_us": round(st["p99_us"], 1),
+                       "max_us": round(st["max_us"], 1), "batches": st["batches"],
+                       "one_at_a_time": {"p50_us": round(float(np.percentile(lat, 50)), 1),
+                                         "p99_us": round(float(np.percentile(lat, 99)), 1),
+                                         "max_us": round(float(lat.max()), 1)}})
+    ref = levels[-1]
+    out = {
+        "metric": "served: resistances/s and p50/p99 latency, 8 resident PDN factors (FP64)",
+        "value": round(sat_rps, 1), "unit": "resistances/s", "n_gpus": 1, "steps": nreq, "warmup": 16,
+        "ms_per_step": round(wall * 1e3 / nreq, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "8 PDN meshes (4 layers, sides " + ",".join(map(str, SERVED_SIDES)) +
+                               "), Poisson requests of 1..100000 pairs (log-uniform), 80% edges / 20% random pairs",
+                   "factors": len(graphs), "nodes": [g.n for g in graphs], "requests": nreq, "pairs": pairs},
+        "saturation": {"resistances_per_s": round(sat_rps, 1), "requests_per_s": round(sat_qps, 2),
+                       "batches": st_sat["batches"], "p50_us": round(st_sat["p50_us"], 1),
+                       "p99_us": round(st_sat["p99_us"], 1)},
+        "one_at_a_time_resistances_per_s": round(alone_rps, 1),
+        "speedup_vs_one_at_a_time": round(sat_rps / alone_rps, 3),
+        "bit_identical_to_alone": bool(same),
+        "load_levels": levels,
+        "p50_us_at_90pct": ref["p50_us"], "p99_us_at_90pct": ref["p99_us"],
+        "hbm_bytes": {"resident_factors_and_workspace": used, "budget": budget},
+        "t_gen_s": round(t_gen, 2), "t_prep_s": round(t_prep, 2), "t_upload_s": round(t_upload, 2),
+    }
+    for f in fs:
+        P.peers_factor_release(f)
+    P.peers_device_close(dev)
+    for h in hs:
+        P.peers_graph_destroy(h)
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="C3", choices=sorted(WORKLOADS) + ["C4"])
+    ap.add_argument("--workload", default="C3", choices=sorted(WORKLOADS) + ["C4", "C5"])
+    ap.add_argument("--served-requests", type=int, default=200, help="requests per served trace (C5)")
     ap.add_argument("--batch-count", type=int, default=256, help="graphs in the C4 batch")
     ap.add_argument("--cpu-sample", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -218,6 +350,9 @@ def main():
         return
     if args.workload == "C4":
         bench_batch(args)
+        return
+    if args.workload == "C5":
+        bench_served(args)
         return
 
     import torch

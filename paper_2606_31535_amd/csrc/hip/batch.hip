@@ -20,10 +20,208 @@
 #include <string>
 
 #include "../../../include/peers.h"
+#include "batch.h"
 #include "device_handle.h"
 #include "sweep_kernels.h"
 
 namespace peers {
+
+const char* const kBatchScheduleNames[kBatchSchedules] = {"natural order, one workgroup per item",
+                                                         "largest first, one workgroup per item",
+                                                         "largest first, persistent 8 workgroups per CU",
+                                                         "largest first, persistent 4 workgroups per CU"};
+
+void BatchLayout::use_schedule(int c) {
+  if (bottom_stage < 0) return;
+  stages[bottom_stage].off = bottom_off[c];
+  stages[bottom_stage].grid = bottom_grid[c];
+}
+
+void batch_layout(const DeviceHandle& D, const std::vector<BatchEntry>& E, BatchLayout& L) {
+  L = BatchLayout();
+  const int32_t nb = (int32_t)E.size();
+  L.fargs.resize(nb);
+  for (int32_t i = 0; i < nb; ++i) {
+    const FactorHandle& F = *E[i].F;
+    L.fargs[i].g = F.gemm;
+    L.fargs[i].a = F.sweep;
+    L.fargs[i].q = E[i].plan->args;
+    L.fargs[i].q.part = (double*)F.part;
+    L.fargs[i].q.stage = (double*)F.stage;
+    L.fargs[i].q.R = E[i].R_dev;
+  }
+  std::vector<GroupItem>& items = L.items;
+  auto stage = [&](int kind, auto&& per_factor) {
+    BatchStage st{kind, (int64_t)items.size(), 0, 0};
+    for (int32_t i = 0; i < nb; ++i) per_factor(i);
+    st.n = (int64_t)items.size() - st.off;
+    st.grid = st.n;
+    if (st.n > 0) L.stages.push_back(st);
+  };
+  auto range = [&](int32_t i, int64_t a, int64_t b) {
+    for (int64_t t = a; t < b; ++t) items.push_back(GroupItem{i, 0, t});
+  };
+  // top-step items of chains the entry's plan does not read are left out
+  auto need = [&](int32_t i, int32_t chain) {
+    const DeviceQueryPlan& Q = *E[i].plan;
+    return !Q.prune_top || Q.chain_need[chain];
+  };
+  auto gemm_range = [&](int32_t i, int64_t a, int64_t b) {
+    const FactorPlan& P = *E[i].F->plan;
+    for (int64_t t = a; t < b; ++t)
+      if (need(i, P.prob_chain[P.tasks[t].prob])) items.push_back(GroupItem{i, 0, t});
+  };
+  int32_t hmax = 0, lmax = 0;
+  for (int32_t i = 0; i < nb; ++i) {
+    hmax = std::max(hmax, E[i].F->plan->inv_heights);
+    lmax = std::max(lmax, (int32_t)E[i].F->plan->t2_ptr.size() - 1);
+  }
+  // top tree: L_CC^{-1} (base blocks, then T and X per recursion height),
+  // chain-internal rows, then the chain levels
+  stage(GK_INV_BASE, [&](int32_t i) {
+    const FactorPlan& P = *E[i].F->plan;
+    for (int64_t b = 0; b < (int64_t)P.base_blocks.size(); ++b)
+      if (need(i, P.base_blocks[b].chain)) items.push_back(GroupItem{i, 0, b});
+  });
+  for (int32_t h = 1; h <= hmax; ++h) {
+    stage(GK_GEMM, [&](int32_t i) {
+      const FactorPlan& P = *E[i].F->plan;
+      if (h <= P.inv_heights) gemm_range(i, P.inv_X_ptr[h - 1], P.inv_T_ptr[h]);
+    });
+    stage(GK_GEMM, [&](int32_t i) {
+      const FactorPlan& P = *E[i].F->plan;
+      if (h <= P.inv_heights) gemm_range(i, P.inv_T_ptr[h], P.inv_X_ptr[h]);
+    });
+  }
+  stage(GK_CHAIN_ROWS, [&](int32_t i) {
+    const FactorPlan& P = *E[i].F->plan;
+    for (int64_t k = 0; k < P.ntop; ++k)
+      if (need(i, P.top_chain[k])) items.push_back(GroupItem{i, 0, k});
+  });
+  for (int32_t l = 0; l < lmax; ++l)
+    stage(GK_GEMM, [&](int32_t i) {
+      const FactorPlan& P = *E[i].F->plan;
+      if (l + 1 < (int32_t)P.t2_ptr.size()) gemm_range(i, P.t2_ptr[l], P.t2_ptr[l + 1]);
+    });
+  // bottom subtrees: one item list per candidate schedule
+  {
+    std::vector<GroupItem> nat;
+    std::vector<double> cost;
+    for (int32_t i = 0; i < nb; ++i) {
+      const FactorPlan& P = *E[i].F->plan;
+      const DeviceQueryPlan& Q = *E[i].plan;
+      for (size_t w = 0; w < Q.work_task.size(); ++w) {
+        const int32_t t = Q.work_task[w];
+        const double nodes = P.btask_ptr[t + 1] - P.btask_ptr[t];
+        const double wins = std::min(kBottomWaves, P.btask_nwin[t] - Q.work_win[w]);
+        nat.push_back(GroupItem{i, 0, (int64_t)w});
+        cost.push_back(nodes * wins);
+      }
+    }
+    std::vector<int64_t> ord(nat.size());
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) { return cost[x] > cost[y]; });
+    L.bottom_n = (int64_t)nat.size();
+    for (int c = 0; c < kBatchSchedules; ++c) {
+      L.bottom_off[c] = (int64_t)items.size();
+      if (c == 0) items.insert(items.end(), nat.begin(), nat.end());
+      else
+        for (int64_t k : ord) items.push_back(nat[k]);
+      L.bottom_grid[c] = c == 2 ? 8 * (int64_t)D.cus : c == 3 ? 4 * (int64_t)D.cus : L.bottom_n;
+    }
+    if (L.bottom_n > 0) {
+      L.bottom_stage = (int)L.stages.size();
+      L.stages.push_back(BatchStage{GK_BOTTOM, L.bottom_off[0], L.bottom_n, L.bottom_n});
+    }
+  }
+  // finish: ordered window sums, top-node pairs, zero pairs, non-ancestor pairs
+  auto blocks = [](int64_t n, int64_t per) { return (n + per - 1) / per; };
+  stage(GK_REDUCE, [&](int32_t i) { range(i, 0, blocks(E[i].plan->args.nbq, kReduceBlock)); });
+  stage(GK_TOP_QUERY, [&](int32_t i) { range(i, 0, blocks(E[i].plan->args.ntq, kTopQueryBlock)); });
+  stage(GK_ZERO, [&](int32_t i) { range(i, 0, blocks(E[i].plan->args.nzero, kZeroBlock)); });
+  stage(GK_GENERAL, [&](int32_t i) { range(i, 0, blocks(E[i].plan->args.ngp, kGeneralBlock)); });
+  const uint64_t fa_bytes = (uint64_t)nb * sizeof(FactorArgs);
+  L.items_offset = (fa_bytes + 255) / 256 * 256;
+  L.bytes = L.items_offset + std::max<uint64_t>(items.size(), 1) * sizeof(GroupItem);
+}
+
+Status batch_upload(const BatchLayout& L, void* mem, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(mem, L.fargs.data(), L.fargs.size() * sizeof(FactorArgs), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !L.items.empty())
+    e = hipMemcpyAsync((char*)mem + L.items_offset, L.items.data(), L.items.size() * sizeof(GroupItem),
+                       hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "batch upload");
+  return OK;
+}
+
+Status batch_launch_stage(const BatchLayout& L, const BatchStage& st, void* mem, hipStream_t s) {
+  const auto* fa = (const FactorArgs*)mem;
+  const auto* items = (const GroupItem*)((char*)mem + L.items_offset);
+  hipError_t e = launch_grouped(st.kind, fa, items + st.off, st.n, st.grid, s);
+  if (e != hipSuccess) return hip_fail(e, "grouped launch");
+  return OK;
+}
+
+Status batch_launch(const BatchLayout& L, void* mem, hipStream_t s) {
+  for (const BatchStage& st : L.stages) {
+    Status r = batch_launch_stage(L, st, mem, s);
+    if (r != OK) return r;
+  }
+  return OK;
+}
+
+Status run_sweep_pruned(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t s, bool profile) {
+  std::vector<BatchEntry> be{BatchEntry{&F, &D, R_dev}};
+  auto L = std::make_shared<BatchLayout>();
+  batch_layout(*F.dev, be, *L);
+  if (L->bytes > D.layout_bytes) {
+    if (D.layout_mem) {
+      (void)hipFree(D.layout_mem);
+      F.dev->release(D.layout_bytes);
+      D.layout_mem = nullptr;
+      D.layout_bytes = 0;
+    }
+    Status st = F.dev->reserve(L->bytes);
+    if (st != OK) return st;
+    hipError_t e = hipMalloc(&D.layout_mem, L->bytes);
+    if (e != hipSuccess) {
+      F.dev->release(L->bytes);
+      return hip_fail(e, "hipMalloc(pruned sweep)");
+    }
+    D.layout_bytes = L->bytes;
+  }
+  Status st = batch_upload(*L, D.layout_mem, s);
+  if (st != OK) return st;
+  D.layout_host = L;  // host image stays alive while the copies may be pending
+  if (profile && !F.ev[0])
+    for (auto& e : F.ev) {
+      hipError_t he = hipEventCreate(&e);
+      if (he != hipSuccess) return hip_fail(he, "hipEventCreate");
+    }
+  F.timed = profile;
+  int32_t top = 0, bottom = 0;
+  const int nst = (int)L->stages.size();
+  // phase boundaries (events 1 and 2): the first bottom-or-finish step and the first finish step
+  int b1 = nst, b2 = nst;
+  for (int k = nst - 1; k >= 0; --k) {
+    if (L->stages[k].kind == GK_BOTTOM || L->stages[k].kind >= GK_REDUCE) b1 = k;
+    if (L->stages[k].kind >= GK_REDUCE) b2 = k;
+  }
+  if (profile) (void)hipEventRecord(F.ev[0], s);
+  for (int k = 0; k <= nst; ++k) {
+    if (profile && k == b1) (void)hipEventRecord(F.ev[1], s);
+    if (profile && k == b2) (void)hipEventRecord(F.ev[2], s);
+    if (k == nst) break;
+    st = batch_launch_stage(*L, L->stages[k], D.layout_mem, s);
+    if (st != OK) return st;
+    if (L->stages[k].kind == GK_BOTTOM) ++bottom;
+    else if (k < b1) ++top;
+  }
+  if (profile) (void)hipEventRecord(F.ev[3], s);
+  F.top_launches = top;
+  F.bottom_launches = bottom;
+  return OK;
+}
 
 namespace {
 
@@ -36,39 +234,20 @@ struct Entry {
   int64_t q = 0;
 };
 
-struct Stage {
-  int kind;
-  int64_t off, n, grid;
-};
-
-constexpr int kSchedules = 4;
-const char* const kScheduleNames[kSchedules] = {"natural order, one workgroup per item",
-                                               "largest first, one workgroup per item",
-                                               "largest first, persistent 8 workgroups per CU",
-                                               "largest first, persistent 4 workgroups per CU"};
-
 }  // namespace
 
-// A built batch: argument blocks, item maps and stages in device memory, and
-// the captured graph.
+// A built batch: layout in device memory and the captured graph.
 struct BatchExec {
   std::vector<const FactorHandle*> factors;
   std::vector<const void*> key;
   DeviceHandle* dev = nullptr;
+  BatchLayout L;
   void* mem = nullptr;
   uint64_t bytes = 0;
-  FactorArgs* fa = nullptr;
-  GroupItem* items = nullptr;
-  std::vector<Stage> stages;               // bottom stage index: bottom_stage
-  int bottom_stage = -1;
-  int64_t bottom_off[kSchedules] = {0, 0, 0, 0};
-  int64_t bottom_grid[kSchedules] = {0, 0, 0, 0};
-  int64_t bottom_n = 0;
   int schedule = -1;
-  double cand_ms[kSchedules] = {0, 0, 0, 0};
+  double cand_ms[kBatchSchedules] = {0, 0, 0, 0};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  int64_t replays = 0;
   ~BatchExec() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -93,9 +272,9 @@ void batch_cache_free(DeviceHandle& D) {
 void batch_cache_forget(DeviceHandle& D, const FactorHandle* F) {
   std::lock_guard<std::mutex> g(D.batch_mu);
   if (!D.batches) return;
-  auto& L = D.batches->execs;
-  for (auto it = L.begin(); it != L.end();) {
-    if (std::find((*it)->factors.begin(), (*it)->factors.end(), F) != (*it)->factors.end()) it = L.erase(it);
+  auto& Lst = D.batches->execs;
+  for (auto it = Lst.begin(); it != Lst.end();) {
+    if (std::find((*it)->factors.begin(), (*it)->factors.end(), F) != (*it)->factors.end()) it = Lst.erase(it);
     else ++it;
   }
 }
@@ -104,132 +283,42 @@ namespace {
 
 constexpr size_t kMaxCached = 4;
 
-Status build_exec(DeviceHandle& D, std::vector<Entry>& E, BatchExec& X) {
-  const int32_t nb = (int32_t)E.size();
-  std::vector<FactorArgs> fargs(nb);
-  for (int32_t i = 0; i < nb; ++i) {
-    FactorHandle& F = *E[i].F;
-    fargs[i].g = F.gemm;
-    fargs[i].a = F.sweep;
-    fargs[i].q = E[i].plan->args;
-    fargs[i].q.part = (double*)F.part;
-    fargs[i].q.stage = (double*)F.stage;
-    fargs[i].q.R = E[i].R_dev;
-    X.factors.push_back(&F);
+Status build_exec(DeviceHandle& D, std::vector<Entry>& E, BatchExec& X, hipStream_t s) {
+  std::vector<BatchEntry> be;
+  for (auto& e : E) {
+    be.push_back(BatchEntry{e.F, e.plan, e.R_dev});
+    X.factors.push_back(e.F);
   }
-  std::vector<GroupItem> items;
-  auto stage = [&](int kind, int64_t grid_cap, auto&& per_factor) {
-    Stage st{kind, (int64_t)items.size(), 0, 0};
-    for (int32_t i = 0; i < nb; ++i) per_factor(i);
-    st.n = (int64_t)items.size() - st.off;
-    st.grid = grid_cap > 0 ? grid_cap : st.n;
-    if (st.n > 0) X.stages.push_back(st);
-  };
-  auto range = [&](int32_t i, int64_t a, int64_t b) {
-    for (int64_t t = a; t < b; ++t) items.push_back(GroupItem{i, 0, t});
-  };
-  int32_t hmax = 0, lmax = 0;
-  for (int32_t i = 0; i < nb; ++i) {
-    hmax = std::max(hmax, E[i].F->plan->inv_heights);
-    lmax = std::max(lmax, (int32_t)E[i].F->plan->t2_ptr.size() - 1);
-  }
-  // top tree: L_CC^{-1} (base blocks, then T and X per recursion height),
-  // chain-internal rows, then the chain levels
-  stage(GK_INV_BASE, 0, [&](int32_t i) { range(i, 0, (int64_t)E[i].F->plan->base_blocks.size()); });
-  for (int32_t h = 1; h <= hmax; ++h) {
-    stage(GK_GEMM, 0, [&](int32_t i) {
-      const FactorPlan& P = *E[i].F->plan;
-      if (h <= P.inv_heights) range(i, P.inv_X_ptr[h - 1], P.inv_T_ptr[h]);
-    });
-    stage(GK_GEMM, 0, [&](int32_t i) {
-      const FactorPlan& P = *E[i].F->plan;
-      if (h <= P.inv_heights) range(i, P.inv_T_ptr[h], P.inv_X_ptr[h]);
-    });
-  }
-  stage(GK_CHAIN_ROWS, 0, [&](int32_t i) { range(i, 0, E[i].F->plan->ntop); });
-  for (int32_t l = 0; l < lmax; ++l)
-    stage(GK_GEMM, 0, [&](int32_t i) {
-      const FactorPlan& P = *E[i].F->plan;
-      if (l + 1 < (int32_t)P.t2_ptr.size()) range(i, P.t2_ptr[l], P.t2_ptr[l + 1]);
-    });
-  // bottom subtrees: one item list per candidate schedule
-  {
-    std::vector<GroupItem> nat;
-    std::vector<double> cost;
-    for (int32_t i = 0; i < nb; ++i) {
-      const FactorPlan& P = *E[i].F->plan;
-      const DeviceQueryPlan& Q = *E[i].plan;
-      for (size_t w = 0; w < Q.work_task.size(); ++w) {
-        const int32_t t = Q.work_task[w];
-        const double nodes = P.btask_ptr[t + 1] - P.btask_ptr[t];
-        const double wins = std::min(kBottomWaves, P.btask_nwin[t] - Q.work_win[w]);
-        nat.push_back(GroupItem{i, 0, (int64_t)w});
-        cost.push_back(nodes * wins);
-      }
-    }
-    std::vector<int64_t> ord(nat.size());
-    std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) { return cost[x] > cost[y]; });
-    X.bottom_n = (int64_t)nat.size();
-    for (int c = 0; c < kSchedules; ++c) {
-      X.bottom_off[c] = (int64_t)items.size();
-      if (c == 0) items.insert(items.end(), nat.begin(), nat.end());
-      else
-        for (int64_t k : ord) items.push_back(nat[k]);
-      X.bottom_grid[c] = c == 2 ? 8 * (int64_t)D.cus : c == 3 ? 4 * (int64_t)D.cus : X.bottom_n;
-    }
-    if (X.bottom_n > 0) {
-      X.bottom_stage = (int)X.stages.size();
-      X.stages.push_back(Stage{GK_BOTTOM, X.bottom_off[1], X.bottom_n, X.bottom_n});
-    }
-  }
-  // finish: ordered window sums, top-node pairs, zero pairs, non-ancestor pairs
-  auto blocks = [](int64_t n, int64_t per) { return (n + per - 1) / per; };
-  stage(GK_REDUCE, 0, [&](int32_t i) { range(i, 0, blocks(E[i].plan->args.nbq, kReduceBlock)); });
-  stage(GK_TOP_QUERY, 0, [&](int32_t i) { range(i, 0, blocks(E[i].plan->args.ntq, kTopQueryBlock)); });
-  stage(GK_ZERO, 0, [&](int32_t i) { range(i, 0, blocks(E[i].plan->args.nzero, kZeroBlock)); });
-  stage(GK_GENERAL, 0, [&](int32_t i) { range(i, 0, blocks(E[i].plan->args.ngp, kGeneralBlock)); });
-
-  const uint64_t fa_bytes = (uint64_t)nb * sizeof(FactorArgs);
-  const uint64_t it_off = (fa_bytes + 255) / 256 * 256;
-  X.bytes = it_off + std::max<uint64_t>(items.size(), 1) * sizeof(GroupItem);
-  Status st = D.reserve(X.bytes);
-  if (st != OK) { X.bytes = 0; return st; }
+  batch_layout(D, be, X.L);
+  Status st = D.reserve(X.L.bytes);
+  if (st != OK) return st;
   X.dev = &D;
+  X.bytes = X.L.bytes;
   hipError_t e = hipMalloc(&X.mem, X.bytes);
-  if (e != hipSuccess) { D.release(X.bytes); X.bytes = 0; X.mem = nullptr; return hip_fail(e, "hipMalloc(batch)"); }
-  X.fa = (FactorArgs*)X.mem;
-  X.items = (GroupItem*)((char*)X.mem + it_off);
-  e = hipMemcpy(X.fa, fargs.data(), fa_bytes, hipMemcpyHostToDevice);
-  if (e == hipSuccess && !items.empty())
-    e = hipMemcpy(X.items, items.data(), items.size() * sizeof(GroupItem), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "batch upload");
-  return OK;
-}
-
-Status launch_stage(const BatchExec& X, const Stage& st, hipStream_t s) {
-  hipError_t e = launch_grouped(st.kind, X.fa, X.items + st.off, st.n, st.grid, s);
-  if (e != hipSuccess) return hip_fail(e, "grouped launch");
-  return OK;
-}
-
-Status launch_all(const BatchExec& X, hipStream_t s) {
-  for (const Stage& st : X.stages) {
-    Status r = launch_stage(X, st, s);
-    if (r != OK) return r;
+  if (e != hipSuccess) {
+    D.release(X.bytes);
+    X.bytes = 0;
+    X.mem = nullptr;
+    return hip_fail(e, "hipMalloc(batch)");
   }
-  return OK;
+  st = batch_upload(X.L, X.mem, s);
+  if (st == OK) {
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize(batch upload)");
+  }
+  return st;
 }
 
 // Times each bottom schedule (after one pass of the top steps, which the
 // bottom step only reads) and keeps the fastest.
 Status autotune(BatchExec& X, hipStream_t s) {
-  if (X.bottom_stage < 0) {
+  BatchLayout& L = X.L;
+  if (L.bottom_stage < 0) {
     X.schedule = 0;
     return OK;
   }
-  for (int k = 0; k < X.bottom_stage; ++k) {
-    Status r = launch_stage(X, X.stages[k], s);
+  for (int k = 0; k < L.bottom_stage; ++k) {
+    Status r = batch_launch_stage(L, L.stages[k], X.mem, s);
     if (r != OK) return r;
   }
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -241,12 +330,12 @@ Status autotune(BatchExec& X, hipStream_t s) {
   }
   Status r = OK;
   double best = 1e300;
-  for (int c = 0; c < kSchedules && r == OK; ++c) {
-    const Stage st{GK_BOTTOM, X.bottom_off[c], X.bottom_n, X.bottom_grid[c]};
+  for (int c = 0; c < kBatchSchedules && r == OK; ++c) {
+    const BatchStage st{GK_BOTTOM, L.bottom_off[c], L.bottom_n, L.bottom_grid[c]};
     double tmin = 1e300;
     for (int rep = 0; rep < 2 && r == OK; ++rep) {
       hipError_t e = hipEventRecord(ev[0], s);
-      if (e == hipSuccess) r = launch_stage(X, st, s);
+      if (e == hipSuccess) r = batch_launch_stage(L, st, X.mem, s);
       if (r == OK && e == hipSuccess) e = hipEventRecord(ev[1], s);
       if (r == OK && e == hipSuccess) e = hipEventSynchronize(ev[1]);
       float ms = 0;
@@ -263,13 +352,11 @@ Status autotune(BatchExec& X, hipStream_t s) {
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);
   if (r != OK) return r;
-  Stage& bs = X.stages[X.bottom_stage];
-  bs.off = X.bottom_off[X.schedule];
-  bs.grid = X.bottom_grid[X.schedule];
+  L.use_schedule(X.schedule);
   return OK;
 }
 
-Status capture(BatchExec& X, hipStream_t s) {
+Status capture(BatchExec& X) {
   hipStream_t cs = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e != hipSuccess) return hip_fail(e, "hipStreamCreate(capture)");
@@ -277,7 +364,7 @@ Status capture(BatchExec& X, hipStream_t s) {
   e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) r = hip_fail(e, "hipStreamBeginCapture");
   if (r == OK) {
-    r = launch_all(X, cs);
+    r = batch_launch(X.L, X.mem, cs);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cs, &g);
     if (r == OK && e != hipSuccess) r = hip_fail(e, "hipStreamEndCapture");
@@ -288,7 +375,6 @@ Status capture(BatchExec& X, hipStream_t s) {
     if (e != hipSuccess) r = hip_fail(e, "hipGraphInstantiate");
   }
   (void)hipStreamDestroy(cs);
-  (void)s;
   return r;
 }
 
@@ -388,9 +474,9 @@ peers_status peers_batch_query(peers_device d, int32_t nb, const peers_factor* f
   if (st == OK && !X) {
     owned.reset(new BatchExec());
     owned->key = key;
-    st = build_exec(*D, E, *owned);
+    st = build_exec(*D, E, *owned, s);
     if (st == OK) st = autotune(*owned, s);
-    if (st == OK) st = capture(*owned, s);
+    if (st == OK) st = capture(*owned);
     if (st == OK) X = owned.get();
   }
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -402,7 +488,6 @@ peers_status peers_batch_query(peers_device d, int32_t nb, const peers_factor* f
     he = hipGraphLaunch(X->exec, s);
     if (he != hipSuccess) st = hip_fail(he, "hipGraphLaunch");
     (void)hipEventRecord(ev[1], s);
-    ++X->replays;
   }
   for (int32_t i = 0; i < nb && st == OK; ++i)
     if (E[i].R_host && E[i].q > 0) {
@@ -418,12 +503,12 @@ peers_status peers_batch_query(peers_device d, int32_t nb, const peers_factor* f
     peers_batch_info& I = C.last;
     I = peers_batch_info{};
     I.factors = nb;
-    I.stages = (int32_t)X->stages.size();
-    I.bottom_items = X->bottom_n;
+    I.stages = (int32_t)X->L.stages.size();
+    I.bottom_items = X->L.bottom_n;
     I.schedule = X->schedule;
-    I.candidates = kSchedules;
-    for (int c = 0; c < kSchedules; ++c) I.candidate_ms[c] = X->cand_ms[c];
-    std::snprintf(I.schedule_name, sizeof(I.schedule_name), "%s", kScheduleNames[std::max(0, X->schedule)]);
+    I.candidates = kBatchSchedules;
+    for (int c = 0; c < kBatchSchedules; ++c) I.candidate_ms[c] = X->cand_ms[c];
+    std::snprintf(I.schedule_name, sizeof(I.schedule_name), "%s", kBatchScheduleNames[std::max(0, X->schedule)]);
     I.graph_reused = reused ? 1 : 0;
     if (must_sync && hipEventElapsedTime(&total_ms, ev[0], ev[1]) == hipSuccess) I.last_ms = total_ms;
   }

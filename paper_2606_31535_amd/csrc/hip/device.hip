@@ -11,6 +11,7 @@
 
 #include "../../../include/peers.h"
 #include "../host/graph_handle.h"
+#include "batch.h"
 #include "device_handle.h"
 #include "sweep_kernels.h"
 
@@ -71,8 +72,7 @@ void DeviceHandle::release(uint64_t bytes) {
   used = bytes > used ? 0 : used - bytes;
 }
 
-Status upload_query_plan(FactorHandle& F, const QueryPlan& Q, DeviceQueryPlan& D, hipStream_t s) {
-  Packer pk;
+static void pack_query_plan(const QueryPlan& Q, DeviceQueryPlan& D, Packer& pk) {
   pk.add(Q.work_task, &D.args.work_task);
   pk.add(Q.work_win, &D.args.work_win);
   pk.add(Q.gp, &D.args.gp);
@@ -91,7 +91,29 @@ Status upload_query_plan(FactorHandle& F, const QueryPlan& Q, DeviceQueryPlan& D
   D.stage_elems = Q.stage_elems;
   D.work_task = Q.work_task;
   D.work_win = Q.work_win;
+  D.chain_need = Q.chain_need;
+  D.prune_top = Q.prune_top;
   D.q = Q.q;
+}
+
+uint64_t query_plan_bytes(const QueryPlan& Q) {
+  Packer pk;
+  DeviceQueryPlan D;
+  pack_query_plan(Q, D, pk);
+  return pk.total;
+}
+
+Status upload_query_plan_to(const QueryPlan& Q, DeviceQueryPlan& D, void* mem, hipStream_t s) {
+  Packer pk;
+  pack_query_plan(Q, D, pk);
+  D.base = nullptr;  // not owned
+  D.bytes = 0;
+  return pk.commit(mem, s);
+}
+
+Status upload_query_plan(FactorHandle& F, const QueryPlan& Q, DeviceQueryPlan& D, hipStream_t s) {
+  Packer pk;
+  pack_query_plan(Q, D, pk);
   D.bytes = pk.total;
   Status st = F.dev->reserve(D.bytes);
   if (st != OK) return st;
@@ -101,6 +123,10 @@ Status upload_query_plan(FactorHandle& F, const QueryPlan& Q, DeviceQueryPlan& D
 }
 
 void free_query_plan(FactorHandle& F, DeviceQueryPlan& D) {
+  if (D.layout_mem) { (void)hipFree(D.layout_mem); F.dev->release(D.layout_bytes); }
+  D.layout_mem = nullptr;
+  D.layout_bytes = 0;
+  D.layout_host.reset();
   if (D.base) { (void)hipFree(D.base); F.dev->release(D.bytes); }
   D.base = nullptr;
   D.bytes = 0;
@@ -150,6 +176,7 @@ static Status run_chain_inverse(FactorHandle& F, hipStream_t s, int32_t& launche
 }
 
 Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t s, bool profile) {
+  if (D.prune_top) return run_sweep_pruned(F, D, R_dev, s, profile);
   QueryArgs q = D.args;
   q.part = (double*)F.part;
   q.stage = (double*)F.stage;

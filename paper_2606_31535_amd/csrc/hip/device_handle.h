@@ -39,6 +39,12 @@ struct DeviceQueryPlan {
   int64_t stage_elems = 0;
   int64_t q = 0;
   std::vector<int32_t> work_task, work_win;  // host copies (batch schedules)
+  std::vector<char> chain_need;              // top chains the plan reads
+  bool prune_top = false;
+  // grouped-launch image of a pruned plan on its own factor (owned)
+  void* layout_mem = nullptr;
+  uint64_t layout_bytes = 0;
+  std::shared_ptr<void> layout_host;
 };
 
 struct FactorHandle {
@@ -73,6 +79,9 @@ struct FactorHandle {
 
 Status hip_fail(hipError_t e, const char* what);
 Status upload_query_plan(FactorHandle& F, const QueryPlan& Q, DeviceQueryPlan& D, hipStream_t s);
+// Device bytes of a plan, and its upload into caller memory (not owned by D).
+uint64_t query_plan_bytes(const QueryPlan& Q);
+Status upload_query_plan_to(const QueryPlan& Q, DeviceQueryPlan& D, void* mem, hipStream_t s);
 void free_query_plan(FactorHandle& F, DeviceQueryPlan& D);
 Status ensure_workspace(FactorHandle& F, int64_t nslots, int64_t nres, int64_t nstage);
 Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t s, bool profile);

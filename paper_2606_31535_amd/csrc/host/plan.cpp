@@ -70,6 +70,11 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
     c.level = pb < 0 ? 0 : P.chains[chain_of[pb]].level + 1;
     P.nchain_levels = std::max(P.nchain_levels, c.level + 1);
   }
+  P.chain_parent.assign(nch, -1);
+  for (int32_t ci = 0; ci < nch; ++ci) {
+    const int32_t pb = S.parent[P.chains[ci].b];
+    P.chain_parent[ci] = pb < 0 ? -1 : chain_of[pb];
+  }
   // U_C, store layout, dense blocks
   std::vector<int32_t> mark(N, -1), upos(N, -1);
   int64_t lcc_elems = 0, luc_elems = 0;
@@ -170,6 +175,7 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
     g.M = c.nU; g.N = c.w; g.K = c.w; g.alpha = -1.0;
     const int32_t pid = (int32_t)P.probs.size();
     P.probs.push_back(g);
+    P.prob_chain.push_back(ci);
     add_tiles(pid, g.M, g.N, [&](int32_t, int32_t c0, int32_t& k0, int32_t& k1) { k0 = c0; k1 = g.K; });
     P.f_bpre += (double)c.nU * c.w * c.w / 2.0;
   }
@@ -209,6 +215,7 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
       g.M = n2; g.N = n1; g.K = n1; g.alpha = 1.0;
       const int32_t pid = (int32_t)P.probs.size();
       P.probs.push_back(g);
+      P.prob_chain.push_back(mg.chain);
       add_tiles(pid, n2, n1, [&](int32_t, int32_t c0, int32_t& k0, int32_t& k1) { k0 = c0; k1 = n1; });
       P.f_top_inv += (double)n2 * n1 * n1 / 2.0;
       toff += ldt * n1;
@@ -227,6 +234,7 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
       g.M = n2; g.N = n1; g.K = n2; g.alpha = -1.0;
       const int32_t pid = (int32_t)P.probs.size();
       P.probs.push_back(g);
+      P.prob_chain.push_back(mg.chain);
       add_tiles(pid, n2, n1, [&](int32_t r0, int32_t, int32_t& k0, int32_t& k1) {
         k0 = 0;
         k1 = std::min(n2, r0 + kTileM);
@@ -251,6 +259,7 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
         g.M = c.dp; g.N = c.w; g.K = c.nU; g.alpha = 1.0;
         const int32_t pid = (int32_t)P.probs.size();
         P.probs.push_back(g);
+        P.prob_chain.push_back(ci);
         const int32_t* ud = P.u_depth.data() + c.u_begin;
         add_tiles(pid, g.M, g.N, [&](int32_t r0, int32_t, int32_t& k0, int32_t& k1) {
           k0 = 0;
@@ -276,11 +285,16 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
   };
   if ((P.store_elems >> (62 - kRefShift)) != 0) { set_error("plan: store too large for packed references"); return E_INTERNAL; }
   P.btask_ptr.assign(1, 0);
+  P.btask_attach_ptr.assign(1, 0);
   int32_t cur = 0, curmaxd = 0;
   auto close_task = [&]() {
     if (cur == 0) return;
     P.btask_ptr.push_back((int32_t)P.bnode.size());
     P.btask_nwin.push_back(nwin_of(curmaxd));
+    auto b = P.btask_attach.begin() + P.btask_attach_ptr.back();
+    std::sort(b, P.btask_attach.end());
+    P.btask_attach.erase(std::unique(b, P.btask_attach.end()), P.btask_attach.end());
+    P.btask_attach_ptr.push_back((int32_t)P.btask_attach.size());
     cur = 0;
     curmaxd = 0;
   };
@@ -290,6 +304,7 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
     if (p >= 0 && P.small[p]) continue;  // not a bottom root
     const int32_t sz = r - S.first[r] + 1;
     if (cur > 0 && cur + sz > kBottomMaxNodes) close_task();
+    if (p >= 0) P.btask_attach.push_back(chain_of[p]);  // the chain this subtree hangs from
     for (int32_t v = r; v >= S.first[r]; --v) {
       BNode bn{};
       bn.isd = P.isd[v];
@@ -343,6 +358,8 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
   P.bent.push_back(BEnt{0, 0.0});
   const int32_t nbt = (int32_t)P.btask_nwin.size();
   P.bpos_task.assign(P.bnode_node.size(), 0);
+  P.node_pos.assign(N, -1);
+  for (int32_t k = 0; k < (int32_t)P.bnode_node.size(); ++k) P.node_pos[P.bnode_node[k]] = k;
   for (int32_t t = 0; t < nbt; ++t)
     for (int32_t k = P.btask_ptr[t]; k < P.btask_ptr[t + 1]; ++k) P.bpos_task[k] = t;
   P.max_btask_nwin = 0;
@@ -401,13 +418,12 @@ Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int
   const int32_t N = P.N;
   Q = QueryPlan();
   Q.q = q;
-  // bottom position of every bottom node
-  std::vector<int32_t> pos(N, -1);
+  const std::vector<int32_t>& pos = P.node_pos;  // bottom position of every bottom node
   const int32_t nbn = (int32_t)P.bnode_node.size();
-  for (int32_t k = 0; k < nbn; ++k) pos[P.bnode_node[k]] = k;
   Q.bq_ptr.assign(nbn + 1, 0);
   std::vector<int32_t> lo_of(q, -2), hi_of(q, -1);
   std::vector<char> general(q, 0);
+  std::vector<int32_t> gp_top;  // top endpoints of non-ancestor pairs
   std::vector<int64_t> stage_of;  // per node: staging offset of its column, -1 if not staged
   auto column = [&](int32_t x, int64_t& off, int32_t& staged) {
     if (!P.small[x]) {
@@ -443,6 +459,8 @@ Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int
       g.dl = c < 0 ? 0 : depth[c];
       g.out = k;
       Q.gp.push_back(g);
+      if (!P.small[lo]) gp_top.push_back(lo);
+      if (!P.small[hi]) gp_top.push_back(hi);
       general[k] = 1;
       continue;
     }
@@ -492,13 +510,25 @@ Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int
   Q.nslots = (int64_t)std::max(Q.max_nwin, P.max_btask_nwin) * nb;
   // work list: the tasks with at least one bucket entry, every window
   const int32_t nbt = (int32_t)P.btask_nwin.size();
+  const int32_t nch = (int32_t)P.chains.size();
+  Q.chain_need.assign(nch, 0);
   for (int32_t t = 0; t < nbt; ++t) {
     if (Q.bq_ptr[P.btask_ptr[t + 1]] == Q.bq_ptr[P.btask_ptr[t]]) continue;
     for (int32_t w = 0; w < P.btask_nwin[t]; w += kBottomWaves) {
       Q.work_task.push_back(t);
       Q.work_win.push_back(w);
     }
+    for (int32_t k = P.btask_attach_ptr[t]; k < P.btask_attach_ptr[t + 1]; ++k) Q.chain_need[P.btask_attach[k]] = 1;
   }
+  // top chains the plan reads: those of its top endpoints and of the swept
+  // subtrees' attachment points, and every ancestor chain of those
+  for (int32_t lo : Q.tq_lo) Q.chain_need[P.top_chain[lo]] = 1;
+  for (int32_t x : gp_top) Q.chain_need[P.top_chain[P.top_index[x]]] = 1;
+  for (int32_t c = 0; c < nch; ++c)
+    if (Q.chain_need[c] && P.chain_parent[c] >= 0) Q.chain_need[P.chain_parent[c]] = 1;
+  int32_t need = 0;
+  for (int32_t c = 0; c < nch; ++c) need += Q.chain_need[c];
+  Q.prune_top = need < nch;
   return OK;
 }
 

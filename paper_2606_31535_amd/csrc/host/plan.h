@@ -145,6 +145,10 @@ struct FactorPlan {
   std::vector<BEnt> bent;
   std::vector<int32_t> btask_nwin;  // windows per task
   std::vector<int32_t> bpos_task;   // per processing position: its task
+  std::vector<int32_t> node_pos;    // per node: its bottom processing position (-1 for top nodes)
+  std::vector<int32_t> btask_attach_ptr, btask_attach;  // per task: chains its subtrees hang from
+  std::vector<int32_t> prob_chain;  // per GEMM problem: its chain
+  std::vector<int32_t> chain_parent;  // per chain: chain of parent(b), -1 at a root
   int32_t max_btask_nwin = 0;
   std::vector<double> isd;          // per node D^{-1/2}
   int32_t max_lslot = 0;
@@ -218,6 +222,10 @@ struct QueryPlan {
   // bottom work items (task, first window): only the subtrees that hold a
   // lower endpoint or a staged column are swept
   std::vector<int32_t> work_task, work_win;
+  // top chains the plan reads (closed under ancestors); prune_top when that
+  // is not every chain, and only those chains' top steps need to run
+  std::vector<char> chain_need;
+  bool prune_top = false;
 };
 
 // a, b: permuted node indices (-1 = ground), per query; out = query number.
