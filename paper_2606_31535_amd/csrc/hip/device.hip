@@ -289,11 +289,11 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
   F->iperm = G.sym.iperm;
   F->first = G.sym.first;
   F->depth = G.sym.depth;
-  F->anc.build(G.sym.parent, G.sym.depth);
   F->plan.reset(new FactorPlan());
   Status st = build_plan(G.sym, G.num, *F->plan);
   if (st != OK) return (peers_status)st;
   const FactorPlan& P = *F->plan;
+  F->anc.build(G.sym.parent, G.sym.depth, P);
   // resident all-edge query plan
   {
     std::vector<int32_t> a(F->m), b(F->m);

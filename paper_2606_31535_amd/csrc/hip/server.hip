@@ -155,8 +155,13 @@ void launch(Server& S, Slot& sl, std::vector<Request*> take) {
   std::vector<std::pair<Request*, peers_status>> failed;
   std::vector<FactorHandle*> planned;
   int64_t total = 0;
-  for (FactorHandle* F : forder) {
-    std::vector<Request*>& G = groups[F];
+  // host plans of the factors, in parallel (independent per factor)
+  const size_t nf = forder.size();
+  std::vector<QueryPlan> plans(nf);
+  std::vector<Status> pst(nf, OK);
+  auto plan_one = [&](size_t i) {
+    FactorHandle* F = forder[i];
+    const std::vector<Request*>& G = groups[F];
     int64_t q = 0;
     for (Request* r : G) q += r->q;
     std::vector<int32_t> a, b;
@@ -166,14 +171,24 @@ void launch(Server& S, Slot& sl, std::vector<Request*> take) {
       a.insert(a.end(), r->a.begin(), r->a.end());
       b.insert(b.end(), r->b.begin(), r->b.end());
     }
-    QueryPlan Q;
-    Status st = build_query_plan_handle(*F, q, a.data(), b.data(), Q);
-    if (st == OK) st = ensure_workspace(*F, Q.nslots, q, Q.stage_elems);
+    pst[i] = build_query_plan_handle(*F, q, a.data(), b.data(), plans[i]);
+  };
+  {
+    std::vector<std::thread> th;
+    for (size_t i = 1; i < nf; ++i) th.emplace_back(plan_one, i);
+    if (nf) plan_one(0);
+    for (auto& t : th) t.join();
+  }
+  for (size_t i = 0; i < nf; ++i) {
+    FactorHandle* F = forder[i];
+    std::vector<Request*>& G = groups[F];
+    Status st = pst[i];
+    if (st == OK) st = ensure_workspace(*F, plans[i].nslots, plans[i].q, plans[i].stage_elems);
     if (st != OK) {
       for (Request* r : G) failed.push_back({r, (peers_status)st});
       continue;
     }
-    sl.hplans.push_back(std::move(Q));
+    sl.hplans.push_back(std::move(plans[i]));
     planned.push_back(F);
     for (Request* r : G) {
       sl.reqs.push_back(r);

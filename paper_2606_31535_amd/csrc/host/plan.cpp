@@ -379,37 +379,46 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
   return OK;
 }
 
-void AncestorTable::build(const std::vector<int32_t>& parent, const std::vector<int32_t>& depth_in) {
-  N = (int32_t)parent.size();
+void AncestorTable::build(const std::vector<int32_t>& parent_in, const std::vector<int32_t>& depth_in,
+                          const FactorPlan& plan) {
+  P = &plan;
+  parent = parent_in;
   depth = depth_in;
-  int32_t h = 1;
-  for (int32_t i = 0; i < N; ++i) h = std::max(h, depth[i]);
-  levels = 1;
-  while ((1 << levels) < h) ++levels;
-  up.assign((size_t)levels * N, -1);
-  for (int32_t i = 0; i < N; ++i) up[i] = parent[i];
-  for (int32_t l = 1; l < levels; ++l)
-    for (int32_t i = 0; i < N; ++i) {
-      const int32_t m = up[(size_t)(l - 1) * N + i];
-      up[(size_t)l * N + i] = m < 0 ? -1 : up[(size_t)(l - 1) * N + m];
-    }
+  const int32_t N = (int32_t)parent.size();
+  broot.assign(N, -1);
+  for (int32_t i = N - 1; i >= 0; --i) {  // parents come after their children
+    if (!P->small[i]) continue;
+    const int32_t p = parent[i];
+    broot[i] = (p >= 0 && P->small[p]) ? broot[p] : i;
+  }
 }
 
 int32_t AncestorTable::lca(int32_t a, int32_t b) const {
-  if (depth[a] < depth[b]) std::swap(a, b);
-  for (int32_t l = levels - 1; l >= 0; --l) {
-    const int32_t m = up[(size_t)l * N + a];
-    if (m >= 0 && depth[m] >= depth[b]) a = m;
-  }
   if (a == b) return a;
-  for (int32_t l = levels - 1; l >= 0; --l) {
-    const int32_t ma = up[(size_t)l * N + a], mb = up[(size_t)l * N + b];
-    if (ma != mb) {
-      a = ma;
-      b = mb;
+  if (P->small[a] && P->small[b] && broot[a] == broot[b]) {
+    while (a != b) {
+      if (depth[a] >= depth[b]) a = parent[a];
+      else b = parent[b];
+    }
+    return a;
+  }
+  // the top nodes the two root paths enter the top tree at
+  if (P->small[a]) a = parent[broot[a]];
+  if (P->small[b]) b = parent[broot[b]];
+  if (a < 0 || b < 0) return -1;  // a bottom subtree that is a whole tree of its own
+  int32_t ca = P->top_chain[P->top_index[a]], cb = P->top_chain[P->top_index[b]];
+  while (ca != cb) {
+    if (P->chains[ca].level >= P->chains[cb].level) {
+      a = parent[P->chains[ca].b];
+      if (a < 0) return -1;
+      ca = P->top_chain[P->top_index[a]];
+    } else {
+      b = parent[P->chains[cb].b];
+      if (b < 0) return -1;
+      cb = P->top_chain[P->top_index[b]];
     }
   }
-  return up[a];  // -1 when a and b are roots of different trees
+  return std::max(a, b);
 }
 
 Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int32_t>& depth,

@@ -192,12 +192,16 @@ struct GPair {
   int64_t out;
 };
 
-// Lowest common ancestors in the elimination tree by binary lifting.
+// Lowest common ancestors in the elimination tree, using the split into
+// bottom subtrees and top chains: inside one bottom subtree by climbing
+// parents (at most its height), otherwise from the top nodes the two subtrees
+// hang from, chain to chain up the chain tree (each chain is a path of
+// consecutive indices, so within a chain the ancestor is the larger index).
 struct AncestorTable {
-  int32_t N = 0, levels = 0;
-  std::vector<int32_t> up;     // up[l * N + i] = 2^l-th ancestor of i (-1 past the root)
-  std::vector<int32_t> depth;  // root = 1
-  void build(const std::vector<int32_t>& parent, const std::vector<int32_t>& depth_in);
+  const FactorPlan* P = nullptr;
+  std::vector<int32_t> parent, depth;
+  std::vector<int32_t> broot;   // per bottom node: root of its bottom subtree (-1 for top nodes)
+  void build(const std::vector<int32_t>& parent_in, const std::vector<int32_t>& depth_in, const FactorPlan& plan);
   int32_t lca(int32_t a, int32_t b) const;  // -1 if a and b are in different trees
 };
 
