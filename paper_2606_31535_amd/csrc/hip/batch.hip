@@ -113,7 +113,7 @@ void batch_layout(const DeviceHandle& D, const std::vector<BatchEntry>& E, Batch
       for (size_t w = 0; w < Q.work_task.size(); ++w) {
         const int32_t t = Q.work_task[w];
         const double nodes = P.btask_ptr[t + 1] - P.btask_ptr[t];
-        const double wins = std::min(kBottomWaves, P.btask_nwin[t] - Q.work_win[w]);
+        const double wins = std::min(kBottomWaves * kWinPerWave, P.btask_nwin[t] - Q.work_win[w]);
         nat.push_back(GroupItem{i, 0, (int64_t)w});
         cost.push_back(nodes * wins);
       }

@@ -288,90 +288,145 @@ __device__ __forceinline__ void chain_rows_body(const SweepArgs& A, int64_t k) {
 
 __global__ __launch_bounds__(256) void chain_rows_kernel(SweepArgs A) { chain_rows_body(A, blockIdx.x); }
 
+// One wavefront sweeps kWinPerWave consecutive windows of one subtree task:
+// lane l holds depth t*64 + l of window t for each of them. The per-node
+// records, address arithmetic and query reductions are shared by the windows.
 __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs& Q, int64_t w) {
+  constexpr int NW = kWinPerWave;
   // the waves of a workgroup sweep the same subtree for consecutive windows
   // and share its records through the scalar cache
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int32_t task = load_uniform(Q.work_task + w);
-  const int32_t t = load_uniform(Q.work_win + w) + wave;
+  const int32_t t0 = load_uniform(Q.work_win + w) + wave * NW;
   const int32_t p0 = load_uniform(A.btask_ptr + task), p1 = load_uniform(A.btask_ptr + task + 1);
-  if (t >= load_uniform(A.btask_nwin + task)) return;
+  if (t0 >= load_uniform(A.btask_nwin + task)) return;
   const int lane = threadIdx.x & 63;
-  const int32_t d0 = t * kWin;
-  const int32_t d = d0 + lane;
   constexpr int64_t kRefMask = (int64_t(1) << kRefShift) - 1;
-  // Value of a top column at this lane's depth. Windows past the column's
-  // depth read the store's leading zero block, so the load is unconditional.
+  // Value of a top column at this lane's depth in window t0 + v. Windows past
+  // the column's depth read the store's leading zero block, so the load is
+  // unconditional.
   const double* __restrict__ zs = A.store + lane;
-  auto top_value = [&](int64_t ref) -> double {
-    const int64_t off = t < (int32_t)(ref & kRefMask) ? (ref >> kRefShift) + d0 : 0;
+  auto top_value = [&](int64_t ref, int v) -> double {
+    const int32_t t = t0 + v;
+    const int64_t off = t < (int32_t)(ref & kRefMask) ? (ref >> kRefShift) + (int64_t)t * kWin : 0;
     return zs[off];
   };
   // values of the current root path inside the subtree, by local depth
   // (register-resident; every slot index is wave-uniform)
-  double ps[kBottomMaxHeight];
+  // one array per window: each stays small enough to live in registers
+  static_assert(NW == 1 || NW == 2, "one or two windows per wavefront");
+  double ps0[kBottomMaxHeight], ps1[kBottomMaxHeight];
 #pragma unroll
-  for (int k = 0; k < kBottomMaxHeight; ++k) ps[k] = 0.0;
-  // window sums of the task's queries: lane j - jb holds query j's, stored
-  // 64 at a time into the window-major partial slots
+  for (int k = 0; k < kBottomMaxHeight; ++k) ps0[k] = ps1[k] = 0.0;
+  auto ps_get = [&](int v, int32_t k) -> double { return v == 0 ? ps0[k] : ps1[k]; };
+  auto ps_set = [&](int v, int32_t k, double x) {
+    if (v == 0) ps0[k] = x;
+    else ps1[k] = x;
+  };
+  // window-group sums of the task's queries: lane j - jb holds query j's,
+  // stored 64 at a time into the window-major partial slots
+  const int32_t grp = t0 / NW;
   const int32_t jend = load_uniform(Q.bq_ptr + p1);
   int32_t jb = load_uniform(Q.bq_ptr + p0);
   double qbuf = 0.0;
   auto flush = [&](int32_t count) {
-    if (lane < count) Q.part[(int64_t)t * Q.nbq + jb + lane] = qbuf;
+    if (lane < count) Q.part[(int64_t)grp * Q.nbq + jb + lane] = qbuf;
   };
 
   // Software pipeline over the subtree's nodes: while node p is computed,
-  // the store values of node p+1 and the record of node p+2 are in flight.
+  // the store values of node p+1, the record of node p+1 and the store
+  // references of node p+2 are in flight.
   BNode cur = load_uniform(A.bnode + p0);
-  BNode nxt = load_uniform(A.bnode + p0 + 1);
-  double va0 = top_value(cur.tref[0]), va1 = top_value(cur.tref[1]);
-  double vb0 = 0.0, vb1 = 0.0;
-  auto step = [&](int32_t p, const double& u0, const double& u1, double& n0, double& n1) {
-    const BNode nx2 = load_uniform(A.bnode + p + 2);
-    n0 = top_value(nxt.tref[0]);
-    n1 = top_value(nxt.tref[1]);
+  int64_t r0 = load_uniform(&A.bnode[p0 + 1].tref[0]), r1 = load_uniform(&A.bnode[p0 + 1].tref[1]);
+  double va[NW][2], vb[NW][2];
+#pragma unroll
+  for (int v = 0; v < NW; ++v) {
+    va[v][0] = top_value(cur.tref[0], v);
+    va[v][1] = top_value(cur.tref[1], v);
+    vb[v][0] = vb[v][1] = 0.0;
+  }
+  auto step = [&](int32_t p, const double (&u)[NW][2], double (&nn)[NW][2]) {
+#pragma unroll
+    for (int v = 0; v < NW; ++v) {
+      nn[v][0] = top_value(r0, v);
+      nn[v][1] = top_value(r1, v);
+    }
+    const BNode nfull = load_uniform(A.bnode + p + 1);
+    const int64_t s0 = load_uniform(&A.bnode[p + 2].tref[0]), s1 = load_uniform(&A.bnode[p + 2].tref[1]);
     const int32_t q0 = load_uniform(Q.bq_ptr + p), q1 = load_uniform(Q.bq_ptr + p + 1);
     // eq 11: entries on the path stack, then entries in the top store
     const int32_t sl = cur.slots;
-    double a = cur.lc[0] * ps[sl & 15];
-    a = fma(cur.lc[1], ps[(sl >> 4) & 15], a);
-    a = fma(cur.lc[2], ps[(sl >> 8) & 15], a);
+    double acc[NW];
+#pragma unroll
+    for (int v = 0; v < NW; ++v) {
+      double a = cur.lc[0] * ps_get(v, sl & 15);
+      a = fma(cur.lc[1], ps_get(v, (sl >> 4) & 15), a);
+      acc[v] = fma(cur.lc[2], ps_get(v, (sl >> 8) & 15), a);
+    }
     const int32_t n_lds_more = cur.n_more & 0xffff, n_top_more = cur.n_more >> 16;
     for (int32_t e = 0; e < n_lds_more; ++e) {
       const BEnt be = load_uniform(A.bent + cur.ent + e);
-      a = fma(be.coef, ps[be.ref & 15], a);
+#pragma unroll
+      for (int v = 0; v < NW; ++v) acc[v] = fma(be.coef, ps_get(v, be.ref & 15), acc[v]);
     }
-    double at = fma(cur.tc[1], u1, cur.tc[0] * u0);
+    double at[NW];
+#pragma unroll
+    for (int v = 0; v < NW; ++v) at[v] = fma(cur.tc[1], u[v][1], cur.tc[0] * u[v][0]);
     for (int32_t e = 0; e < n_top_more; ++e) {
       const BEnt be = load_uniform(A.bent + cur.ent + n_lds_more + e);
-      const double v = top_value(be.ref);
+      double x[NW];
+#pragma unroll
+      for (int v = 0; v < NW; ++v) x[v] = top_value(be.ref, v);
       wait_vector_loads();
-      at = fma(be.coef, v, at);
+#pragma unroll
+      for (int v = 0; v < NW; ++v) at[v] = fma(be.coef, x[v], at[v]);
     }
-    double acc = a + at;
-    if (d == cur.depth - 1) acc = cur.isd;
-    ps[(sl >> 12) & 15] = acc;
-    // eq 12 over this window for the queries whose lower endpoint is this node
-    if (t < (cur.depth + kWin - 1) / kWin) {
+    const int32_t top_slot = (sl >> 12) & 15;
+#pragma unroll
+    for (int v = 0; v < NW; ++v) {
+      acc[v] += at[v];
+      if ((t0 + v) * kWin + lane == cur.depth - 1) acc[v] = cur.isd;
+      ps_set(v, top_slot, acc[v]);
+    }
+    // eq 12 over these windows for the queries whose lower endpoint is this node
+    const int32_t nwin_node = (cur.depth + kWin - 1) / kWin;
+    if (t0 < nwin_node) {
       for (int32_t j = q0; j < q1; ++j) {
         const int64_t h = load_uniform(&Q.bq[j].hiref);
         if (h == kStageRef) {
           // this node's column is one side of a non-ancestor pair
-          Q.stage[load_uniform(&Q.bq[j].out) + d] = acc;
+          const int64_t off = load_uniform(&Q.bq[j].out);
+#pragma unroll
+          for (int v = 0; v < NW; ++v)
+            if (t0 + v < nwin_node) Q.stage[off + (int64_t)(t0 + v) * kWin + lane] = acc[v];
           continue;
         }
-        double zh;
-        if (h >= 0) zh = ps[h & 15];
-        else if (h == kInlineTopRef) zh = u0;
-        else if (h == kInlineTopRef - 1) zh = u1;
-        else if (h == kGroundRef) zh = 0.0;
-        else {
-          zh = top_value(-h - kStoreRefBias);
+        double zh[NW];
+        if (h >= 0) {
+#pragma unroll
+          for (int v = 0; v < NW; ++v) zh[v] = ps_get(v, h & 15);
+        } else if (h == kInlineTopRef) {
+#pragma unroll
+          for (int v = 0; v < NW; ++v) zh[v] = u[v][0];
+        } else if (h == kInlineTopRef - 1) {
+#pragma unroll
+          for (int v = 0; v < NW; ++v) zh[v] = u[v][1];
+        } else if (h == kGroundRef) {
+#pragma unroll
+          for (int v = 0; v < NW; ++v) zh[v] = 0.0;
+        } else {
+#pragma unroll
+          for (int v = 0; v < NW; ++v) zh[v] = top_value(-h - kStoreRefBias, v);
           wait_vector_loads();
         }
-        const double df = acc - zh;
-        const double sq = wave_sum(df * df);
+        // windows past the node's depth hold zeros on both sides
+        double s = 0.0;
+#pragma unroll
+        for (int v = 0; v < NW; ++v) {
+          const double df = acc[v] - zh[v];
+          s = fma(df, df, s);
+        }
+        const double sq = wave_sum(s);
         while (j - jb >= kWin) {
           flush(kWin);
           jb += kWin;
@@ -379,12 +434,13 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
         qbuf = lane == j - jb ? sq : qbuf;
       }
     }
-    cur = nxt;
-    nxt = nx2;
+    cur = nfull;
+    r0 = s0;
+    r1 = s1;
   };
   for (int32_t p = p0; p < p1; p += 2) {
-    step(p, va0, va1, vb0, vb1);
-    if (p + 1 < p1) step(p + 1, vb0, vb1, va0, va1);
+    step(p, va, vb);
+    if (p + 1 < p1) step(p + 1, vb, va);
   }
   while (jend - jb > kWin) {
     flush(kWin);
@@ -403,7 +459,8 @@ __device__ __forceinline__ void reduce_body(const QueryArgs& Q, int64_t blk) {
   const BQuery bq = Q.bq[j];
   if (bq.hiref == kStageRef) return;
   double s = 0.0;
-  for (int32_t t = 0; t < bq.nwin; ++t) s += Q.part[(int64_t)t * Q.nbq + j];
+  const int32_t ng = (bq.nwin + kWinPerWave - 1) / kWinPerWave;
+  for (int32_t g = 0; g < ng; ++g) s += Q.part[(int64_t)g * Q.nbq + j];
   Q.R[bq.out] = s;
 }
 

@@ -514,16 +514,17 @@ Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int
     }
     Q.max_nwin = std::max(Q.max_nwin, bq.nwin);
   }
-  // a sweep window writes the slots of all its task's queries (those of
-  // windows past a query's column are never read)
-  Q.nslots = (int64_t)std::max(Q.max_nwin, P.max_btask_nwin) * nb;
+  // a sweep wavefront writes one slot per query of its task for its group of
+  // kWinPerWave windows (groups past a query's column are never read)
+  const int32_t groups = (std::max(Q.max_nwin, P.max_btask_nwin) + kWinPerWave - 1) / kWinPerWave;
+  Q.nslots = (int64_t)groups * nb;
   // work list: the tasks with at least one bucket entry, every window
   const int32_t nbt = (int32_t)P.btask_nwin.size();
   const int32_t nch = (int32_t)P.chains.size();
   Q.chain_need.assign(nch, 0);
   for (int32_t t = 0; t < nbt; ++t) {
     if (Q.bq_ptr[P.btask_ptr[t + 1]] == Q.bq_ptr[P.btask_ptr[t]]) continue;
-    for (int32_t w = 0; w < P.btask_nwin[t]; w += kBottomWaves) {
+    for (int32_t w = 0; w < P.btask_nwin[t]; w += kBottomWaves * kWinPerWave) {
       Q.work_task.push_back(t);
       Q.work_win.push_back(w);
     }

@@ -44,7 +44,8 @@ constexpr int kTileN = 32;            // GEMM output tile columns
 constexpr int kBase = 64;             // base block of the triangular inverse
 constexpr int kBottomMaxHeight = 16;  // path-stack slots (registers) per window
 constexpr int kBottomMaxNodes = 512;
-constexpr int kBottomWaves = 4;       // windows per bottom workgroup (one per wavefront)
+constexpr int kBottomWaves = 4;       // wavefronts per bottom workgroup
+constexpr int kWinPerWave = 2;        // windows per bottom wavefront (lane l: depths t*64 + l)
 constexpr int32_t kGroundCode = INT32_MIN;
 
 // Device buffers a GEMM operand can live in.
