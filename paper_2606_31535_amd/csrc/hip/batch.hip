@@ -71,28 +71,10 @@ void batch_layout(const DeviceHandle& D, const std::vector<BatchEntry>& E, Batch
     for (int64_t t = a; t < b; ++t)
       if (need(i, P.prob_chain[P.tasks[t].prob])) items.push_back(GroupItem{i, 0, t});
   };
-  int32_t hmax = 0, lmax = 0;
-  for (int32_t i = 0; i < nb; ++i) {
-    hmax = std::max(hmax, E[i].F->plan->inv_heights);
-    lmax = std::max(lmax, (int32_t)E[i].F->plan->t2_ptr.size() - 1);
-  }
-  // top tree: L_CC^{-1} (base blocks, then T and X per recursion height),
-  // chain-internal rows, then the chain levels
-  stage(GK_INV_BASE, [&](int32_t i) {
-    const FactorPlan& P = *E[i].F->plan;
-    for (int64_t b = 0; b < (int64_t)P.base_blocks.size(); ++b)
-      if (need(i, P.base_blocks[b].chain)) items.push_back(GroupItem{i, 0, b});
-  });
-  for (int32_t h = 1; h <= hmax; ++h) {
-    stage(GK_GEMM, [&](int32_t i) {
-      const FactorPlan& P = *E[i].F->plan;
-      if (h <= P.inv_heights) gemm_range(i, P.inv_X_ptr[h - 1], P.inv_T_ptr[h]);
-    });
-    stage(GK_GEMM, [&](int32_t i) {
-      const FactorPlan& P = *E[i].F->plan;
-      if (h <= P.inv_heights) gemm_range(i, P.inv_T_ptr[h], P.inv_X_ptr[h]);
-    });
-  }
+  int32_t lmax = 0;
+  for (int32_t i = 0; i < nb; ++i) lmax = std::max(lmax, (int32_t)E[i].F->plan->t2_ptr.size() - 1);
+  // top tree (L_CC^{-1} is part of each prepared factor): chain-internal
+  // rows, then the chain levels
   stage(GK_CHAIN_ROWS, [&](int32_t i) {
     const FactorPlan& P = *E[i].F->plan;
     for (int64_t k = 0; k < P.ntop; ++k)

@@ -82,7 +82,7 @@ static void pack_query_plan(const QueryPlan& Q, DeviceQueryPlan& D, Packer& pk) 
   pk.add(Q.tq_hi, &D.args.tq_hi);
   pk.add(Q.tq_out, &D.args.tq_out);
   pk.add(Q.zero_out, &D.args.zero_out);
-  D.args.nbq = (int64_t)Q.bq.size();
+  D.args.nbq = Q.nbq();
   D.args.ntq = (int64_t)Q.tq_out.size();
   D.args.nzero = (int64_t)Q.zero_out.size();
   D.args.nwork = (int64_t)Q.work_task.size();
@@ -186,9 +186,9 @@ Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t
     for (auto& e : F.ev) HIP_TRY(hipEventCreate(&e));
   F.timed = profile;
   if (profile) HIP_TRY(hipEventRecord(F.ev[0], s));
+  // L_CC^{-1} of every chain is part of the prepared factor (formed at
+  // upload with B_C); the sweep starts from the chain-internal rows
   int32_t launches = 0;
-  Status st = run_chain_inverse(F, s, launches);
-  if (st != OK) return st;
   HIP_TRY(launch_chain_rows(F.sweep, P.ntop, s));
   launches += P.ntop > 0 ? 1 : 0;
   for (size_t l = 0; l + 1 < P.t2_ptr.size(); ++l) {
@@ -383,6 +383,16 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
   (void)hipFree(lucbuf);
   D->release(luc_bytes);
   GA.buf[BUF_LUC] = nullptr;
+  // the recursion temporaries are needed only while L_CC^{-1} is formed
+  if (st == OK && F->tbuf) {
+    (void)hipFree(F->tbuf);
+    F->tbuf = nullptr;
+    GA.buf[BUF_T] = nullptr;
+    const uint64_t tb = (uint64_t)std::max<int64_t>(P.t_elems, 1) * 8;
+    F->store_bytes -= tb;
+    F->reserved -= tb;
+    D->release(tb);
+  }
   if (st != OK) return (peers_status)st;
   st = ensure_workspace(*F, F->edges.nslots, F->m, F->edges.stage_elems);
   if (st != OK) return (peers_status)st;

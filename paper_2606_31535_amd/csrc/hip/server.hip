@@ -214,7 +214,7 @@ void launch(Server& S, Slot& sl, std::vector<Request*> take) {
       DeviceQueryPlan& d = sl.dplans[i];
       d.work_task = sl.hplans[i].work_task;
       d.work_win = sl.hplans[i].work_win;
-      d.args.nbq = (int64_t)sl.hplans[i].bq.size();
+      d.args.nbq = sl.hplans[i].nbq();
       d.args.ntq = (int64_t)sl.hplans[i].tq_out.size();
       d.args.nzero = (int64_t)sl.hplans[i].zero_out.size();
       d.args.ngp = (int64_t)sl.hplans[i].gp.size();

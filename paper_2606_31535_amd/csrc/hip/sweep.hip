@@ -77,20 +77,28 @@ __device__ __forceinline__ double dpp(double x) {
 // not have to drain the loads that are prefetched for the next node.
 __device__ __forceinline__ void wait_vector_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
+// A DPP move of a double into the rows enabled by ROWS (other rows get 0).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_rows(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROWS, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
 // Sum over the 64 lanes, in a fixed order, without LDS traffic: butterflies
 // inside each row of 16 (quad_perm [1,0,3,2], [2,3,0,1], row_half_mirror,
-// row_mirror), then the four row sums combined as (r0 + r1) + (r2 + r3).
-// The result is wave-uniform.
+// row_mirror) leave row r's sum S_r in all its lanes; then row_bcast:15 adds
+// S_0 into row 1 and S_2 into row 3, and row_bcast:31 adds row 1's lane 31
+// into row 3, so lane 63 holds (S_3 + S_2) + (S_1 + S_0). Wave-uniform result.
 __device__ __forceinline__ double wave_sum(double v) {
   v += dpp<0xB1>(v);
   v += dpp<0x4E>(v);
   v += dpp<0x141>(v);
   v += dpp<0x140>(v);
-  auto lane_value = [&](int l) {
-    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
-                            __builtin_amdgcn_readlane(__double2loint(v), l));
-  };
-  return (lane_value(0) + lane_value(16)) + (lane_value(32) + lane_value(48));
+  v += dpp_rows<0x142, 0xA>(v);
+  v += dpp_rows<0x143, 0xC>(v);
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                          __builtin_amdgcn_readlane(__double2loint(v), 63));
 }
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -100,7 +108,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // e1 are clamped to a valid column and their B value is zeroed at use, so the
 // loop body has no branches and each load is waited for only right before its
 // MFMAs. Gathered column offsets come through the scalar unit one step ahead.
-template <bool GATHER>
+template <bool GATHER, bool BT>
 __device__ __forceinline__ void gemm_accumulate(f64x4 (&C)[4][2], const double* __restrict__ A,
                                                 const double* __restrict__ B, const int64_t* __restrict__ gt,
                                                 const GemmProb& pb, const int32_t (&rows)[4], const int32_t (&cols)[2],
@@ -131,7 +139,7 @@ __device__ __forceinline__ void gemm_accumulate(f64x4 (&C)[4][2], const double* 
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) a[rb] = A[acol + rows[rb]];
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) b[cb] = B[(int64_t)cols[cb] * pb.ldb + ec];
+    for (int cb = 0; cb < 2; ++cb) b[cb] = BT ? B[(int64_t)ec * pb.ldb + cols[cb]] : B[(int64_t)cols[cb] * pb.ldb + ec];
   };
   auto mma = [&](int32_t e, const double (&a)[4], const double (&b)[2]) {
     const bool ok = e + kk < e1;
@@ -196,8 +204,13 @@ __device__ __forceinline__ void gemm_body(const GemmArgs* Gp, int64_t task, Gemm
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) C[rb][cb] = f64x4{0.0, 0.0, 0.0, 0.0};
   if (e0 < e1) {
-    if (pb.gather) gemm_accumulate<true>(C, A, B, gt, pb, rows, cols, kk, e0, e1);
-    else gemm_accumulate<false>(C, A, B, gt, pb, rows, cols, kk, e0, e1);
+    if (pb.gather) {
+      if (pb.trans & 1) gemm_accumulate<true, true>(C, A, B, gt, pb, rows, cols, kk, e0, e1);
+      else gemm_accumulate<true, false>(C, A, B, gt, pb, rows, cols, kk, e0, e1);
+    } else {
+      if (pb.trans & 1) gemm_accumulate<false, true>(C, A, B, gt, pb, rows, cols, kk, e0, e1);
+      else gemm_accumulate<false, false>(C, A, B, gt, pb, rows, cols, kk, e0, e1);
+    }
   }
   if (wave > 0) {
 #pragma unroll
@@ -231,10 +244,18 @@ __device__ __forceinline__ void gemm_body(const GemmArgs* Gp, int64_t task, Gemm
   }
   __syncthreads();
   double* __restrict__ Cm = load_uniform(&Gp->buf[pb.c_buf]) + pb.c_off;
-  for (int idx = threadIdx.x; idx < kTileM * kTileN; idx += 256) {
-    const int r = idx & (kTileM - 1), c = idx / kTileM;
-    const int32_t gr = tk.row0 + r, gc = tk.col0 + c;
-    if (gr < pb.M && gc < pb.N) Cm[(int64_t)gc * pb.ldc + gr] = pb.alpha * tile[r * LD + c];
+  if (pb.trans & 2) {
+    for (int idx = threadIdx.x; idx < kTileM * kTileN; idx += 256) {
+      const int c = idx & (kTileN - 1), r = idx / kTileN;
+      const int32_t gr = tk.row0 + r, gc = tk.col0 + c;
+      if (gr < pb.M && gc < pb.N) Cm[(int64_t)gr * pb.ldc + gc] = pb.alpha * tile[r * LD + c];
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < kTileM * kTileN; idx += 256) {
+      const int r = idx & (kTileM - 1), c = idx / kTileM;
+      const int32_t gr = tk.row0 + r, gc = tk.col0 + c;
+      if (gr < pb.M && gc < pb.N) Cm[(int64_t)gc * pb.ldc + gr] = pb.alpha * tile[r * LD + c];
+    }
   }
 }
 
@@ -338,6 +359,9 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
   // references of node p+2 are in flight.
   BNode cur = load_uniform(A.bnode + p0);
   int64_t r0 = load_uniform(&A.bnode[p0 + 1].tref[0]), r1 = load_uniform(&A.bnode[p0 + 1].tref[1]);
+  int32_t qa = load_uniform(Q.bq_ptr + p0), qb = load_uniform(Q.bq_ptr + p0 + 1);
+  int64_t qh = load_uniform(&Q.bq[qa].hiref);
+  int32_t qk = load_uniform(&Q.bq[qa].kind);
   double va[NW][2], vb[NW][2];
 #pragma unroll
   for (int v = 0; v < NW; ++v) {
@@ -353,7 +377,12 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
     }
     const BNode nfull = load_uniform(A.bnode + p + 1);
     const int64_t s0 = load_uniform(&A.bnode[p + 2].tref[0]), s1 = load_uniform(&A.bnode[p + 2].tref[1]);
-    const int32_t q0 = load_uniform(Q.bq_ptr + p), q1 = load_uniform(Q.bq_ptr + p + 1);
+    // bucket of node p is [q0, q1) (read two nodes ahead); request the end of
+    // node p+2's bucket and node p+1's first entry (one padding entry at the end)
+    const int32_t q0 = qa, q1 = qb;
+    const int32_t nqc = load_uniform(Q.bq_ptr + p + 2);
+    const int64_t nqh = load_uniform(&Q.bq[q1].hiref);
+    const int32_t nqk = load_uniform(&Q.bq[q1].kind);
     // eq 11: entries on the path stack, then entries in the top store
     const int32_t sl = cur.slots;
     double acc[NW];
@@ -392,41 +421,40 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
     const int32_t nwin_node = (cur.depth + kWin - 1) / kWin;
     if (t0 < nwin_node) {
       for (int32_t j = q0; j < q1; ++j) {
-        const int64_t h = load_uniform(&Q.bq[j].hiref);
-        if (h == kStageRef) {
+        // the node's first entry was read during the previous node
+        int64_t h = qh;
+        int32_t kind = qk;
+        if (j > q0) {
+          h = load_uniform(&Q.bq[j].hiref);
+          kind = load_uniform(&Q.bq[j].kind);
+        }
+        if (kind == kQStage) {
           // this node's column is one side of a non-ancestor pair
-          const int64_t off = load_uniform(&Q.bq[j].out);
 #pragma unroll
           for (int v = 0; v < NW; ++v)
-            if (t0 + v < nwin_node) Q.stage[off + (int64_t)(t0 + v) * kWin + lane] = acc[v];
+            if (t0 + v < nwin_node) Q.stage[h + (int64_t)(t0 + v) * kWin + lane] = acc[v];
           continue;
         }
         double zh[NW];
-        if (h >= 0) {
+        if (kind == kQSlot) {
 #pragma unroll
-          for (int v = 0; v < NW; ++v) zh[v] = ps_get(v, h & 15);
-        } else if (h == kInlineTopRef) {
+          for (int v = 0; v < NW; ++v) zh[v] = ps_get(v, (int32_t)h & 15);
+        } else if (kind != kQStore) {
 #pragma unroll
-          for (int v = 0; v < NW; ++v) zh[v] = u[v][0];
-        } else if (h == kInlineTopRef - 1) {
-#pragma unroll
-          for (int v = 0; v < NW; ++v) zh[v] = u[v][1];
-        } else if (h == kGroundRef) {
-#pragma unroll
-          for (int v = 0; v < NW; ++v) zh[v] = 0.0;
+          for (int v = 0; v < NW; ++v) zh[v] = kind == kQInl0 ? u[v][0] : (kind == kQInl1 ? u[v][1] : 0.0);
         } else {
 #pragma unroll
-          for (int v = 0; v < NW; ++v) zh[v] = top_value(-h - kStoreRefBias, v);
+          for (int v = 0; v < NW; ++v) zh[v] = top_value(h, v);
           wait_vector_loads();
         }
         // windows past the node's depth hold zeros on both sides
-        double s = 0.0;
+        double sacc = 0.0;
 #pragma unroll
         for (int v = 0; v < NW; ++v) {
           const double df = acc[v] - zh[v];
-          s = fma(df, df, s);
+          sacc = fma(df, df, sacc);
         }
-        const double sq = wave_sum(s);
+        const double sq = wave_sum(sacc);
         while (j - jb >= kWin) {
           flush(kWin);
           jb += kWin;
@@ -434,6 +462,10 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
         qbuf = lane == j - jb ? sq : qbuf;
       }
     }
+    qh = nqh;
+    qk = nqk;
+    qa = q1;
+    qb = nqc;
     cur = nfull;
     r0 = s0;
     r1 = s1;
@@ -457,7 +489,7 @@ __device__ __forceinline__ void reduce_body(const QueryArgs& Q, int64_t blk) {
   const int64_t j = blk * 256 + threadIdx.x;
   if (j >= Q.nbq) return;
   const BQuery bq = Q.bq[j];
-  if (bq.hiref == kStageRef) return;
+  if (bq.kind == kQStage) return;
   double s = 0.0;
   const int32_t ng = (bq.nwin + kWinPerWave - 1) / kWinPerWave;
   for (int32_t g = 0; g < ng; ++g) s += Q.part[(int64_t)g * Q.nbq + j];

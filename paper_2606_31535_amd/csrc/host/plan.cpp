@@ -171,7 +171,7 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
     GemmProb g{};
     g.a_buf = BUF_LUC; g.a_off = c.luc_off; g.lda = c.ldb; g.aoff_begin = -1; g.gather = 0;
     g.b_buf = BUF_X; g.b_off = c.x_off; g.ldb = c.ldl;
-    g.c_buf = BUF_BT; g.c_off = c.bt_off; g.ldc = c.ldb;
+    g.c_buf = BUF_BT; g.c_off = c.bt_off; g.ldc = c.w; g.trans = 2;  // B_C row-major
     g.M = c.nU; g.N = c.w; g.K = c.w; g.alpha = -1.0;
     const int32_t pid = (int32_t)P.probs.size();
     P.probs.push_back(g);
@@ -254,7 +254,7 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
         const Chain& c = P.chains[ci];
         GemmProb g{};
         g.a_buf = BUF_STORE; g.a_off = 0; g.lda = 0; g.aoff_begin = c.u_begin; g.gather = 1;
-        g.b_buf = BUF_BT; g.b_off = c.bt_off; g.ldb = c.ldb;
+        g.b_buf = BUF_BT; g.b_off = c.bt_off; g.ldb = c.w; g.trans = 1;  // B_C row-major
         g.c_buf = BUF_STORE; g.c_off = c.store_base; g.ldc = c.ld;
         g.M = c.dp; g.N = c.w; g.K = c.nU; g.alpha = 1.0;
         const int32_t pid = (int32_t)P.probs.size();
@@ -491,8 +491,9 @@ Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int
     for (int32_t x = 0; x < N; ++x) {
       if (stage_of[x] < 0) continue;
       BQuery& bq = Q.bq[fill[pos[x]]++];
-      bq.hiref = kStageRef;
-      bq.out = stage_of[x];
+      bq.kind = kQStage;
+      bq.hiref = stage_of[x];
+      bq.out = -1;
       bq.nwin = nwin_of(depth[x]);
       Q.max_nwin = std::max(Q.max_nwin, bq.nwin);
     }
@@ -504,16 +505,24 @@ Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int
     bq.out = k;
     bq.nwin = nwin_of(depth[lo]);
     const int32_t ps = pos[lo];
-    if (hi < 0) bq.hiref = kGroundRef;
-    else if (P.small[hi]) bq.hiref = P.lslot[hi];
-    else if (P.bnode_tinl[2 * ps] == hi) bq.hiref = kInlineTopRef;
-    else if (P.bnode_tinl[2 * ps + 1] == hi) bq.hiref = kInlineTopRef - 1;
+    bq.hiref = 0;
+    if (hi < 0) bq.kind = kQGround;
+    else if (P.small[hi]) {
+      bq.kind = kQSlot;
+      bq.hiref = P.lslot[hi];
+    } else if (P.bnode_tinl[2 * ps] == hi) bq.kind = kQInl0;
+    else if (P.bnode_tinl[2 * ps + 1] == hi) bq.kind = kQInl1;
     else {
       const int32_t t = P.top_index[hi];
-      bq.hiref = -(((P.top_off[t] << kRefShift) | (int64_t)nwin_of(P.top_depth[t])) + kStoreRefBias);
+      bq.kind = kQStore;
+      bq.hiref = (P.top_off[t] << kRefShift) | (int64_t)nwin_of(P.top_depth[t]);
     }
     Q.max_nwin = std::max(Q.max_nwin, bq.nwin);
   }
+  // one padding entry each: the sweep reads bucket bounds two positions and
+  // first entries one position ahead of time
+  Q.bq.push_back(BQuery{0, kQGround, 0, -1});
+  Q.bq_ptr.push_back(Q.bq_ptr.back());
   // a sweep wavefront writes one slot per query of its task for its group of
   // kWinPerWave windows (groups past a query's column are never read)
   const int32_t groups = (std::max(Q.max_nwin, P.max_btask_nwin) + kWinPerWave - 1) / kWinPerWave;

@@ -51,8 +51,9 @@ constexpr int32_t kGroundCode = INT32_MIN;
 // Device buffers a GEMM operand can live in.
 enum GemmBuf : int32_t { BUF_STORE = 0, BUF_LCC = 1, BUF_X = 2, BUF_T = 3, BUF_BT = 4, BUF_LUC = 5, BUF_COUNT = 6 };
 
-// C[M x N] = alpha * A[M x K] * B[K x N]; all column-major. Column k of A
-// starts at buffer[a_buf] + (gather ? gather_table[aoff_begin + k] : a_off + k * lda).
+// C[M x N] = alpha * A[M x K] * B[K x N]; column-major unless `trans` says
+// otherwise for B or C. Column k of A starts at
+// buffer[a_buf] + (gather ? gather_table[aoff_begin + k] : a_off + k * lda).
 struct GemmProb {
   int64_t a_off, lda, aoff_begin;
   int64_t b_off, ldb;
@@ -60,7 +61,7 @@ struct GemmProb {
   int32_t M, N, K;
   int32_t a_buf, b_buf, c_buf;
   int32_t gather;
-  int32_t pad_;
+  int32_t trans;  // bit 0: B stored row-major (element (k, j) at b_off + k * ldb + j); bit 1: C row-major
   double alpha;
 };
 
@@ -76,7 +77,7 @@ struct Chain {
   int64_t store_base, ld;  // column a+j of the store at store_base + j*ld, ld = roundup64(dp + w)
   int64_t lcc_off, ldl;    // dense L_CC, column-major
   int64_t x_off;           // L_CC^{-1} workspace, same shape as L_CC
-  int64_t bt_off, ldb;     // B_C, column-major |U| x w (ldb = roundup64(nU))
+  int64_t bt_off, ldb;     // B_C, |U| x w row-major (row u at bt_off + u * w); ldb = roundup64(nU) sizes L_{U,C}
   int64_t luc_off;         // dense L_{U,C}, column-major (upload only), ld = ldb
 };
 
@@ -159,24 +160,21 @@ struct FactorPlan {
 
 Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P);
 
-// A query whose lower endpoint is a bottom node.
+// A query whose lower endpoint is a bottom node, or a staging entry.
 struct BQuery {
-  int64_t hiref;   // see kInlineTopRef
-  int64_t out;     // output index
+  int64_t hiref;   // kQSlot: path-stack slot; kQStore: store reference; kQStage: staging offset
+  int32_t kind;    // how the higher endpoint's column is found (kQ*)
   int32_t nwin;    // windows of the lower endpoint's column
-  int32_t pad_;
+  int64_t out;     // output index
 };
-// BQuery::hiref: the higher endpoint's column in the lower endpoint's sweep.
-//   >= 0            path-stack slot (the higher endpoint is in the same subtree)
-//   -1, -2          the lower endpoint's inline top-store entry 0 / 1
-//   kGroundRef      the ground (z = 0)
-//   kStageRef       not a pair: the sweep writes the node's column to the
-//                   staging buffer at element offset `out` (non-ancestor pairs)
-//   other negative  -(store reference) - 3
-constexpr int64_t kGroundRef = INT64_MIN;
-constexpr int64_t kStageRef = INT64_MIN + 1;
-constexpr int64_t kInlineTopRef = -1;
-constexpr int64_t kStoreRefBias = 3;
+// BQuery::kind: the higher endpoint's column in the lower endpoint's sweep
+//   kQSlot   on the path stack (the higher endpoint is in the same subtree)
+//   kQInl0/1 the lower endpoint's inline top-store entry 0 / 1
+//   kQGround the ground (z = 0)
+//   kQStore  another top-store column: hiref = (store offset << 12) | windows
+//   kQStage  not a pair: the sweep writes the node's column to the staging
+//            buffer at element offset hiref (non-ancestor pairs)
+enum BQueryKind : int32_t { kQSlot = 0, kQInl0 = 1, kQInl1 = 2, kQGround = 3, kQStore = 4, kQStage = 5 };
 // The first kWin elements of the top store are zero; loads of windows past a
 // column's depth are pointed there.
 constexpr int64_t kStoreZeroBlock = kWin;
@@ -211,8 +209,9 @@ struct QueryPlan {
   int64_t q = 0;
   // bottom queries bucketed by lower endpoint, in the order of the bottom
   // nodes' processing positions (FactorPlan::bnode)
-  std::vector<int32_t> bq_ptr;     // #bottom positions + 1
-  std::vector<BQuery> bq;          // bucket order; partial of window t at part[t * nbq + j]
+  std::vector<int32_t> bq_ptr;     // #bottom positions + 1, plus one padding entry
+  std::vector<BQuery> bq;          // bucket order, plus one padding entry; partial of window group g at part[g * nbq() + j]
+  int64_t nbq() const { return bq.empty() ? 0 : (int64_t)bq.size() - 1; }
   int32_t max_nwin = 0;
   int64_t nslots = 0;
   // top queries
