@@ -80,11 +80,18 @@ void batch_layout(const DeviceHandle& D, const std::vector<BatchEntry>& E, Batch
     for (int64_t k = 0; k < P.ntop; ++k)
       if (need(i, P.top_chain[k])) items.push_back(GroupItem{i, 0, k});
   });
-  for (int32_t l = 0; l < lmax; ++l)
+  for (int32_t l = 0; l < lmax; ++l) {
     stage(GK_GEMM, [&](int32_t i) {
       const FactorPlan& P = *E[i].F->plan;
       if (l + 1 < (int32_t)P.t2_ptr.size()) gemm_range(i, P.t2_ptr[l], P.t2_ptr[l + 1]);
     });
+    stage(GK_GEMM_NARROW, [&](int32_t i) {
+      const FactorPlan& P = *E[i].F->plan;
+      if (l + 1 < (int32_t)P.t2n_ptr.size())
+        for (int64_t t = P.t2n_ptr[l]; t < P.t2n_ptr[l + 1]; ++t)
+          if (need(i, P.prob_chain[P.ntasks[t].prob])) items.push_back(GroupItem{i, 0, t});
+    });
+  }
   // bottom subtrees: one item list per candidate schedule
   {
     std::vector<GroupItem> nat;
@@ -186,8 +193,10 @@ Status run_sweep_pruned(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipS
   // phase boundaries (events 1 and 2): the first bottom-or-finish step and the first finish step
   int b1 = nst, b2 = nst;
   for (int k = nst - 1; k >= 0; --k) {
-    if (L->stages[k].kind == GK_BOTTOM || L->stages[k].kind >= GK_REDUCE) b1 = k;
-    if (L->stages[k].kind >= GK_REDUCE) b2 = k;
+    const int kd = L->stages[k].kind;
+    const bool finish = kd == GK_REDUCE || kd == GK_TOP_QUERY || kd == GK_ZERO || kd == GK_GENERAL;
+    if (kd == GK_BOTTOM || finish) b1 = k;
+    if (finish) b2 = k;
   }
   if (profile) (void)hipEventRecord(F.ev[0], s);
   for (int k = 0; k <= nst; ++k) {

@@ -193,7 +193,8 @@ Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t
   launches += P.ntop > 0 ? 1 : 0;
   for (size_t l = 0; l + 1 < P.t2_ptr.size(); ++l) {
     HIP_TRY(launch_gemm(F.gemm, P.t2_ptr[l], P.t2_ptr[l + 1] - P.t2_ptr[l], s));
-    ++launches;
+    HIP_TRY(launch_gemm_narrow(F.gemm, P.t2n_ptr[l], P.t2n_ptr[l + 1] - P.t2n_ptr[l], s));
+    launches += 2;
   }
   F.top_launches = launches;
   if (profile) HIP_TRY(hipEventRecord(F.ev[1], s));
@@ -321,6 +322,7 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
   pk.add(P.u_off, &GA.gather);
   pk.add(P.probs, &GA.probs);
   pk.add(P.tasks, &GA.tasks);
+  pk.add(P.ntasks, &GA.ntasks);
   pk.add(P.top_off, &A.top_off);
   pk.add(P.top_depth, &A.top_depth);
   pk.add(P.top_isd, &A.top_isd);

@@ -108,10 +108,10 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // e1 are clamped to a valid column and their B value is zeroed at use, so the
 // loop body has no branches and each load is waited for only right before its
 // MFMAs. Gathered column offsets come through the scalar unit one step ahead.
-template <bool GATHER, bool BT>
-__device__ __forceinline__ void gemm_accumulate(f64x4 (&C)[4][2], const double* __restrict__ A,
+template <bool GATHER, bool BT, int NB = 2>
+__device__ __forceinline__ void gemm_accumulate(f64x4 (&C)[4][NB], const double* __restrict__ A,
                                                 const double* __restrict__ B, const int64_t* __restrict__ gt,
-                                                const GemmProb& pb, const int32_t (&rows)[4], const int32_t (&cols)[2],
+                                                const GemmProb& pb, const int32_t (&rows)[4], const int32_t (&cols)[NB],
                                                 int kk, int32_t e0, int32_t e1) {
   // four separate scalars (an array here would be indexed per lane and
   // placed in scratch memory)
@@ -126,7 +126,7 @@ __device__ __forceinline__ void gemm_accumulate(f64x4 (&C)[4][2], const double* 
     }
     return c;
   };
-  auto load = [&](int32_t e, const Cols& gc, double (&a)[4], double (&b)[2]) {
+  auto load = [&](int32_t e, const Cols& gc, double (&a)[4], double (&b)[NB]) {
     const int32_t ec = min(e + kk, e1 - 1);
     int64_t acol;
     if (GATHER) {
@@ -139,19 +139,19 @@ __device__ __forceinline__ void gemm_accumulate(f64x4 (&C)[4][2], const double* 
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) a[rb] = A[acol + rows[rb]];
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) b[cb] = BT ? B[(int64_t)ec * pb.ldb + cols[cb]] : B[(int64_t)cols[cb] * pb.ldb + ec];
+    for (int cb = 0; cb < NB; ++cb) b[cb] = BT ? B[(int64_t)ec * pb.ldb + cols[cb]] : B[(int64_t)cols[cb] * pb.ldb + ec];
   };
-  auto mma = [&](int32_t e, const double (&a)[4], const double (&b)[2]) {
+  auto mma = [&](int32_t e, const double (&a)[4], const double (&b)[NB]) {
     const bool ok = e + kk < e1;
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
+    for (int cb = 0; cb < NB; ++cb) {
       const double bv = ok ? b[cb] : 0.0;
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb) C[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb], bv, C[rb][cb], 0, 0, 0);
     }
   };
   // two operand buffers, each loaded one step before its MFMAs
-  double a0[4], b0[2], a1[4], b1[2];
+  double a0[4], b0[NB], a1[4], b1[NB];
   load(e0, gathers(e0), a0, b0);
   Cols g1 = gathers(e0 + 4);
   for (int32_t e = e0; e < e1; e += 8) {
@@ -262,6 +262,46 @@ __device__ __forceinline__ void gemm_body(const GemmArgs* Gp, int64_t task, Gemm
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs G, int64_t task0) {
   __shared__ GemmRed red;
   gemm_body(&G, task0 + blockIdx.x, red);
+}
+
+// Narrow chains (width at most 16): one 64 x 16 output tile over the task's
+// whole reduction range, computed by one wavefront with no K split, no LDS
+// and no barrier (four independent tasks per workgroup). Same operand layout
+// and summation order within the wavefront as gemm_accumulate.
+__device__ __forceinline__ void gemm_narrow_body(const GemmArgs* Gp, int64_t task) {
+  const GemmTask* tasks = load_uniform(&Gp->ntasks);
+  const GemmProb* probs = load_uniform(&Gp->probs);
+  const GemmTask tk = tasks[task];
+  const GemmProb pb = probs[tk.prob];
+  const int lane = threadIdx.x & 63;
+  const int kk = lane >> 4, ii = lane & 15;
+  const double* __restrict__ A = load_uniform(&Gp->buf[pb.a_buf]);
+  const double* __restrict__ B = load_uniform(&Gp->buf[pb.b_buf]) + pb.b_off;
+  int32_t rows[4], cols[1];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) rows[rb] = min(tk.row0 + 16 * rb + ii, pb.M - 1);
+  cols[0] = min(tk.col0 + ii, pb.N - 1);
+  const int64_t* __restrict__ gt = load_uniform(&Gp->gather) + pb.aoff_begin;
+  f64x4 C[4][1];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) C[rb][0] = f64x4{0.0, 0.0, 0.0, 0.0};
+  if (tk.k0 < tk.k1) gemm_accumulate<true, true, 1>(C, A, B, gt, pb, rows, cols, kk, tk.k0, tk.k1);
+  double* __restrict__ Cm = load_uniform(&Gp->buf[pb.c_buf]) + pb.c_off;
+  const int32_t gc = tk.col0 + ii;
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int32_t gr = tk.row0 + 16 * rb + 4 * r + kk;
+      if (gr < pb.M && gc < pb.N) Cm[(int64_t)gc * pb.ldc + gr] = pb.alpha * C[rb][0][r];
+    }
+}
+
+__global__ __launch_bounds__(256) void gemm_narrow_kernel(GemmArgs G, int64_t task0, int64_t ntasks) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t i = (int64_t)blockIdx.x * 4 + wave;
+  if (i >= ntasks) return;
+  gemm_narrow_body(&G, task0 + i);
 }
 
 // Inverse of one diagonal block (at most 64 x 64) of a chain's unit-lower
@@ -586,6 +626,15 @@ __global__ __launch_bounds__(256) void grouped_gemm_kernel(const FactorArgs* __r
   }
 }
 
+__global__ __launch_bounds__(256) void grouped_narrow_kernel(const FactorArgs* __restrict__ fa,
+                                                             const GroupItem* __restrict__ items, int64_t nitems) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int64_t b = blockIdx.x; b * 4 < nitems; b += gridDim.x) {
+    const int64_t i = b * 4 + wave;
+    if (i < nitems) gemm_narrow_body(&fa[load_uniform(&items[i].fa)].g, load_uniform(&items[i].local));
+  }
+}
+
 __global__ __launch_bounds__(64) void grouped_inv_base_kernel(const FactorArgs* __restrict__ fa,
                                                               const GroupItem* __restrict__ items, int64_t nitems) {
   __shared__ BaseTile Ls, Xs;
@@ -628,6 +677,12 @@ hipError_t launch_grouped(int kind, const FactorArgs* fa, const GroupItem* items
   const dim3 g((unsigned)std::max<int64_t>(1, std::min(grid, nitems)));
   switch (kind) {
     case GK_GEMM: hipLaunchKernelGGL(grouped_gemm_kernel, g, dim3(256), 0, s, fa, items, nitems); break;
+    case GK_GEMM_NARROW: {
+      // four tasks per workgroup
+      const dim3 gn((unsigned)std::max<int64_t>(1, (std::min(grid, nitems) + 3) / 4));
+      hipLaunchKernelGGL(grouped_narrow_kernel, gn, dim3(256), 0, s, fa, items, nitems);
+      break;
+    }
     case GK_INV_BASE: hipLaunchKernelGGL(grouped_inv_base_kernel, g, dim3(64), 0, s, fa, items, nitems); break;
     case GK_CHAIN_ROWS: hipLaunchKernelGGL(grouped_kernel<GK_CHAIN_ROWS>, g, dim3(256), 0, s, fa, items, nitems); break;
     case GK_BOTTOM:
@@ -639,6 +694,12 @@ hipError_t launch_grouped(int kind, const FactorArgs* fa, const GroupItem* items
     case GK_GENERAL: hipLaunchKernelGGL(grouped_kernel<GK_GENERAL>, g, dim3(256), 0, s, fa, items, nitems); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_narrow(const GemmArgs& g, int64_t task0, int64_t ntasks, hipStream_t s) {
+  if (ntasks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gemm_narrow_kernel, dim3((unsigned)((ntasks + 3) / 4)), dim3(256), 0, s, g, task0, ntasks);
   return hipGetLastError();
 }
 

@@ -20,6 +20,7 @@ struct GemmArgs {
   double* buf[BUF_COUNT];
   const GemmProb* probs;
   const GemmTask* tasks;
+  const GemmTask* ntasks;  // narrow-chain tasks (one wavefront each)
   const int64_t* gather;
 };
 
@@ -83,7 +84,7 @@ struct GroupItem {
 
 enum GroupKind : int {
   GK_GEMM = 0, GK_INV_BASE = 1, GK_CHAIN_ROWS = 2, GK_BOTTOM = 3,
-  GK_REDUCE = 4, GK_TOP_QUERY = 5, GK_ZERO = 6, GK_GENERAL = 7
+  GK_REDUCE = 4, GK_TOP_QUERY = 5, GK_ZERO = 6, GK_GENERAL = 7, GK_GEMM_NARROW = 8
 };
 
 // Items per finish block of each kind (threads or wavefronts per item).
@@ -92,6 +93,7 @@ constexpr int kReduceBlock = 256, kTopQueryBlock = 4, kZeroBlock = 256, kGeneral
 hipError_t launch_grouped(int kind, const FactorArgs* fa, const GroupItem* items, int64_t nitems, int64_t grid,
                           hipStream_t s);
 hipError_t launch_gemm(const GemmArgs& g, int64_t task0, int64_t ntasks, hipStream_t s);
+hipError_t launch_gemm_narrow(const GemmArgs& g, int64_t task0, int64_t ntasks, hipStream_t s);
 hipError_t launch_inv_base(const SweepArgs& a, hipStream_t s);
 hipError_t launch_chain_rows(const SweepArgs& a, int32_t ntop, hipStream_t s);
 hipError_t launch_bottom(const SweepArgs& a, const QueryArgs& q, hipStream_t s);

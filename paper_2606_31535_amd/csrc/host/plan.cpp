@@ -246,6 +246,7 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
   for (const BaseBlock& bb : P.base_blocks) P.f_top_inv += (double)bb.size * bb.size * bb.size / 6.0;
   // per sweep, level by level: Z[0:dp, C] = Z[0:dp, U_C] B_C (rows r need U with depth > r)
   P.t2_ptr.assign(1, (int64_t)P.tasks.size());
+  P.t2n_ptr.assign(1, 0);
   {
     std::vector<std::vector<int32_t>> lev(P.nchain_levels);
     for (int32_t ci = 0; ci < nch; ++ci) lev[P.chains[ci].level].push_back(ci);
@@ -261,13 +262,24 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
         P.probs.push_back(g);
         P.prob_chain.push_back(ci);
         const int32_t* ud = P.u_depth.data() + c.u_begin;
-        add_tiles(pid, g.M, g.N, [&](int32_t r0, int32_t, int32_t& k0, int32_t& k1) {
+        auto krange = [&](int32_t r0, int32_t, int32_t& k0, int32_t& k1) {
           k0 = 0;
           k1 = (int32_t)(std::lower_bound(ud, ud + c.nU, r0, std::greater<int32_t>()) - ud);  // depth > r0
-        });
+        };
+        if (g.N <= kNarrowN) {
+          // narrow chains: one wavefront per 64 x 16 tile over the whole reduction
+          for (int32_t r0 = 0; r0 < g.M; r0 += kTileM) {
+            int32_t k0, k1;
+            krange(r0, 0, k0, k1);
+            P.ntasks.push_back(GemmTask{pid, r0, 0, k0, k1});
+          }
+        } else {
+          add_tiles(pid, g.M, g.N, krange);
+        }
         for (int32_t e = 0; e < c.nU; ++e) P.f_top_gemm += (double)ud[e] * c.w;
       }
       P.t2_ptr.push_back((int64_t)P.tasks.size());
+      P.t2n_ptr.push_back((int64_t)P.ntasks.size());
     }
   }
 

@@ -41,6 +41,7 @@ namespace peers {
 constexpr int kWin = 64;              // depths per window = wavefront lanes
 constexpr int kTileM = 64;            // GEMM output tile rows
 constexpr int kTileN = 32;            // GEMM output tile columns
+constexpr int kNarrowN = 16;          // chain widths handled by the one-wavefront narrow GEMM tiles
 constexpr int kBase = 64;             // base block of the triangular inverse
 constexpr int kBottomMaxHeight = 16;  // path-stack slots (registers) per window
 constexpr int kBottomMaxNodes = 512;
@@ -135,6 +136,8 @@ struct FactorPlan {
   std::vector<int64_t> inv_T_ptr;   // per recursion height h >= 1: tasks of T = L21 X11
   std::vector<int64_t> inv_X_ptr;   // per height: tasks of X21 = -X22 T
   std::vector<int64_t> t2_ptr;      // per chain level: tasks of Z[rows, C] = Z[rows, U] B_C
+  std::vector<GemmTask> ntasks;     // narrow chains (w <= kNarrowN): one 64 x 16 tile per task
+  std::vector<int64_t> t2n_ptr;     // per chain level: its narrow tasks
   int64_t bpre_begin = 0, bpre_end = 0;  // upload: B_C = -L_{U,C} L_CC^{-1}
   int32_t inv_heights = 0;
   // bottom subtrees
