@@ -362,15 +362,17 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
   const int32_t p0 = load_uniform(A.btask_ptr + task), p1 = load_uniform(A.btask_ptr + task + 1);
   if (t0 >= load_uniform(A.btask_nwin + task)) return;
   const int lane = threadIdx.x & 63;
-  constexpr int64_t kRefMask = (int64_t(1) << kRefShift) - 1;
-  // Value of a top column at this lane's depth in window t0 + v. Windows past
-  // the column's depth read the store's leading zero block, so the load is
-  // unconditional.
+  // Values of a top column at this lane's depths in windows t0 .. t0+NW-1.
+  // Store columns are zero-padded to whole groups of NW windows and t0 is a
+  // multiple of NW, so one bound check covers the group; groups past the
+  // column read the store's leading zero block, so the loads are unconditional.
   const double* __restrict__ zs = A.store + lane;
-  auto top_value = [&](int64_t ref, int v) -> double {
-    const int32_t t = t0 + v;
-    const int64_t off = t < (int32_t)(ref & kRefMask) ? (ref >> kRefShift) + (int64_t)t * kWin : 0;
-    return zs[off];
+  auto top_values = [&](int64_t ref, double (&x)[NW]) {
+    const int32_t wb = (int32_t)ref, nw = (int32_t)(ref >> 32);
+    const int32_t wi = t0 < nw ? wb + t0 : 0;
+    const double* __restrict__ pz = zs + (int64_t)wi * kWin;
+#pragma unroll
+    for (int v = 0; v < NW; ++v) x[v] = pz[v * kWin];
   };
   // values of the current root path inside the subtree, by local depth
   // (register-resident; every slot index is wave-uniform)
@@ -397,30 +399,28 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
   // Software pipeline over the subtree's nodes: while node p is computed,
   // the store values of node p+1, the record of node p+1 and the store
   // references of node p+2 are in flight.
-  BNode cur = load_uniform(A.bnode + p0);
-  int64_t r0 = load_uniform(&A.bnode[p0 + 1].tref[0]), r1 = load_uniform(&A.bnode[p0 + 1].tref[1]);
-  int32_t qa = load_uniform(Q.bq_ptr + p0), qb = load_uniform(Q.bq_ptr + p0 + 1);
+  const BNode* rec = A.bnode + p0;      // record of the current node
+  const int32_t* bqp = Q.bq_ptr + p0;   // bucket bounds of the current node
+  BNode cur = load_uniform(rec);
+  int64_t r0 = load_uniform(&rec[1].tref[0]), r1 = load_uniform(&rec[1].tref[1]);
+  int32_t qa = load_uniform(bqp), qb = load_uniform(bqp + 1);
   int64_t qh = load_uniform(&Q.bq[qa].hiref);
   int32_t qk = load_uniform(&Q.bq[qa].kind);
-  double va[NW][2], vb[NW][2];
+  double va[2][NW], vb[2][NW];
+  top_values(cur.tref[0], va[0]);
+  top_values(cur.tref[1], va[1]);
 #pragma unroll
-  for (int v = 0; v < NW; ++v) {
-    va[v][0] = top_value(cur.tref[0], v);
-    va[v][1] = top_value(cur.tref[1], v);
-    vb[v][0] = vb[v][1] = 0.0;
-  }
-  auto step = [&](int32_t p, const double (&u)[NW][2], double (&nn)[NW][2]) {
-#pragma unroll
-    for (int v = 0; v < NW; ++v) {
-      nn[v][0] = top_value(r0, v);
-      nn[v][1] = top_value(r1, v);
-    }
-    const BNode nfull = load_uniform(A.bnode + p + 1);
-    const int64_t s0 = load_uniform(&A.bnode[p + 2].tref[0]), s1 = load_uniform(&A.bnode[p + 2].tref[1]);
-    // bucket of node p is [q0, q1) (read two nodes ahead); request the end of
-    // node p+2's bucket and node p+1's first entry (one padding entry at the end)
+  for (int v = 0; v < NW; ++v) vb[0][v] = vb[1][v] = 0.0;
+  auto step = [&](const double (&u)[2][NW], double (&nn)[2][NW]) {
+    top_values(r0, nn[0]);
+    top_values(r1, nn[1]);
+    const BNode nfull = load_uniform(rec + 1);
+    const int64_t s0 = load_uniform(&rec[2].tref[0]), s1 = load_uniform(&rec[2].tref[1]);
+    // bucket of this node is [q0, q1) (read two nodes ahead); request the end
+    // of the bucket two nodes on and the next node's first entry (one padding
+    // entry each at the end)
     const int32_t q0 = qa, q1 = qb;
-    const int32_t nqc = load_uniform(Q.bq_ptr + p + 2);
+    const int32_t nqc = load_uniform(bqp + 2);
     const int64_t nqh = load_uniform(&Q.bq[q1].hiref);
     const int32_t nqk = load_uniform(&Q.bq[q1].kind);
     // eq 11: entries on the path stack, then entries in the top store
@@ -440,12 +440,11 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
     }
     double at[NW];
 #pragma unroll
-    for (int v = 0; v < NW; ++v) at[v] = fma(cur.tc[1], u[v][1], cur.tc[0] * u[v][0]);
+    for (int v = 0; v < NW; ++v) at[v] = fma(cur.tc[1], u[1][v], cur.tc[0] * u[0][v]);
     for (int32_t e = 0; e < n_top_more; ++e) {
       const BEnt be = load_uniform(A.bent + cur.ent + n_lds_more + e);
       double x[NW];
-#pragma unroll
-      for (int v = 0; v < NW; ++v) x[v] = top_value(be.ref, v);
+      top_values(be.ref, x);
       wait_vector_loads();
 #pragma unroll
       for (int v = 0; v < NW; ++v) at[v] = fma(be.coef, x[v], at[v]);
@@ -481,10 +480,9 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
           for (int v = 0; v < NW; ++v) zh[v] = ps_get(v, (int32_t)h & 15);
         } else if (kind != kQStore) {
 #pragma unroll
-          for (int v = 0; v < NW; ++v) zh[v] = kind == kQInl0 ? u[v][0] : (kind == kQInl1 ? u[v][1] : 0.0);
+          for (int v = 0; v < NW; ++v) zh[v] = kind == kQInl0 ? u[0][v] : (kind == kQInl1 ? u[1][v] : 0.0);
         } else {
-#pragma unroll
-          for (int v = 0; v < NW; ++v) zh[v] = top_value(h, v);
+          top_values(h, zh);
           wait_vector_loads();
         }
         // windows past the node's depth hold zeros on both sides
@@ -506,13 +504,15 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
     qk = nqk;
     qa = q1;
     qb = nqc;
+    ++rec;
+    ++bqp;
     cur = nfull;
     r0 = s0;
     r1 = s1;
   };
   for (int32_t p = p0; p < p1; p += 2) {
-    step(p, va, vb);
-    if (p + 1 < p1) step(p + 1, vb, va);
+    step(va, vb);
+    if (p + 1 < p1) step(vb, va);
   }
   while (jend - jb > kWin) {
     flush(kWin);

@@ -9,6 +9,10 @@ namespace peers {
 
 namespace {
 inline int32_t nwin_of(int32_t depth) { return (depth + kWin - 1) / kWin; }
+// windows of a top column as the sweep reads them: whole groups of kWinPerWave
+inline int32_t nwin_grouped(int32_t depth) {
+  return (nwin_of(depth) + kWinPerWave - 1) / kWinPerWave * kWinPerWave;
+}
 }  // namespace
 
 Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
@@ -95,7 +99,7 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
       P.u_depth.push_back(S.depth[U[e]]);
       P.u_off.push_back(-1);  // filled once every chain has its store base
     }
-    c.ld = (int64_t)nwin_of(c.dp + c.w) * kWin;
+    c.ld = (int64_t)nwin_grouped(c.dp + c.w) * kWin;
     c.store_base = P.store_elems;
     P.store_elems += c.ld * c.w;
     for (int32_t j = 0; j < c.w; ++j) P.top_off[P.top_index[c.a + j]] = c.store_base + (int64_t)j * c.ld;
@@ -293,9 +297,9 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
   }
   auto topref = [&](int32_t k) -> int64_t {
     const int32_t t = P.top_index[k];
-    return (P.top_off[t] << kRefShift) | (int64_t)nwin_of(P.top_depth[t]);
+    return store_ref(P.top_off[t], nwin_grouped(P.top_depth[t]));
   };
-  if ((P.store_elems >> (62 - kRefShift)) != 0) { set_error("plan: store too large for packed references"); return E_INTERNAL; }
+  if (P.store_elems / 64 >= (int64_t)INT32_MAX) { set_error("plan: store too large for 32-bit window references"); return E_INTERNAL; }
   P.btask_ptr.assign(1, 0);
   P.btask_attach_ptr.assign(1, 0);
   int32_t cur = 0, curmaxd = 0;
@@ -527,7 +531,7 @@ Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int
     else {
       const int32_t t = P.top_index[hi];
       bq.kind = kQStore;
-      bq.hiref = (P.top_off[t] << kRefShift) | (int64_t)nwin_of(P.top_depth[t]);
+      bq.hiref = store_ref(P.top_off[t], nwin_grouped(P.top_depth[t]));
     }
     Q.max_nwin = std::max(Q.max_nwin, bq.nwin);
   }

@@ -75,7 +75,7 @@ struct Chain {
   int32_t a, b, w, dp;     // nodes a..b; dp = depth of parent(b) (rows above the chain)
   int32_t level, nU;       // chain-tree depth; |U_C|
   int64_t u_begin;         // into u_off / u_depth (U_C ascending = depth descending)
-  int64_t store_base, ld;  // column a+j of the store at store_base + j*ld, ld = roundup64(dp + w)
+  int64_t store_base, ld;  // column a+j of the store at store_base + j*ld; ld = (dp + w) rounded up to whole window groups
   int64_t lcc_off, ldl;    // dense L_CC, column-major
   int64_t x_off;           // L_CC^{-1} workspace, same shape as L_CC
   int64_t bt_off, ldb;     // B_C, |U| x w row-major (row u at bt_off + u * w); ldb = roundup64(nU) sizes L_{U,C}
@@ -94,7 +94,7 @@ struct BaseBlock {
 struct BNode {
   double isd;                      // D_i^{-1/2}
   double lc[3];                    // -L_ki of the inline path-stack entries
-  int64_t tref[2];                 // inline store entries: (store offset << 12) | windows of column k
+  int64_t tref[2];                 // inline store entries: store_ref of column k (0 when absent)
   double tc[2];                    // their -L_ki
   int32_t slots;                   // bits 4e..4e+3: slot of inline entry e; bits 12..15: own slot
   int32_t depth;
@@ -103,13 +103,16 @@ struct BNode {
 };
 static_assert(sizeof(BNode) == 80, "BNode is read as one 80-byte scalar record");
 
-// An overflow entry -L_ki of a bottom column: ref = path-stack slot, or
-// (store offset << 12) | windows of column k for a top-store entry.
+// An overflow entry -L_ki of a bottom column: ref = path-stack slot, or the
+// store_ref of column k for a top-store entry.
 struct BEnt {
   int64_t ref;
   double coef;
 };
-constexpr int kRefShift = 12;
+// A reference to a top-store column: low 32 bits = index of its first window
+// (element offset / 64), high 32 bits = its number of windows, rounded up to
+// a multiple of kWinPerWave (the column is zero-padded that far).
+inline int64_t store_ref(int64_t elem_off, int32_t nwin) { return ((int64_t)nwin << 32) | (int64_t)(elem_off / 64); }
 
 struct FactorPlan {
   int32_t N = 0;
@@ -165,7 +168,7 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P);
 
 // A query whose lower endpoint is a bottom node, or a staging entry.
 struct BQuery {
-  int64_t hiref;   // kQSlot: path-stack slot; kQStore: store reference; kQStage: staging offset
+  int64_t hiref;   // kQSlot: path-stack slot; kQStore: store_ref; kQStage: staging offset
   int32_t kind;    // how the higher endpoint's column is found (kQ*)
   int32_t nwin;    // windows of the lower endpoint's column
   int64_t out;     // output index
@@ -174,13 +177,13 @@ struct BQuery {
 //   kQSlot   on the path stack (the higher endpoint is in the same subtree)
 //   kQInl0/1 the lower endpoint's inline top-store entry 0 / 1
 //   kQGround the ground (z = 0)
-//   kQStore  another top-store column: hiref = (store offset << 12) | windows
+//   kQStore  another top-store column: hiref = its store_ref
 //   kQStage  not a pair: the sweep writes the node's column to the staging
 //            buffer at element offset hiref (non-ancestor pairs)
 enum BQueryKind : int32_t { kQSlot = 0, kQInl0 = 1, kQInl1 = 2, kQGround = 3, kQStore = 4, kQStage = 5 };
-// The first kWin elements of the top store are zero; loads of windows past a
-// column's depth are pointed there.
-constexpr int64_t kStoreZeroBlock = kWin;
+// The first kWinPerWave windows of the top store are zero; loads of windows
+// past a column's depth are pointed there.
+constexpr int64_t kStoreZeroBlock = (int64_t)kWin * kWinPerWave;
 
 // A pair whose endpoints are not ancestor-related: both columns are read
 // whole after the sweep (top store, or the staging buffer for bottom nodes)
