@@ -352,6 +352,7 @@ __global__ __launch_bounds__(256) void chain_rows_kernel(SweepArgs A) { chain_ro
 // One wavefront sweeps kWinPerWave consecutive windows of one subtree task:
 // lane l holds depth t*64 + l of window t for each of them. The per-node
 // records, address arithmetic and query reductions are shared by the windows.
+template <bool WIDE>
 __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs& Q, int64_t w) {
   constexpr int NW = kWinPerWave;
   // the waves of a workgroup sweep the same subtree for consecutive windows
@@ -366,11 +367,15 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
   // Store columns are zero-padded to whole groups of NW windows and t0 is a
   // multiple of NW, so one bound check covers the group; groups past the
   // column read the store's leading zero block, so the loads are unconditional.
-  const double* __restrict__ zs = A.store + lane;
+  // byte offsets in the store fit 32 bits unless WIDE
+  const char* __restrict__ zsb = (const char*)A.store;
+  const uint32_t lane_off = (uint32_t)lane * 8u;
   auto top_values = [&](int64_t ref, double (&x)[NW]) {
     const int32_t wb = (int32_t)ref, nw = (int32_t)(ref >> 32);
     const int32_t wi = t0 < nw ? wb + t0 : 0;
-    const double* __restrict__ pz = zs + (int64_t)wi * kWin;
+    const double* __restrict__ pz;
+    if (WIDE) pz = (const double*)(zsb + (size_t)wi * (kWin * 8) + lane_off);
+    else pz = (const double*)(zsb + (size_t)((uint32_t)wi * (uint32_t)(kWin * 8) + lane_off));
 #pragma unroll
     for (int v = 0; v < NW; ++v) x[v] = pz[v * kWin];
   };
@@ -428,9 +433,12 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
     double acc[NW];
 #pragma unroll
     for (int v = 0; v < NW; ++v) {
-      double a = cur.lc[0] * ps_get(v, sl & 15);
-      a = fma(cur.lc[1], ps_get(v, (sl >> 4) & 15), a);
-      acc[v] = fma(cur.lc[2], ps_get(v, (sl >> 8) & 15), a);
+      const double a = cur.lc[0] * ps_get(v, sl & 15);
+      acc[v] = fma(cur.lc[1], ps_get(v, (sl >> 4) & 15), a);
+    }
+    if (((sl >> 20) & 3) == 3) {  // a third inline entry (about one node in ten)
+#pragma unroll
+      for (int v = 0; v < NW; ++v) acc[v] = fma(cur.lc[2], ps_get(v, (sl >> 8) & 15), acc[v]);
     }
     const int32_t n_lds_more = cur.n_more & 0xffff, n_top_more = cur.n_more >> 16;
     for (int32_t e = 0; e < n_lds_more; ++e) {
@@ -454,10 +462,11 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
     for (int v = 0; v < NW; ++v) {
       acc[v] += at[v];
       if ((t0 + v) * kWin + lane == cur.depth - 1) acc[v] = cur.isd;
-      ps_set(v, top_slot, acc[v]);
     }
+#pragma unroll
+    for (int v = 0; v < NW; ++v) ps_set(v, top_slot, acc[v]);
     // eq 12 over these windows for the queries whose lower endpoint is this node
-    const int32_t nwin_node = (cur.depth + kWin - 1) / kWin;
+    const int32_t nwin_node = (int32_t)(((uint32_t)cur.depth + (kWin - 1)) / kWin);
     if (t0 < nwin_node) {
       for (int32_t j = q0; j < q1; ++j) {
         // the node's first entry was read during the previous node
@@ -521,8 +530,9 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
   flush(jend - jb);
 }
 
+template <bool WIDE>
 __global__ __launch_bounds__(64 * kBottomWaves) void bottom_kernel(SweepArgs A, QueryArgs Q) {
-  bottom_body(A, Q, blockIdx.x);
+  bottom_body<WIDE>(A, Q, blockIdx.x);
 }
 
 __device__ __forceinline__ void reduce_body(const QueryArgs& Q, int64_t blk) {
@@ -656,7 +666,8 @@ __global__ __launch_bounds__(256) void grouped_kernel(const FactorArgs* __restri
     if constexpr (KIND == GK_CHAIN_ROWS) {
       chain_rows_body(load_struct(&fa[f].a), local);
     } else if constexpr (KIND == GK_BOTTOM) {
-      bottom_body(load_struct(&fa[f].a), load_struct(&fa[f].q), local);
+      if (load_uniform(&fa[f].a.store_wide)) bottom_body<true>(load_struct(&fa[f].a), load_struct(&fa[f].q), local);
+      else bottom_body<false>(load_struct(&fa[f].a), load_struct(&fa[f].q), local);
     } else if constexpr (KIND == GK_REDUCE) {
       reduce_body(load_struct(&fa[f].q), local);
     } else if constexpr (KIND == GK_TOP_QUERY) {
@@ -723,7 +734,10 @@ hipError_t launch_chain_rows(const SweepArgs& a, int32_t ntop, hipStream_t s) {
 
 hipError_t launch_bottom(const SweepArgs& a, const QueryArgs& q, hipStream_t s) {
   if (q.nwork <= 0) return hipSuccess;
-  hipLaunchKernelGGL(bottom_kernel, dim3((unsigned)q.nwork), dim3(64 * kBottomWaves), 0, s, a, q);
+  if (a.store_wide)
+    hipLaunchKernelGGL(bottom_kernel<true>, dim3((unsigned)q.nwork), dim3(64 * kBottomWaves), 0, s, a, q);
+  else
+    hipLaunchKernelGGL(bottom_kernel<false>, dim3((unsigned)q.nwork), dim3(64 * kBottomWaves), 0, s, a, q);
   return hipGetLastError();
 }
 

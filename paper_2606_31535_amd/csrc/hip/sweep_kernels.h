@@ -43,6 +43,7 @@ struct SweepArgs {
   const BNode* bnode;
   const BEnt* bent;
   const double* isd;
+  int32_t store_wide;  // 1: store byte offsets need 64 bits
 };
 
 struct QueryArgs {

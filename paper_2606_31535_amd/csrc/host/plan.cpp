@@ -299,7 +299,8 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
     const int32_t t = P.top_index[k];
     return store_ref(P.top_off[t], nwin_grouped(P.top_depth[t]));
   };
-  if (P.store_elems / 64 >= (int64_t)INT32_MAX) { set_error("plan: store too large for 32-bit window references"); return E_INTERNAL; }
+  // the bottom sweep addresses the store with 32-bit byte offsets when it can
+  P.store_wide = P.store_elems * 8 >= (int64_t)UINT32_MAX;
   P.btask_ptr.assign(1, 0);
   P.btask_attach_ptr.assign(1, 0);
   int32_t cur = 0, curmaxd = 0;
@@ -351,6 +352,7 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
           ++nt;
         }
       }
+      bn.slots |= std::min(nl, 3) << 20;
       if (more_top.size() > 32767 || P.bent.size() + more_lds.size() + more_top.size() > (size_t)INT32_MAX) {
         set_error("plan: bottom column too long for the node record");
         return E_INTERNAL;

@@ -96,7 +96,8 @@ struct BNode {
   double lc[3];                    // -L_ki of the inline path-stack entries
   int64_t tref[2];                 // inline store entries: store_ref of column k (0 when absent)
   double tc[2];                    // their -L_ki
-  int32_t slots;                   // bits 4e..4e+3: slot of inline entry e; bits 12..15: own slot
+  int32_t slots;                   // bits 4e..4e+3: slot of inline entry e; bits 12..15: own slot;
+                                   // bits 20..21: number of inline path-stack entries
   int32_t depth;
   int32_t ent;                     // first overflow entry in bent
   int32_t n_more;                  // overflow path-stack entries (bits 0..15), then store entries (16..31)
@@ -126,6 +127,7 @@ struct FactorPlan {
   std::vector<double> top_isd;      // per top index: D^{-1/2}
   std::vector<int32_t> top_chain;   // per top index: chain
   int64_t store_elems = 0;
+  bool store_wide = false;          // store bytes beyond 32-bit offsets
   std::vector<Chain> chains;
   int32_t nchain_levels = 0;
   std::vector<int64_t> u_off;       // gather table: store offset of each U_C column
