@@ -74,6 +74,8 @@ typedef struct {
   const int32_t* given_order; /* PEERS_ORDER_GIVEN: n-1 original ids (ground excluded), elimination order */
   int32_t threads;            /* host threads for the factorization; 0 = all hardware threads */
   int32_t leaf_size;          /* nested-dissection leaf size; 0 = 64 */
+  int32_t store_offsets_64;   /* 1: the sweep addresses the top store with 64-bit offsets even
+                                 when 32-bit ones suffice (they are used above 4 GB); for tests */
 } peers_graph_opts;
 
 typedef struct {

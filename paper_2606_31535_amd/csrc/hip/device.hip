@@ -332,7 +332,7 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
   pk.add(P.bent, &A.bent);
   pk.add(P.isd, &A.isd);
   A.nbase = (int32_t)P.base_blocks.size();
-  A.store_wide = P.store_wide ? 1 : 0;
+  A.store_wide = (P.store_wide || G.store64) ? 1 : 0;
   F->resident_bytes = pk.total + (uint64_t)std::max<int64_t>(P.bt_elems, 1) * 8;
   F->store_bytes = (uint64_t)(std::max<int64_t>(P.store_elems, kWin) + std::max<int64_t>(P.x_elems, 1) +
                               std::max<int64_t>(P.t_elems, 1)) * 8;

@@ -13,6 +13,7 @@ struct GraphHandle {
   Numeric num;
   peers_graph_stats stats{};
   std::vector<int32_t> eu, ev;  // the input edge list (all-edge queries in input order)
+  bool store64 = false;         // peers_graph_opts::store_offsets_64
 };
 
 Status build_graph(int64_t n, int64_t m, const int32_t* eu, const int32_t* ev, const double* w, int32_t ground,

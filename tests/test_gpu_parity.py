@@ -203,6 +203,17 @@ def test_device_output_and_determinism(dev):
         P.peers_graph_destroy(h)
 
 
+def test_wide_store_addressing_same_bits(dev):
+    # stores beyond 4 GB are addressed with 64-bit offsets; forcing that form on
+    # a small factor must give the same bits as the 32-bit form
+    g = synth.pdn_multilayer(side=48, layers=4, seed=21)
+    R32 = _all_edges(dev, g)
+    R64 = _all_edges(dev, g, store_offsets_64=True)
+    assert np.array_equal(R32.view(np.int64), R64.view(np.int64))
+    Ro = sparse.SparseOracle(g).resistances(g.eu[:200], g.ev[:200])
+    assert _relerr(R64[:200], Ro) <= TOL
+
+
 def test_scaling_by_four_is_bit_exact(dev):
     # Z = D^{-1/2} L^{-1}: scaling every conductance by 4 scales D by 4 and
     # D^{-1/2} by exactly 1/2 (sqrt is correctly rounded), L and the ordering
