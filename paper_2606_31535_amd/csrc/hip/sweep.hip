@@ -382,17 +382,28 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
   // values of the current root path inside the subtree, by local depth
   // (register-resident; every slot index is wave-uniform)
   // one array per window: each stays small enough to live in registers
-  static_assert(NW == 1 || NW == 2, "one or two windows per wavefront");
-  double ps0[kBottomMaxHeight], ps1[kBottomMaxHeight];
+  // (arrays of windows past NW are never touched and compile away)
+  static_assert(NW >= 1 && NW <= 4, "one to four windows per wavefront");
+  double ps0[kBottomMaxHeight], ps1[kBottomMaxHeight], ps2[kBottomMaxHeight], ps3[kBottomMaxHeight];
 #pragma unroll
-  for (int k = 0; k < kBottomMaxHeight; ++k) ps0[k] = ps1[k] = 0.0;
-  auto ps_get = [&](int v, int32_t k) -> double { return v == 0 ? ps0[k] : ps1[k]; };
+  for (int k = 0; k < kBottomMaxHeight; ++k) ps0[k] = ps1[k] = ps2[k] = ps3[k] = 0.0;
+  auto ps_get = [&](int v, int32_t k) -> double {
+    return v == 0 ? ps0[k] : (v == 1 ? ps1[k] : (v == 2 ? ps2[k] : ps3[k]));
+  };
   auto ps_set = [&](int v, int32_t k, double x) {
     if (v == 0) ps0[k] = x;
-    else ps1[k] = x;
+    else if (v == 1) ps1[k] = x;
+    else if (v == 2) ps2[k] = x;
+    else ps3[k] = x;
   };
   // window-group sums of the task's queries: lane j - jb holds query j's,
   // stored 64 at a time into the window-major partial slots
+  // query records by index (the record table is far below 4 GB, so the byte
+  // offset is formed in 32 bits)
+  const char* __restrict__ bqb = (const char*)Q.bq;
+  auto bq_at = [&](int32_t j) -> const BQuery* {
+    return (const BQuery*)(bqb + (uint32_t)j * (uint32_t)sizeof(BQuery));
+  };
   const int32_t grp = t0 / NW;
   const int32_t jend = load_uniform(Q.bq_ptr + p1);
   int32_t jb = load_uniform(Q.bq_ptr + p0);
@@ -409,8 +420,8 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
   BNode cur = load_uniform(rec);
   int64_t r0 = load_uniform(&rec[1].tref[0]), r1 = load_uniform(&rec[1].tref[1]);
   int32_t qa = load_uniform(bqp), qb = load_uniform(bqp + 1);
-  int64_t qh = load_uniform(&Q.bq[qa].hiref);
-  int32_t qk = load_uniform(&Q.bq[qa].kind);
+  int64_t qh = load_uniform(&bq_at(qa)->hiref);
+  int32_t qk = load_uniform(&bq_at(qa)->kind);
   double va[2][NW], vb[2][NW];
   top_values(cur.tref[0], va[0]);
   top_values(cur.tref[1], va[1]);
@@ -426,25 +437,32 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
     // entry each at the end)
     const int32_t q0 = qa, q1 = qb;
     const int32_t nqc = load_uniform(bqp + 2);
-    const int64_t nqh = load_uniform(&Q.bq[q1].hiref);
-    const int32_t nqk = load_uniform(&Q.bq[q1].kind);
-    // eq 11: entries on the path stack, then entries in the top store
+    const BQuery* __restrict__ nqp = bq_at(q1);
+    const int64_t nqh = load_uniform(&nqp->hiref);
+    const int32_t nqk = load_uniform(&nqp->kind);
+    // eq 11: entries on the path stack, then entries in the top store (the
+    // windows' values of one slot are read together: one index setup each)
     const int32_t sl = cur.slots;
-    double acc[NW];
+    double acc[NW], pa[NW], pb[NW];
 #pragma unroll
-    for (int v = 0; v < NW; ++v) {
-      const double a = cur.lc[0] * ps_get(v, sl & 15);
-      acc[v] = fma(cur.lc[1], ps_get(v, (sl >> 4) & 15), a);
-    }
-    if (((sl >> 20) & 3) == 3) {  // a third inline entry (about one node in ten)
+    for (int v = 0; v < NW; ++v) pa[v] = ps_get(v, sl & kSlotMask);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int v = 0; v < NW; ++v) acc[v] = fma(cur.lc[2], ps_get(v, (sl >> 8) & 15), acc[v]);
+    for (int v = 0; v < NW; ++v) pb[v] = ps_get(v, (sl >> kSlotBits) & kSlotMask);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int v = 0; v < NW; ++v) acc[v] = fma(cur.lc[1], pb[v], cur.lc[0] * pa[v]);
+    if (((sl >> kInlineCountShift) & 3) == 3) {  // a third inline entry (about one node in ten)
+#pragma unroll
+      for (int v = 0; v < NW; ++v) pa[v] = ps_get(v, (sl >> (2 * kSlotBits)) & kSlotMask);
+#pragma unroll
+      for (int v = 0; v < NW; ++v) acc[v] = fma(cur.lc[2], pa[v], acc[v]);
     }
     const int32_t n_lds_more = cur.n_more & 0xffff, n_top_more = cur.n_more >> 16;
     for (int32_t e = 0; e < n_lds_more; ++e) {
       const BEnt be = load_uniform(A.bent + cur.ent + e);
 #pragma unroll
-      for (int v = 0; v < NW; ++v) acc[v] = fma(be.coef, ps_get(v, be.ref & 15), acc[v]);
+      for (int v = 0; v < NW; ++v) acc[v] = fma(be.coef, ps_get(v, (int32_t)be.ref & kSlotMask), acc[v]);
     }
     double at[NW];
 #pragma unroll
@@ -457,42 +475,59 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
 #pragma unroll
       for (int v = 0; v < NW; ++v) at[v] = fma(be.coef, x[v], at[v]);
     }
-    const int32_t top_slot = (sl >> 12) & 15;
+    const int32_t top_slot = (sl >> kOwnSlotShift) & kSlotMask;
 #pragma unroll
     for (int v = 0; v < NW; ++v) {
       acc[v] += at[v];
       if ((t0 + v) * kWin + lane == cur.depth - 1) acc[v] = cur.isd;
     }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int v = 0; v < NW; ++v) ps_set(v, top_slot, acc[v]);
+    __builtin_amdgcn_sched_barrier(0);
     // eq 12 over these windows for the queries whose lower endpoint is this node
     const int32_t nwin_node = (int32_t)(((uint32_t)cur.depth + (kWin - 1)) / kWin);
-    if (t0 < nwin_node) {
-      for (int32_t j = q0; j < q1; ++j) {
-        // the node's first entry was read during the previous node
-        int64_t h = qh;
-        int32_t kind = qk;
-        if (j > q0) {
-          h = load_uniform(&Q.bq[j].hiref);
-          kind = load_uniform(&Q.bq[j].kind);
-        }
-        if (kind == kQStage) {
-          // this node's column is one side of a non-ancestor pair
-#pragma unroll
-          for (int v = 0; v < NW; ++v)
-            if (t0 + v < nwin_node) Q.stage[h + (int64_t)(t0 + v) * kWin + lane] = acc[v];
-          continue;
-        }
+    if (t0 < nwin_node && q0 < q1) {
+      // the node's first entry was read during the previous node; the rest
+      // are read one ahead of use
+      int64_t h = qh;
+      int32_t kind = qk;
+      const BQuery* __restrict__ qp = bq_at(q0);
+      int32_t jl = q0 - jb;  // lane of entry j in the query buffer
+      int32_t j = q0;
+      do {
+        // next entry (the table ends with a padding entry)
+        const int64_t h_next = load_uniform(&qp[1].hiref);
+        const int32_t kind_next = load_uniform(&qp[1].kind);
+        // path-stack value first (nine entries in ten on the all-edge
+        // workloads; any slot is in range for the other kinds)
         double zh[NW];
-        if (kind == kQSlot) {
 #pragma unroll
-          for (int v = 0; v < NW; ++v) zh[v] = ps_get(v, (int32_t)h & 15);
-        } else if (kind != kQStore) {
+        for (int v = 0; v < NW; ++v) zh[v] = ps_get(v, (int32_t)h & kSlotMask);
+        // (a bit test rather than a comparison keeps this one branch: the
+        // compiler would otherwise fold it into a search tree over the kinds)
+        static_assert(kQSlot == 0 && kQStage < 8, "query kinds");
+        if ((kind & 7) != 0) {
+          if (kind == kQInl0) {
 #pragma unroll
-          for (int v = 0; v < NW; ++v) zh[v] = kind == kQInl0 ? u[0][v] : (kind == kQInl1 ? u[1][v] : 0.0);
-        } else {
-          top_values(h, zh);
-          wait_vector_loads();
+            for (int v = 0; v < NW; ++v) zh[v] = u[0][v];
+          } else if (kind == kQInl1) {
+#pragma unroll
+            for (int v = 0; v < NW; ++v) zh[v] = u[1][v];
+          } else if (kind == kQStore) {
+            top_values(h, zh);
+            wait_vector_loads();
+          } else {
+            // ground (zero column), or a staging entry: this node's column is
+            // one side of a non-ancestor pair (its sum below is never read)
+            if (kind == kQStage) {
+#pragma unroll
+              for (int v = 0; v < NW; ++v)
+                if (t0 + v < nwin_node) Q.stage[h + (int64_t)(t0 + v) * kWin + lane] = acc[v];
+            }
+#pragma unroll
+            for (int v = 0; v < NW; ++v) zh[v] = 0.0;
+          }
         }
         // windows past the node's depth hold zeros on both sides
         double sacc = 0.0;
@@ -502,12 +537,17 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
           sacc = fma(df, df, sacc);
         }
         const double sq = wave_sum(sacc);
-        while (j - jb >= kWin) {
+        while (jl >= kWin) {
           flush(kWin);
           jb += kWin;
+          jl -= kWin;
         }
-        qbuf = lane == j - jb ? sq : qbuf;
-      }
+        qbuf = lane == jl ? sq : qbuf;
+        h = h_next;
+        kind = kind_next;
+        ++qp;
+        ++jl;
+      } while (++j < q1);
     }
     qh = nqh;
     qk = nqk;

@@ -326,7 +326,7 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
       BNode bn{};
       bn.isd = P.isd[v];
       bn.depth = S.depth[v];
-      bn.slots = P.lslot[v] << 12;
+      bn.slots = P.lslot[v] << kOwnSlotShift;
       int32_t tinl[2] = {-1, -1};
       std::vector<BEnt> more_lds, more_top;
       int32_t nl = 0, nt = 0;
@@ -336,7 +336,7 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
         if (P.small[k]) {
           if (nl < 3) {
             bn.lc[nl] = c;
-            bn.slots |= P.lslot[k] << (4 * nl);
+            bn.slots |= P.lslot[k] << (kSlotBits * nl);
           } else {
             more_lds.push_back(BEnt{P.lslot[k], c});
           }
@@ -352,7 +352,7 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
           ++nt;
         }
       }
-      bn.slots |= std::min(nl, 3) << 20;
+      bn.slots |= std::min(nl, 3) << kInlineCountShift;
       if (more_top.size() > 32767 || P.bent.size() + more_lds.size() + more_top.size() > (size_t)INT32_MAX) {
         set_error("plan: bottom column too long for the node record");
         return E_INTERNAL;
@@ -498,6 +498,15 @@ Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int
       Q.tq_lo.push_back(P.top_index[lo]);
       Q.tq_hi.push_back(hi < 0 ? -1 : P.top_index[hi]);
       Q.tq_out.push_back(k);
+    }
+  }
+  {
+    // the sweep forms record byte offsets in 32 bits (one padding record)
+    int64_t total = 0;
+    for (int32_t i = 0; i < nbn; ++i) total += Q.bq_ptr[i + 1];
+    if ((total + 1) * (int64_t)sizeof(BQuery) > (int64_t)UINT32_MAX) {
+      set_error("query plan: too many queries with a bottom lower endpoint for one plan (split the request)");
+      return E_INVALID_ARG;
     }
   }
   for (int32_t i = 0; i < nbn; ++i) Q.bq_ptr[i + 1] += Q.bq_ptr[i];

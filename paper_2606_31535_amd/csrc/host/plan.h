@@ -43,7 +43,17 @@ constexpr int kTileM = 64;            // GEMM output tile rows
 constexpr int kTileN = 32;            // GEMM output tile columns
 constexpr int kNarrowN = 16;          // chain widths handled by the one-wavefront narrow GEMM tiles
 constexpr int kBase = 64;             // base block of the triangular inverse
-constexpr int kBottomMaxHeight = 16;  // path-stack slots (registers) per window
+// path-stack slots (registers) per window: the stack is indexed with a
+// wave-uniform slot, which stays in registers only up to 16 doubles (the
+// widest register tuple, 32 dwords); a taller stack would spill to scratch
+constexpr int kBottomMaxHeight = 16;
+// BNode::slots packing: slot of inline entry e at bits kSlotBits*e, own slot
+// at kOwnSlotShift, number of inline path-stack entries at kInlineCountShift
+constexpr int kSlotBits = 4;
+constexpr int kSlotMask = (1 << kSlotBits) - 1;
+constexpr int kOwnSlotShift = 3 * kSlotBits;
+constexpr int kInlineCountShift = 20;
+static_assert(kBottomMaxHeight <= kSlotMask + 1, "slots fit their bit fields");
 constexpr int kBottomMaxNodes = 512;
 constexpr int kBottomWaves = 4;       // wavefronts per bottom workgroup
 constexpr int kWinPerWave = 2;        // windows per bottom wavefront (lane l: depths t*64 + l)
@@ -96,8 +106,7 @@ struct BNode {
   double lc[3];                    // -L_ki of the inline path-stack entries
   int64_t tref[2];                 // inline store entries: store_ref of column k (0 when absent)
   double tc[2];                    // their -L_ki
-  int32_t slots;                   // bits 4e..4e+3: slot of inline entry e; bits 12..15: own slot;
-                                   // bits 20..21: number of inline path-stack entries
+  int32_t slots;                   // path-stack slots and inline count (kSlotBits packing)
   int32_t depth;
   int32_t ent;                     // first overflow entry in bent
   int32_t n_more;                  // overflow path-stack entries (bits 0..15), then store entries (16..31)
