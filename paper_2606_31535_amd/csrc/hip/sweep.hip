@@ -128,10 +128,11 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // Reduction loop of gemm_kernel for indices [e0, e1) in steps of 4 (one
 // v_mfma_f64_16x16x4f64 k-group). Every load is unconditional: indices past
-// e1 are clamped to a valid column and their B value is zeroed at use, so the
-// loop body has no branches and each load is waited for only right before its
-// MFMAs. Gathered column offsets come through the scalar unit one step ahead.
-template <bool GATHER, bool BT, int NB = 2>
+// e1 are clamped to a valid column and their B value is zeroed at use, so
+// each load is waited for only right before its MFMAs. Gathered column
+// offsets come through the scalar unit one step ahead. Operands are kept
+// DEPTH - 1 steps ahead (three buffers measured best for both tile forms).
+template <bool GATHER, bool BT, int NB = 2, int DEPTH = 3>
 __device__ __forceinline__ void gemm_accumulate(f64x4 (&C)[4][NB], const double* __restrict__ A,
                                                 const double* __restrict__ B, const int64_t* __restrict__ gt,
                                                 const GemmProb& pb, const int32_t (&rows)[4], const int32_t (&cols)[NB],
@@ -173,17 +174,20 @@ __device__ __forceinline__ void gemm_accumulate(f64x4 (&C)[4][NB], const double*
       for (int rb = 0; rb < 4; ++rb) C[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb], bv, C[rb][cb], 0, 0, 0);
     }
   };
-  // two operand buffers, each loaded one step before its MFMAs
-  double a0[4], b0[NB], a1[4], b1[NB];
-  load(e0, gathers(e0), a0, b0);
-  Cols g1 = gathers(e0 + 4);
-  for (int32_t e = e0; e < e1; e += 8) {
-    load(e + 4, g1, a1, b1);
-    const Cols g0 = gathers(e + 8);
-    mma(e, a0, b0);
-    load(e + 8, g0, a0, b0);
-    g1 = gathers(e + 12);
-    mma(e + 4, a1, b1);
+  // DEPTH operand buffers: step i's operands are requested DEPTH - 1 steps
+  // before its MFMAs (steps wholly past e1 are skipped)
+  double a[DEPTH][4], b[DEPTH][NB];
+#pragma unroll
+  for (int i = 0; i < DEPTH - 1; ++i) load(e0 + 4 * i, gathers(e0 + 4 * i), a[i], b[i]);
+  Cols gn = gathers(e0 + 4 * (DEPTH - 1));
+  for (int32_t e = e0; e < e1; e += 4 * DEPTH) {
+#pragma unroll
+    for (int i = 0; i < DEPTH; ++i) {
+      const int nb = (i + DEPTH - 1) % DEPTH;
+      load(e + 4 * (i + DEPTH - 1), gn, a[nb], b[nb]);
+      gn = gathers(e + 4 * (i + DEPTH));
+      if (i == 0 || e + 4 * i < e1) mma(e + 4 * i, a[i], b[i]);
+    }
   }
 }
 
@@ -282,9 +286,23 @@ __device__ __forceinline__ void gemm_body(const GemmArgs* Gp, int64_t task, Gemm
   }
 }
 
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs G, int64_t task0) {
+// Workgroups go to the device's XCDs round-robin (block b to XCD b % kXcds),
+// and each XCD has its own L2. The tile tasks of a problem are listed row
+// tile by row tile, so neighbouring tasks share operand slabs: runs of kXcdRun
+// consecutive tasks are given to one XCD (the grid is padded to whole rounds
+// of runs; padding blocks exit at once).
+constexpr int64_t kXcds = 8, kXcdRun = 32;
+__device__ __forceinline__ int64_t xcd_task(int64_t b) {
+  const int64_t x = b % kXcds, slot = b / kXcds;
+  return (slot / kXcdRun) * (kXcds * kXcdRun) + x * kXcdRun + slot % kXcdRun;
+}
+inline int64_t xcd_grid(int64_t n) { return (n + kXcds * kXcdRun - 1) / (kXcds * kXcdRun) * (kXcds * kXcdRun); }
+
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs G, int64_t task0, int64_t ntasks) {
   __shared__ GemmRed red;
-  gemm_body(&G, task0 + blockIdx.x, red);
+  const int64_t t = xcd_task(blockIdx.x);
+  if (t >= ntasks) return;
+  gemm_body(&G, task0 + t, red);
 }
 
 // Narrow chains (width at most 16): one 64 x 16 output tile over the task's
@@ -308,7 +326,7 @@ __device__ __forceinline__ void gemm_narrow_body(const GemmArgs* Gp, int64_t tas
   f64x4 C[4][1];
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb) C[rb][0] = f64x4{0.0, 0.0, 0.0, 0.0};
-  if (tk.k0 < tk.k1) gemm_accumulate<true, true, 1>(C, A, B, gt, pb, rows, cols, kk, tk.k0, tk.k1);
+  if (tk.k0 < tk.k1) gemm_accumulate<true, true, 1, 3>(C, A, B, gt, pb, rows, cols, kk, tk.k0, tk.k1);
   double* __restrict__ Cm = load_uniform(&Gp->buf[pb.c_buf]) + pb.c_off;
   const int32_t gc = tk.col0 + ii;
 #pragma unroll
@@ -779,7 +797,7 @@ hipError_t launch_gemm_narrow(const GemmArgs& g, int64_t task0, int64_t ntasks, 
 
 hipError_t launch_gemm(const GemmArgs& g, int64_t task0, int64_t ntasks, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gemm_kernel, dim3((unsigned)ntasks), dim3(256), 0, s, g, task0);
+  hipLaunchKernelGGL(gemm_kernel, dim3((unsigned)xcd_grid(ntasks)), dim3(256), 0, s, g, task0, ntasks);
   return hipGetLastError();
 }
 
