@@ -454,25 +454,27 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
   };
 
   // Software pipeline over the subtree's nodes: while node p is computed,
-  // the store values of node p+1, the record of node p+1 and the store
-  // references of node p+2 are in flight.
+  // the store values of nodes p+1 and p+2, the record of node p+1 and the
+  // store references of node p+3 are in flight.
   const BNode* rec = A.bnode + p0;      // record of the current node
   const int32_t* bqp = Q.bq_ptr + p0;   // bucket bounds of the current node
   BNode cur = load_uniform(rec);
-  int64_t r0 = load_uniform(&rec[1].tref[0]), r1 = load_uniform(&rec[1].tref[1]);
+  int64_t r0 = load_uniform(&rec[2].tref[0]), r1 = load_uniform(&rec[2].tref[1]);
   int32_t qa = load_uniform(bqp), qb = load_uniform(bqp + 1);
   int64_t qh = load_uniform(&bq_at(qa)->hiref);
   int32_t qk = load_uniform(&bq_at(qa)->kind);
-  double va[2][NW], vb[2][NW];
+  double va[2][NW], vb[2][NW], vc[2][NW];
   top_values(cur.tref[0], va[0]);
   top_values(cur.tref[1], va[1]);
+  top_values(load_uniform(&rec[1].tref[0]), vb[0]);
+  top_values(load_uniform(&rec[1].tref[1]), vb[1]);
 #pragma unroll
-  for (int v = 0; v < NW; ++v) vb[0][v] = vb[1][v] = 0.0;
+  for (int v = 0; v < NW; ++v) vc[0][v] = vc[1][v] = 0.0;
   auto step = [&](const double (&u)[2][NW], double (&nn)[2][NW]) {
     top_values(r0, nn[0]);
     top_values(r1, nn[1]);
     const BNode nfull = load_uniform(rec + 1);
-    const int64_t s0 = load_uniform(&rec[2].tref[0]), s1 = load_uniform(&rec[2].tref[1]);
+    const int64_t s0 = load_uniform(&rec[3].tref[0]), s1 = load_uniform(&rec[3].tref[1]);
     // bucket of this node is [q0, q1) (read two nodes ahead); request the end
     // of the bucket two nodes on and the next node's first entry (one padding
     // entry each at the end)
@@ -600,9 +602,15 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
     r0 = s0;
     r1 = s1;
   };
-  for (int32_t p = p0; p < p1; p += 2) {
-    step(va, vb);
-    if (p + 1 < p1) step(vb, va);
+  // (every path back to the loop head has consumed all three buffers, so no
+  // load is waited for there)
+  for (int32_t p = p0;; p += 3) {
+    step(va, vc);
+    if (p + 1 >= p1) break;
+    step(vb, va);
+    if (p + 2 >= p1) break;
+    step(vc, vb);
+    if (p + 3 >= p1) break;
   }
   while (jend - jb > kWin) {
     flush(kWin);

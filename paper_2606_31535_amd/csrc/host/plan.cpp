@@ -370,7 +370,8 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
     cur += sz;
   }
   close_task();
-  // the sweep reads the records of the next two positions ahead of time
+  // the sweep reads the records of the next three positions ahead of time
+  P.bnode.push_back(BNode{});
   P.bnode.push_back(BNode{});
   P.bnode.push_back(BNode{});
   P.bent.push_back(BEnt{0, 0.0});
