@@ -439,12 +439,12 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
   };
   // window-group sums of the task's queries: lane j - jb holds query j's,
   // stored 64 at a time into the window-major partial slots
-  // query records by index (the record table is far below 4 GB, so the byte
-  // offset is formed in 32 bits)
+  // query records by byte offset (the record table is below 4 GB, which the
+  // planner checks, so offsets are carried in 32 bits)
   const char* __restrict__ bqb = (const char*)Q.bq;
-  auto bq_at = [&](int32_t j) -> const BQuery* {
-    return (const BQuery*)(bqb + (uint32_t)j * (uint32_t)sizeof(BQuery));
-  };
+  constexpr uint32_t kBQ = sizeof(BQuery);
+  auto bq_at = [&](uint32_t off) -> const BQuery* { return (const BQuery*)(bqb + off); };
+  const int32_t t0d = t0 * kWin;  // first depth of the wave's windows
   const int32_t grp = t0 / NW;
   const int32_t jend = load_uniform(Q.bq_ptr + p1);
   int32_t jb = load_uniform(Q.bq_ptr + p0);
@@ -461,8 +461,9 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
   BNode cur = load_uniform(rec);
   int64_t r0 = load_uniform(&rec[2].tref[0]), r1 = load_uniform(&rec[2].tref[1]);
   int32_t qa = load_uniform(bqp), qb = load_uniform(bqp + 1);
-  int64_t qh = load_uniform(&bq_at(qa)->hiref);
-  int32_t qk = load_uniform(&bq_at(qa)->kind);
+  uint32_t qao = (uint32_t)qa * kBQ;
+  int64_t qh = load_uniform(&bq_at(qao)->hiref);
+  int32_t qk = load_uniform(&bq_at(qao)->kind);
   double va[2][NW], vb[2][NW], vc[2][NW];
   top_values(cur.tref[0], va[0]);
   top_values(cur.tref[1], va[1]);
@@ -479,10 +480,10 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
     // of the bucket two nodes on and the next node's first entry (one padding
     // entry each at the end)
     const int32_t q0 = qa, q1 = qb;
+    const uint32_t q0o = qao, q1o = (uint32_t)q1 * kBQ;
     const int32_t nqc = load_uniform(bqp + 2);
-    const BQuery* __restrict__ nqp = bq_at(q1);
-    const int64_t nqh = load_uniform(&nqp->hiref);
-    const int32_t nqk = load_uniform(&nqp->kind);
+    const int64_t nqh = load_uniform(&bq_at(q1o)->hiref);
+    const int32_t nqk = load_uniform(&bq_at(q1o)->kind);
     // eq 11: entries on the path stack, then entries in the top store (the
     // windows' values of one slot are read together: one index setup each)
     const int32_t sl = cur.slots;
@@ -522,31 +523,35 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
 #pragma unroll
     for (int v = 0; v < NW; ++v) {
       acc[v] += at[v];
-      if ((t0 + v) * kWin + lane == cur.depth - 1) acc[v] = cur.isd;
+      if (t0d + v * kWin + lane + 1 == cur.depth) acc[v] = cur.isd;
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int v = 0; v < NW; ++v) ps_set(v, top_slot, acc[v]);
     __builtin_amdgcn_sched_barrier(0);
     // eq 12 over these windows for the queries whose lower endpoint is this node
-    const int32_t nwin_node = (int32_t)(((uint32_t)cur.depth + (kWin - 1)) / kWin);
-    if (t0 < nwin_node && q0 < q1) {
+    // (the wave's windows hold some of the node's depths iff t0d < depth;
+    // both conditions as one sign test, which stays a single scalar branch)
+    if (((q1 - q0 - 1) | (cur.depth - 1 - t0d)) >= 0) {
       // the node's first entry was read during the previous node; the rest
       // are read one ahead of use
       int64_t h = qh;
       int32_t kind = qk;
-      const BQuery* __restrict__ qp = bq_at(q0);
+      uint32_t qo = q0o;
       int32_t jl = q0 - jb;  // lane of entry j in the query buffer
       int32_t j = q0;
       do {
-        // next entry (the table ends with a padding entry)
-        const int64_t h_next = load_uniform(&qp[1].hiref);
-        const int32_t kind_next = load_uniform(&qp[1].kind);
         // path-stack value first (nine entries in ten on the all-edge
         // workloads; any slot is in range for the other kinds)
         double zh[NW];
 #pragma unroll
         for (int v = 0; v < NW; ++v) zh[v] = ps_get(v, (int32_t)h & kSlotMask);
+        // next entry (the table ends with a padding entry), requested only
+        // after this entry's fields are in use: scalar loads are waited for
+        // all together, so the request must not precede that wait
+        __builtin_amdgcn_sched_barrier(0);
+        const int64_t h_next = load_uniform(&bq_at(qo + kBQ)->hiref);
+        const int32_t kind_next = load_uniform(&bq_at(qo + kBQ)->kind);
         // (a bit test rather than a comparison keeps this one branch: the
         // compiler would otherwise fold it into a search tree over the kinds)
         static_assert(kQSlot == 0 && kQStage < 8, "query kinds");
@@ -562,11 +567,12 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
             wait_vector_loads();
           } else {
             // ground (zero column), or a staging entry: this node's column is
-            // one side of a non-ancestor pair (its sum below is never read)
+            // one side of a non-ancestor pair (its sum below is never read);
+            // staged columns span whole window groups, so every window of the
+            // group is written (zeros past the node's depth)
             if (kind == kQStage) {
 #pragma unroll
-              for (int v = 0; v < NW; ++v)
-                if (t0 + v < nwin_node) Q.stage[h + (int64_t)(t0 + v) * kWin + lane] = acc[v];
+              for (int v = 0; v < NW; ++v) Q.stage[h + (int64_t)(t0 + v) * kWin + lane] = acc[v];
             }
 #pragma unroll
             for (int v = 0; v < NW; ++v) zh[v] = 0.0;
@@ -588,13 +594,14 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
         qbuf = set_lane(qbuf, jl, sq);
         h = h_next;
         kind = kind_next;
-        ++qp;
+        qo += kBQ;
         ++jl;
       } while (++j < q1);
     }
     qh = nqh;
     qk = nqk;
     qa = q1;
+    qao = q1o;
     qb = nqc;
     ++rec;
     ++bqp;

@@ -461,7 +461,9 @@ Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int
     }
     if (stage_of[x] < 0) {
       stage_of[x] = Q.stage_elems;
-      Q.stage_elems += (int64_t)nwin_of(depth[x]) * kWin;
+      // whole groups of kWinPerWave windows: the sweep writes its window
+      // group unconditionally (zeros past the column's depth)
+      Q.stage_elems += (int64_t)nwin_grouped(depth[x]) * kWin;
       Q.bq_ptr[pos[x] + 1]++;  // one staging entry at the node
     }
     off = stage_of[x];
