@@ -428,6 +428,20 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
   double ps0[kBottomMaxHeight], ps1[kBottomMaxHeight], ps2[kBottomMaxHeight], ps3[kBottomMaxHeight];
 #pragma unroll
   for (int k = 0; k < kBottomMaxHeight; ++k) ps0[k] = ps1[k] = ps2[k] = ps3[k] = 0.0;
+  // slot index of a slot code (codes are even, which lets the register
+  // offset be taken from the code as it is)
+  auto slot_of = [](int32_t code) -> int32_t {
+    __builtin_assume((code & 1) == 0);
+    return code >> 1;
+  };
+  // the slot code in bits [at, at + kSlotBits) of x: one s_bfe_u32 (written
+  // out, since the compiler would otherwise rewrite the extraction into a
+  // shift and a mask)
+  auto code_at = [](int32_t x, auto at) -> int32_t {
+    int32_t r;
+    asm("s_bfe_u32 %0, %1, %2" : "=s"(r) : "s"(x), "i"(decltype(at)::value | (kSlotBits << 16)));
+    return r;
+  };
   auto ps_get = [&](int v, int32_t k) -> double {
     return v == 0 ? ps0[k] : (v == 1 ? ps1[k] : (v == 2 ? ps2[k] : ps3[k]));
   };
@@ -456,8 +470,15 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
   // Software pipeline over the subtree's nodes: while node p is computed,
   // the store values of nodes p+1 and p+2, the record of node p+1 and the
   // store references of node p+3 are in flight.
-  const BNode* rec = A.bnode + p0;      // record of the current node
-  const int32_t* bqp = Q.bq_ptr + p0;   // bucket bounds of the current node
+  // records and bucket bounds of the task's nodes, addressed by 32-bit byte
+  // offsets from the task's first node (a task has at most kBottomMaxNodes)
+  const char* __restrict__ recb = (const char*)(A.bnode + p0);
+  const char* __restrict__ bqpb = (const char*)(Q.bq_ptr + p0);
+  uint32_t ro = 0, bo = 0;  // offsets of the current node's record and bounds
+  auto rec_at = [&](int k) -> const BNode* { return (const BNode*)(recb + ro) + k; };
+  auto bqp_at = [&](int k) -> const int32_t* { return (const int32_t*)(bqpb + bo) + k; };
+  const BNode* rec = rec_at(0);
+  const int32_t* bqp = bqp_at(0);
   BNode cur = load_uniform(rec);
   int64_t r0 = load_uniform(&rec[2].tref[0]), r1 = load_uniform(&rec[2].tref[1]);
   int32_t qa = load_uniform(bqp), qb = load_uniform(bqp + 1);
@@ -474,14 +495,14 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
   auto step = [&](const double (&u)[2][NW], double (&nn)[2][NW]) {
     top_values(r0, nn[0]);
     top_values(r1, nn[1]);
-    const BNode nfull = load_uniform(rec + 1);
-    const int64_t s0 = load_uniform(&rec[3].tref[0]), s1 = load_uniform(&rec[3].tref[1]);
+    const BNode nfull = load_uniform(rec_at(1));
+    const int64_t s0 = load_uniform(&rec_at(3)->tref[0]), s1 = load_uniform(&rec_at(3)->tref[1]);
     // bucket of this node is [q0, q1) (read two nodes ahead); request the end
     // of the bucket two nodes on and the next node's first entry (one padding
     // entry each at the end)
     const int32_t q0 = qa, q1 = qb;
     const uint32_t q0o = qao, q1o = (uint32_t)q1 * kBQ;
-    const int32_t nqc = load_uniform(bqp + 2);
+    const int32_t nqc = load_uniform(bqp_at(2));
     const int64_t nqh = load_uniform(&bq_at(q1o)->hiref);
     const int32_t nqk = load_uniform(&bq_at(q1o)->kind);
     // eq 11: entries on the path stack, then entries in the top store (the
@@ -489,16 +510,16 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
     const int32_t sl = cur.slots;
     double acc[NW], pa[NW], pb[NW];
 #pragma unroll
-    for (int v = 0; v < NW; ++v) pa[v] = ps_get(v, sl & kSlotMask);
+    for (int v = 0; v < NW; ++v) pa[v] = ps_get(v, slot_of(sl & kSlotMask));
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int v = 0; v < NW; ++v) pb[v] = ps_get(v, (sl >> kSlotBits) & kSlotMask);
+    for (int v = 0; v < NW; ++v) pb[v] = ps_get(v, slot_of(code_at(sl, std::integral_constant<int, kSlotBits>())));
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int v = 0; v < NW; ++v) acc[v] = fma(cur.lc[1], pb[v], cur.lc[0] * pa[v]);
     if (((sl >> kInlineCountShift) & 3) == 3) {  // a third inline entry (about one node in ten)
 #pragma unroll
-      for (int v = 0; v < NW; ++v) pa[v] = ps_get(v, (sl >> (2 * kSlotBits)) & kSlotMask);
+      for (int v = 0; v < NW; ++v) pa[v] = ps_get(v, slot_of(code_at(sl, std::integral_constant<int, 2 * kSlotBits>())));
 #pragma unroll
       for (int v = 0; v < NW; ++v) acc[v] = fma(cur.lc[2], pa[v], acc[v]);
     }
@@ -506,7 +527,7 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
     for (int32_t e = 0; e < n_lds_more; ++e) {
       const BEnt be = load_uniform(A.bent + cur.ent + e);
 #pragma unroll
-      for (int v = 0; v < NW; ++v) acc[v] = fma(be.coef, ps_get(v, (int32_t)be.ref & kSlotMask), acc[v]);
+      for (int v = 0; v < NW; ++v) acc[v] = fma(be.coef, ps_get(v, slot_of((int32_t)be.ref & kSlotMask)), acc[v]);
     }
     double at[NW];
 #pragma unroll
@@ -519,7 +540,7 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
 #pragma unroll
       for (int v = 0; v < NW; ++v) at[v] = fma(be.coef, x[v], at[v]);
     }
-    const int32_t top_slot = (sl >> kOwnSlotShift) & kSlotMask;
+    const int32_t top_slot = slot_of(code_at(sl, std::integral_constant<int, kOwnSlotShift>()));
 #pragma unroll
     for (int v = 0; v < NW; ++v) {
       acc[v] += at[v];
@@ -545,7 +566,7 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
         // workloads; any slot is in range for the other kinds)
         double zh[NW];
 #pragma unroll
-        for (int v = 0; v < NW; ++v) zh[v] = ps_get(v, (int32_t)h & kSlotMask);
+        for (int v = 0; v < NW; ++v) zh[v] = ps_get(v, slot_of((int32_t)h & kSlotMask));
         // next entry (the table ends with a padding entry), requested only
         // after this entry's fields are in use: scalar loads are waited for
         // all together, so the request must not precede that wait
@@ -603,8 +624,8 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
     qa = q1;
     qao = q1o;
     qb = nqc;
-    ++rec;
-    ++bqp;
+    ro += (uint32_t)sizeof(BNode);
+    bo += (uint32_t)sizeof(int32_t);
     cur = nfull;
     r0 = s0;
     r1 = s1;

@@ -326,7 +326,7 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
       BNode bn{};
       bn.isd = P.isd[v];
       bn.depth = S.depth[v];
-      bn.slots = P.lslot[v] << kOwnSlotShift;
+      bn.slots = slot_code(P.lslot[v]) << kOwnSlotShift;
       int32_t tinl[2] = {-1, -1};
       std::vector<BEnt> more_lds, more_top;
       int32_t nl = 0, nt = 0;
@@ -336,9 +336,9 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
         if (P.small[k]) {
           if (nl < 3) {
             bn.lc[nl] = c;
-            bn.slots |= P.lslot[k] << (kSlotBits * nl);
+            bn.slots |= slot_code(P.lslot[k]) << (kSlotBits * nl);
           } else {
-            more_lds.push_back(BEnt{P.lslot[k], c});
+            more_lds.push_back(BEnt{slot_code(P.lslot[k]), c});
           }
           ++nl;
         } else {
@@ -539,7 +539,7 @@ Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int
     if (hi < 0) bq.kind = kQGround;
     else if (P.small[hi]) {
       bq.kind = kQSlot;
-      bq.hiref = P.lslot[hi];
+      bq.hiref = slot_code(P.lslot[hi]);
     } else if (P.bnode_tinl[2 * ps] == hi) bq.kind = kQInl0;
     else if (P.bnode_tinl[2 * ps + 1] == hi) bq.kind = kQInl1;
     else {

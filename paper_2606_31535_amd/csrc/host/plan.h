@@ -47,13 +47,18 @@ constexpr int kBase = 64;             // base block of the triangular inverse
 // wave-uniform slot, which stays in registers only up to 16 doubles (the
 // widest register tuple, 32 dwords); a taller stack would spill to scratch
 constexpr int kBottomMaxHeight = 16;
-// BNode::slots packing: slot of inline entry e at bits kSlotBits*e, own slot
+// Path-stack slots are stored as slot codes, twice the slot index (the
+// register offset of the slot's double), so that the sweep gets a register
+// offset from a record with one bit-field extraction.
+// BNode::slots packing: code of inline entry e at bits kSlotBits*e, own code
 // at kOwnSlotShift, number of inline path-stack entries at kInlineCountShift
-constexpr int kSlotBits = 4;
+constexpr int kSlotBits = 5;
 constexpr int kSlotMask = (1 << kSlotBits) - 1;
 constexpr int kOwnSlotShift = 3 * kSlotBits;
 constexpr int kInlineCountShift = 20;
-static_assert(kBottomMaxHeight <= kSlotMask + 1, "slots fit their bit fields");
+static_assert(2 * (kBottomMaxHeight - 1) <= kSlotMask && kOwnSlotShift + kSlotBits <= kInlineCountShift,
+              "slot codes fit their bit fields");
+inline int32_t slot_code(int32_t slot) { return 2 * slot; }
 constexpr int kBottomMaxNodes = 512;
 constexpr int kBottomWaves = 4;       // wavefronts per bottom workgroup
 constexpr int kWinPerWave = 2;        // windows per bottom wavefront (lane l: depths t*64 + l)
@@ -106,7 +111,7 @@ struct BNode {
   double lc[3];                    // -L_ki of the inline path-stack entries
   int64_t tref[2];                 // inline store entries: store_ref of column k (0 when absent)
   double tc[2];                    // their -L_ki
-  int32_t slots;                   // path-stack slots and inline count (kSlotBits packing)
+  int32_t slots;                   // path-stack slot codes and inline count (kSlotBits packing)
   int32_t depth;
   int32_t ent;                     // first overflow entry in bent
   int32_t n_more;                  // overflow path-stack entries (bits 0..15), then store entries (16..31)
