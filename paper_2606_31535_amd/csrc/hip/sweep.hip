@@ -542,9 +542,15 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
     }
     const int32_t top_slot = slot_of(code_at(sl, std::integral_constant<int, kOwnSlotShift>()));
 #pragma unroll
-    for (int v = 0; v < NW; ++v) {
-      acc[v] += at[v];
-      if (t0d + v * kWin + lane + 1 == cur.depth) acc[v] = cur.isd;
+    for (int v = 0; v < NW; ++v) acc[v] += at[v];
+    // the diagonal entry D^{-1/2} sits at depth - 1, in one window group of
+    // the column only: the other waves skip the lane test
+    const uint32_t dl = (uint32_t)(cur.depth - 1 - t0d);
+    if (dl < (uint32_t)(NW * kWin)) {
+      __builtin_amdgcn_sched_barrier(0);  // keeps this a branch (not selects)
+#pragma unroll
+      for (int v = 0; v < NW; ++v)
+        if (v * kWin + lane == (int)dl) acc[v] = cur.isd;
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
