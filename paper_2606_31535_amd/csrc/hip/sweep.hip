@@ -393,8 +393,12 @@ __global__ __launch_bounds__(256) void chain_rows_kernel(SweepArgs A) { chain_ro
 // One wavefront sweeps kWinPerWave consecutive windows of one subtree task:
 // lane l holds depth t*64 + l of window t for each of them. The per-node
 // records, address arithmetic and query reductions are shared by the windows.
+// Per-wave LDS blocks of the bottom sweep's query sums (33 KB per workgroup).
+constexpr int kQBlock = 16, kQRowPad = kWin + 1;
+typedef double BottomLds[kBottomWaves][kQBlock][kQRowPad];
+
 template <bool WIDE>
-__device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs& Q, int64_t w) {
+__device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs& Q, int64_t w, BottomLds& lds) {
   constexpr int NW = kWinPerWave;
   // the waves of a workgroup sweep the same subtree for consecutive windows
   // and share its records through the scalar cache
@@ -451,8 +455,6 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
     else if (v == 2) ps2[k] = x;
     else ps3[k] = x;
   };
-  // window-group sums of the task's queries: lane j - jb holds query j's,
-  // stored 64 at a time into the window-major partial slots
   // query records by byte offset (the record table is below 4 GB, which the
   // planner checks, so offsets are carried in 32 bits)
   const char* __restrict__ bqb = (const char*)Q.bq;
@@ -462,9 +464,24 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
   const int32_t grp = t0 / NW;
   const int32_t jend = load_uniform(Q.bq_ptr + p1);
   int32_t jb = load_uniform(Q.bq_ptr + p0);
-  double qbuf = 0.0;
+  // Per-lane values of the task's entries are summed over the lanes in
+  // blocks of kQBlock entries through LDS: entry jb + c's 64 values go to row
+  // c of the wave's block (rows padded to 65 doubles so that the transposed
+  // reads below hit distinct banks); at the end of a block lane l adds up
+  // the 16 values of row l/4 starting at 16 (l % 4), in a fixed tree, and
+  // two butterflies inside each group of four lanes complete the row sums,
+  // which are stored into the window-major partial slots.
+  double (&qrow)[kQBlock][kQRowPad] = lds[wave];
   auto flush = [&](int32_t count) {
-    if (lane < count) Q.part[(int64_t)grp * Q.nbq + jb + lane] = qbuf;
+    const int e = lane >> 2, part = lane & 3;
+    const double* __restrict__ src = &qrow[e][16 * part];
+    double t4[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) t4[i] = (src[4 * i] + src[4 * i + 1]) + (src[4 * i + 2] + src[4 * i + 3]);
+    double t = (t4[0] + t4[1]) + (t4[2] + t4[3]);
+    t += dpp<0xB1>(t);
+    t += dpp<0x4E>(t);
+    if (part == 0 && e < count) Q.part[(int64_t)grp * Q.nbq + jb + e] = t;
   };
 
   // Software pipeline over the subtree's nodes: while node p is computed,
@@ -565,7 +582,7 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
       int64_t h = qh;
       int32_t kind = qk;
       uint32_t qo = q0o;
-      int32_t jl = q0 - jb;  // lane of entry j in the query buffer
+      int32_t jl = q0 - jb;  // row of entry j in the LDS block
       int32_t j = q0;
       do {
         // path-stack value first (nine entries in ten on the all-edge
@@ -612,13 +629,12 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
           const double df = acc[v] - zh[v];
           sacc = fma(df, df, sacc);
         }
-        const double sq = wave_sum(sacc);
-        while (jl >= kWin) {
-          flush(kWin);
-          jb += kWin;
-          jl -= kWin;
+        while (jl >= kQBlock) {
+          flush(kQBlock);
+          jb += kQBlock;
+          jl -= kQBlock;
         }
-        qbuf = set_lane(qbuf, jl, sq);
+        qrow[jl][lane] = sacc;
         h = h_next;
         kind = kind_next;
         qo += kBQ;
@@ -646,16 +662,17 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
     step(vc, vb);
     if (p + 3 >= p1) break;
   }
-  while (jend - jb > kWin) {
-    flush(kWin);
-    jb += kWin;
+  while (jend - jb > kQBlock) {
+    flush(kQBlock);
+    jb += kQBlock;
   }
   flush(jend - jb);
 }
 
 template <bool WIDE>
 __global__ __launch_bounds__(64 * kBottomWaves) void bottom_kernel(SweepArgs A, QueryArgs Q) {
-  bottom_body<WIDE>(A, Q, blockIdx.x);
+  __shared__ BottomLds lds;
+  bottom_body<WIDE>(A, Q, blockIdx.x, lds);
 }
 
 __device__ __forceinline__ void reduce_body(const QueryArgs& Q, int64_t blk) {
@@ -789,8 +806,9 @@ __global__ __launch_bounds__(256) void grouped_kernel(const FactorArgs* __restri
     if constexpr (KIND == GK_CHAIN_ROWS) {
       chain_rows_body(load_struct(&fa[f].a), local);
     } else if constexpr (KIND == GK_BOTTOM) {
-      if (load_uniform(&fa[f].a.store_wide)) bottom_body<true>(load_struct(&fa[f].a), load_struct(&fa[f].q), local);
-      else bottom_body<false>(load_struct(&fa[f].a), load_struct(&fa[f].q), local);
+      __shared__ BottomLds lds;
+      if (load_uniform(&fa[f].a.store_wide)) bottom_body<true>(load_struct(&fa[f].a), load_struct(&fa[f].q), local, lds);
+      else bottom_body<false>(load_struct(&fa[f].a), load_struct(&fa[f].q), local, lds);
     } else if constexpr (KIND == GK_REDUCE) {
       reduce_body(load_struct(&fa[f].q), local);
     } else if constexpr (KIND == GK_TOP_QUERY) {
