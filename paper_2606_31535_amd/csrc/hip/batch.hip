@@ -119,8 +119,10 @@ void batch_layout(const DeviceHandle& D, const std::vector<BatchEntry>& E, Batch
       L.bottom_grid[c] = c == 2 ? 8 * (int64_t)D.cus : c == 3 ? 4 * (int64_t)D.cus : L.bottom_n;
     }
     if (L.bottom_n > 0) {
+      bool wide = false;
+      for (int32_t i = 0; i < nb; ++i) wide = wide || L.fargs[i].a.store_wide != 0;
       L.bottom_stage = (int)L.stages.size();
-      L.stages.push_back(BatchStage{GK_BOTTOM, L.bottom_off[0], L.bottom_n, L.bottom_n});
+      L.stages.push_back(BatchStage{wide ? GK_BOTTOM_WIDE : GK_BOTTOM, L.bottom_off[0], L.bottom_n, L.bottom_n});
     }
   }
   // finish: ordered window sums, top-node pairs, zero pairs, non-ancestor pairs
@@ -195,7 +197,7 @@ Status run_sweep_pruned(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipS
   for (int k = nst - 1; k >= 0; --k) {
     const int kd = L->stages[k].kind;
     const bool finish = kd == GK_REDUCE || kd == GK_TOP_QUERY || kd == GK_ZERO || kd == GK_GENERAL;
-    if (kd == GK_BOTTOM || finish) b1 = k;
+    if (kd == GK_BOTTOM || kd == GK_BOTTOM_WIDE || finish) b1 = k;
     if (finish) b2 = k;
   }
   if (profile) (void)hipEventRecord(F.ev[0], s);
@@ -205,7 +207,7 @@ Status run_sweep_pruned(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipS
     if (k == nst) break;
     st = batch_launch_stage(*L, L->stages[k], D.layout_mem, s);
     if (st != OK) return st;
-    if (L->stages[k].kind == GK_BOTTOM) ++bottom;
+    if (L->stages[k].kind == GK_BOTTOM || L->stages[k].kind == GK_BOTTOM_WIDE) ++bottom;
     else if (k < b1) ++top;
   }
   if (profile) (void)hipEventRecord(F.ev[3], s);
@@ -322,7 +324,7 @@ Status autotune(BatchExec& X, hipStream_t s) {
   Status r = OK;
   double best = 1e300;
   for (int c = 0; c < kBatchSchedules && r == OK; ++c) {
-    const BatchStage st{GK_BOTTOM, L.bottom_off[c], L.bottom_n, L.bottom_grid[c]};
+    const BatchStage st{L.stages[L.bottom_stage].kind, L.bottom_off[c], L.bottom_n, L.bottom_grid[c]};
     double tmin = 1e300;
     for (int rep = 0; rep < 2 && r == OK; ++rep) {
       hipError_t e = hipEventRecord(ev[0], s);

@@ -797,6 +797,17 @@ __global__ __launch_bounds__(64) void grouped_inv_base_kernel(const FactorArgs* 
   }
 }
 
+// One (factor, item) per workgroup of the bottom step (grids that cover the
+// items); the persistent schedules use grouped_kernel's loop.
+template <bool WIDE>
+__global__ __launch_bounds__(64 * kBottomWaves) void grouped_bottom_once_kernel(const FactorArgs* __restrict__ fa,
+                                                                               const GroupItem* __restrict__ items) {
+  __shared__ BottomLds lds;
+  const int32_t f = load_uniform(&items[blockIdx.x].fa);
+  const int64_t local = load_uniform(&items[blockIdx.x].local);
+  bottom_body<WIDE>(load_struct(&fa[f].a), load_struct(&fa[f].q), local, lds);
+}
+
 template <int KIND>
 __global__ __launch_bounds__(256) void grouped_kernel(const FactorArgs* __restrict__ fa,
                                                       const GroupItem* __restrict__ items, int64_t nitems) {
@@ -805,10 +816,9 @@ __global__ __launch_bounds__(256) void grouped_kernel(const FactorArgs* __restri
     const int64_t local = load_uniform(&items[i].local);
     if constexpr (KIND == GK_CHAIN_ROWS) {
       chain_rows_body(load_struct(&fa[f].a), local);
-    } else if constexpr (KIND == GK_BOTTOM) {
+    } else if constexpr (KIND == GK_BOTTOM || KIND == GK_BOTTOM_WIDE) {
       __shared__ BottomLds lds;
-      if (load_uniform(&fa[f].a.store_wide)) bottom_body<true>(load_struct(&fa[f].a), load_struct(&fa[f].q), local, lds);
-      else bottom_body<false>(load_struct(&fa[f].a), load_struct(&fa[f].q), local, lds);
+      bottom_body<KIND == GK_BOTTOM_WIDE>(load_struct(&fa[f].a), load_struct(&fa[f].q), local, lds);
     } else if constexpr (KIND == GK_REDUCE) {
       reduce_body(load_struct(&fa[f].q), local);
     } else if constexpr (KIND == GK_TOP_QUERY) {
@@ -838,7 +848,16 @@ hipError_t launch_grouped(int kind, const FactorArgs* fa, const GroupItem* items
     case GK_INV_BASE: hipLaunchKernelGGL(grouped_inv_base_kernel, g, dim3(64), 0, s, fa, items, nitems); break;
     case GK_CHAIN_ROWS: hipLaunchKernelGGL(grouped_kernel<GK_CHAIN_ROWS>, g, dim3(256), 0, s, fa, items, nitems); break;
     case GK_BOTTOM:
-      hipLaunchKernelGGL(grouped_kernel<GK_BOTTOM>, g, dim3(64 * kBottomWaves), 0, s, fa, items, nitems);
+      if ((int64_t)g.x == nitems)
+        hipLaunchKernelGGL(grouped_bottom_once_kernel<false>, g, dim3(64 * kBottomWaves), 0, s, fa, items);
+      else
+        hipLaunchKernelGGL(grouped_kernel<GK_BOTTOM>, g, dim3(64 * kBottomWaves), 0, s, fa, items, nitems);
+      break;
+    case GK_BOTTOM_WIDE:
+      if ((int64_t)g.x == nitems)
+        hipLaunchKernelGGL(grouped_bottom_once_kernel<true>, g, dim3(64 * kBottomWaves), 0, s, fa, items);
+      else
+        hipLaunchKernelGGL(grouped_kernel<GK_BOTTOM_WIDE>, g, dim3(64 * kBottomWaves), 0, s, fa, items, nitems);
       break;
     case GK_REDUCE: hipLaunchKernelGGL(grouped_kernel<GK_REDUCE>, g, dim3(256), 0, s, fa, items, nitems); break;
     case GK_TOP_QUERY: hipLaunchKernelGGL(grouped_kernel<GK_TOP_QUERY>, g, dim3(256), 0, s, fa, items, nitems); break;

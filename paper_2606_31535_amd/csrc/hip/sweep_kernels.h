@@ -85,7 +85,10 @@ struct GroupItem {
 
 enum GroupKind : int {
   GK_GEMM = 0, GK_INV_BASE = 1, GK_CHAIN_ROWS = 2, GK_BOTTOM = 3,
-  GK_REDUCE = 4, GK_TOP_QUERY = 5, GK_ZERO = 6, GK_GENERAL = 7, GK_GEMM_NARROW = 8
+  GK_REDUCE = 4, GK_TOP_QUERY = 5, GK_ZERO = 6, GK_GENERAL = 7, GK_GEMM_NARROW = 8,
+  // the bottom step of a group holding a factor with 64-bit store offsets
+  // (GK_BOTTOM runs only the 32-bit form, which keeps its register count low)
+  GK_BOTTOM_WIDE = 9
 };
 
 // Items per finish block of each kind (threads or wavefronts per item).
