@@ -132,3 +132,29 @@ def test_batch_errors(dev, batch):
         P.peers_batch_query(dev, [fs[1]], [np.array([0, graphs[1].n], np.int32)], [np.array([1, 2], np.int32)],
                             [np.zeros(2)])
     assert ei.value.status == -2
+
+
+def test_batch_with_wide_store_factor(dev, batch):
+    # one factor with 64-bit store offsets switches the group's bottom step to
+    # the 64-bit form; every factor must still give its single-call bits
+    graphs, fs = batch
+    g = synth.pdn_multilayer(side=24, layers=3, seed=31)
+    h = P.peers_graph_create(g.n, g.eu, g.ev, g.w, g.ground, coords=g.coords, store_offsets_64=True)
+    f = P.peers_factor_upload(dev, h)
+    try:
+        gs = graphs[:3] + [g]
+        sub = fs[:3] + [f]
+        alone = []
+        for x, fx in zip(gs, sub):
+            R = np.full(x.m, np.nan)
+            P.peers_query_all_edges(fx, R)
+            alone.append(R)
+        outs = [np.full(x.m, np.nan) for x in gs]
+        P.peers_batch_query(dev, sub, [None] * len(sub), [None] * len(sub), outs)
+        for a, b in zip(alone, outs):
+            assert np.array_equal(_bits(a), _bits(b))
+        Ro = dense.resistances(g, g.eu, g.ev)
+        assert float(np.max(np.abs(outs[-1] - Ro) / Ro)) <= 1e-10
+    finally:
+        P.peers_factor_release(f)
+        P.peers_graph_destroy(h)
