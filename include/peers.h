@@ -166,7 +166,9 @@ peers_status peers_query_all_edges(peers_factor f, double* R_out, uint32_t flags
  * in query order. Blocks until the results are in R_out (host output) or
  * enqueued (device output without PEERS_SYNC).
  * Errors: NODE_RANGE for an id outside [0, n); OVER_BUDGET when the plan and
- * workspace do not fit the device budget. */
+ * workspace do not fit the device budget; INVALID_ARG when the pairs whose
+ * lower endpoint lies in a bottom subtree need more than 4 GB of query
+ * records (about 178M such pairs; split the request). */
 peers_status peers_query(peers_factor f, int64_t q, const int32_t* qu, const int32_t* qv, double* R_out,
                          uint32_t flags, void* hip_stream);
 
@@ -185,8 +187,8 @@ peers_status peers_query(peers_factor f, int64_t q, const int32_t* qu, const int
  * later calls with the same factors and outputs (released factors and grown
  * workspaces drop it). Blocks until done unless every entry is all-edge with
  * device output and PEERS_SYNC is not set.
- * Errors: INVALID_ARG (null, duplicate factor, factor of another device),
- * NODE_RANGE, OVER_BUDGET. */
+ * Errors: INVALID_ARG (null, duplicate factor, factor of another device, a
+ * plan over the query-record limit of peers_query), NODE_RANGE, OVER_BUDGET. */
 peers_status peers_batch_query(peers_device d, int32_t nb, const peers_factor* f, const int64_t* q,
                                const int32_t* const* qu, const int32_t* const* qv, double* const* R_out,
                                uint32_t flags, void* hip_stream);
