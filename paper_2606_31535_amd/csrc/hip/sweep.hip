@@ -131,8 +131,11 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // e1 are clamped to a valid column and their B value is zeroed at use, so
 // each load is waited for only right before its MFMAs. Gathered column
 // offsets come through the scalar unit one step ahead. Operands are kept
-// DEPTH - 1 steps ahead (three buffers measured best for both tile forms).
-template <bool GATHER, bool BT, int NB = 2, int DEPTH = 3>
+// DEPTH - 1 steps ahead: the 64 x 32 tiles use two buffers, which keeps them
+// within 128 registers (four waves per SIMD, with 32 KB of LDS per
+// workgroup), measured faster than three buffers at three waves; the
+// one-wave narrow tiles use three.
+template <bool GATHER, bool BT, int NB = 2, int DEPTH = 2>
 __device__ __forceinline__ void gemm_accumulate(f64x4 (&C)[4][NB], const double* __restrict__ A,
                                                 const double* __restrict__ B, const int64_t* __restrict__ gt,
                                                 const GemmProb& pb, const int32_t (&rows)[4], const int32_t (&cols)[NB],
@@ -195,9 +198,9 @@ __device__ __forceinline__ void gemm_accumulate(f64x4 (&C)[4][NB], const double*
 // reduction range [k0, k1) of its task. v_mfma_f64_16x16x4f64 operands:
 // A lane l = (row l%16, k l/16), B lane l = (k l/16, col l%16), C lane l reg
 // r = (row 4r + l/16, col l%16). The four waves take consecutive quarters of
-// the reduction range (multiples of 4) and are summed in LDS in wave order,
-// so the result does not depend on scheduling.
-typedef double GemmRed[3][8][4][kWin];
+// the reduction range (multiples of 4) and are summed in LDS in a fixed
+// order, (C0 + C2) + (C1 + C3), so the result does not depend on scheduling.
+typedef double GemmRed[2][8][4][kWin];
 
 // Gp points at the argument block in kernel-argument or global memory; its
 // buffer table is read with uniform loads at the problem's (uniform) index.
@@ -239,24 +242,41 @@ __device__ __forceinline__ void gemm_body(const GemmArgs* Gp, int64_t task, Gemm
       else gemm_accumulate<false, false>(C, A, B, gt, pb, rows, cols, kk, e0, e1);
     }
   }
-  if (wave > 0) {
+  // (C0 + C2) + (C1 + C3), in two rounds through a two-wave buffer
+  if (wave >= 2) {
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
       for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) red[wave - 1][rb * 2 + cb][r][lane] = C[rb][cb][r];
+        for (int r = 0; r < 4; ++r) red[wave - 2][rb * 2 + cb][r][lane] = C[rb][cb][r];
+  }
+  __syncthreads();
+  if (wave < 2) {
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) C[rb][cb][r] += red[wave][rb * 2 + cb][r][lane];
+  }
+  __syncthreads();
+  if (wave == 1) {
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[0][rb * 2 + cb][r][lane] = C[rb][cb][r];
   }
   __syncthreads();
   if (wave == 0) {
 #pragma unroll
-    for (int w = 0; w < 3; ++w)
+    for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb)
+      for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) C[rb][cb][r] += red[w][rb * 2 + cb][r][lane];
+        for (int r = 0; r < 4; ++r) C[rb][cb][r] += red[0][rb * 2 + cb][r][lane];
   }
   __syncthreads();
   constexpr int LD = kTileN + 1;
@@ -298,7 +318,7 @@ __device__ __forceinline__ int64_t xcd_task(int64_t b) {
 }
 inline int64_t xcd_grid(int64_t n) { return (n + kXcds * kXcdRun - 1) / (kXcds * kXcdRun) * (kXcds * kXcdRun); }
 
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs G, int64_t task0, int64_t ntasks) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void gemm_kernel(GemmArgs G, int64_t task0, int64_t ntasks) {
   __shared__ GemmRed red;
   const int64_t t = xcd_task(blockIdx.x);
   if (t >= ntasks) return;
@@ -765,7 +785,7 @@ __device__ __forceinline__ T load_struct(const T* p) {
   return r;
 }
 
-__global__ __launch_bounds__(256) void grouped_gemm_kernel(const FactorArgs* __restrict__ fa,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void grouped_gemm_kernel(const FactorArgs* __restrict__ fa,
                                                            const GroupItem* __restrict__ items, int64_t nitems) {
   __shared__ GemmRed red;
   for (int64_t i = blockIdx.x; i < nitems; i += gridDim.x) {
