@@ -392,7 +392,7 @@ def main():
     ph = {k: float(np.mean([p[k] for p in phases])) for k in ("top_ms", "bottom_ms", "finish_ms", "total_ms")}
     tm = phases[-1]
     if ph["top_ms"] >= ph["bottom_ms"]:
-        kname, ms, flops, nl = "gemm_kernel", ph["top_ms"], tm["top_flops"], tm["top_launches"]
+        kname, ms, flops, nl = "gemm_level_kernel", ph["top_ms"], tm["top_flops"], tm["top_launches"]
         bound = "mfma"
     else:
         kname, ms, flops, nl = "bottom_kernel", ph["bottom_ms"], tm["bottom_flops"], tm["bottom_launches"]

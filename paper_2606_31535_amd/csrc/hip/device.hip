@@ -192,9 +192,9 @@ Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t
   HIP_TRY(launch_chain_rows(F.sweep, P.ntop, s));
   launches += P.ntop > 0 ? 1 : 0;
   for (size_t l = 0; l + 1 < P.t2_ptr.size(); ++l) {
-    HIP_TRY(launch_gemm(F.gemm, P.t2_ptr[l], P.t2_ptr[l + 1] - P.t2_ptr[l], s));
-    HIP_TRY(launch_gemm_narrow(F.gemm, P.t2n_ptr[l], P.t2n_ptr[l + 1] - P.t2n_ptr[l], s));
-    launches += 2;
+    HIP_TRY(launch_gemm_level(F.gemm, P.t2_ptr[l], P.t2_ptr[l + 1] - P.t2_ptr[l], P.t2n_ptr[l],
+                              P.t2n_ptr[l + 1] - P.t2n_ptr[l], s));
+    launches += 1;
   }
   F.top_launches = launches;
   if (profile) HIP_TRY(hipEventRecord(F.ev[1], s));

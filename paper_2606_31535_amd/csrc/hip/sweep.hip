@@ -316,7 +316,7 @@ __device__ __forceinline__ int64_t xcd_task(int64_t b) {
   const int64_t x = b % kXcds, slot = b / kXcds;
   return (slot / kXcdRun) * (kXcds * kXcdRun) + x * kXcdRun + slot % kXcdRun;
 }
-inline int64_t xcd_grid(int64_t n) { return (n + kXcds * kXcdRun - 1) / (kXcds * kXcdRun) * (kXcds * kXcdRun); }
+__host__ __device__ inline int64_t xcd_grid(int64_t n) { return (n + kXcds * kXcdRun - 1) / (kXcds * kXcdRun) * (kXcds * kXcdRun); }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void gemm_kernel(GemmArgs G, int64_t task0, int64_t ntasks) {
   __shared__ GemmRed red;
@@ -363,6 +363,23 @@ __global__ __launch_bounds__(256) void gemm_narrow_kernel(GemmArgs G, int64_t ta
   const int64_t i = (int64_t)blockIdx.x * 4 + wave;
   if (i >= ntasks) return;
   gemm_narrow_body(&G, task0 + i);
+}
+
+// One chain level: the 64 x 32 tiles of its wide chains (first, in XCD runs)
+// and the 64 x 16 one-wave tiles of its narrow chains (after them) in one
+// launch, so the narrow tiles fill the device as the wide ones drain.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void gemm_level_kernel(
+    GemmArgs G, int64_t task0, int64_t ntasks, int64_t ntask0, int64_t nntasks) {
+  __shared__ GemmRed red;
+  const int64_t nwide = xcd_grid(ntasks);
+  if ((int64_t)blockIdx.x < nwide) {
+    const int64_t t = xcd_task(blockIdx.x);
+    if (t < ntasks) gemm_body(&G, task0 + t, red);
+  } else {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t i = ((int64_t)blockIdx.x - nwide) * 4 + wave;
+    if (i < nntasks) gemm_narrow_body(&G, ntask0 + i);
+  }
 }
 
 // Inverse of one diagonal block (at most 64 x 64) of a chain's unit-lower
@@ -885,6 +902,14 @@ hipError_t launch_grouped(int kind, const FactorArgs* fa, const GroupItem* items
     case GK_GENERAL: hipLaunchKernelGGL(grouped_kernel<GK_GENERAL>, g, dim3(256), 0, s, fa, items, nitems); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_level(const GemmArgs& g, int64_t task0, int64_t ntasks, int64_t ntask0, int64_t nntasks,
+                             hipStream_t s) {
+  const int64_t grid = xcd_grid(ntasks) + (nntasks + 3) / 4;
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gemm_level_kernel, dim3((unsigned)grid), dim3(256), 0, s, g, task0, ntasks, ntask0, nntasks);
   return hipGetLastError();
 }
 

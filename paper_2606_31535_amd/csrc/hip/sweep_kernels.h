@@ -98,6 +98,9 @@ hipError_t launch_grouped(int kind, const FactorArgs* fa, const GroupItem* items
                           hipStream_t s);
 hipError_t launch_gemm(const GemmArgs& g, int64_t task0, int64_t ntasks, hipStream_t s);
 hipError_t launch_gemm_narrow(const GemmArgs& g, int64_t task0, int64_t ntasks, hipStream_t s);
+// wide tiles [task0, task0 + ntasks) and narrow tiles [ntask0, ntask0 + nntasks) of one chain level
+hipError_t launch_gemm_level(const GemmArgs& g, int64_t task0, int64_t ntasks, int64_t ntask0, int64_t nntasks,
+                             hipStream_t s);
 hipError_t launch_inv_base(const SweepArgs& a, hipStream_t s);
 hipError_t launch_chain_rows(const SweepArgs& a, int32_t ntop, hipStream_t s);
 hipError_t launch_bottom(const SweepArgs& a, const QueryArgs& q, hipStream_t s);
