@@ -412,20 +412,21 @@ __global__ __launch_bounds__(64) void inv_base_kernel(SweepArgs A) {
 
 // Rows of a top column that lie inside its own chain (Z[C, C] = D^{-1/2} L_CC^{-1})
 // and the zero padding below the column's depth. One workgroup per top column.
-__device__ __forceinline__ void chain_rows_body(const SweepArgs& A, int64_t k) {
+// (threads tid, tid + nthr, ... of the caller write top node k's rows)
+__device__ __forceinline__ void chain_rows_body(const SweepArgs& A, int64_t k, int tid, int nthr) {
   const Chain c = A.chains[A.top_chain[k]];
   const int32_t j = A.top_node[k] - c.a;
   const int64_t nrow = c.ld - c.dp;
   double* col = A.store + c.store_base + (int64_t)j * c.ld + c.dp;
   const double* xc = A.X + c.x_off + (int64_t)j * c.ldl;
-  for (int64_t r = threadIdx.x; r < nrow; r += 256) {
+  for (int64_t r = tid; r < nrow; r += nthr) {
     double v = 0.0;
     if (r < c.w - j) v = A.isd[c.b - r] * xc[c.w - 1 - r];
     col[r] = v;
   }
 }
 
-__global__ __launch_bounds__(256) void chain_rows_kernel(SweepArgs A) { chain_rows_body(A, blockIdx.x); }
+__global__ __launch_bounds__(256) void chain_rows_kernel(SweepArgs A) { chain_rows_body(A, blockIdx.x, threadIdx.x, 256); }
 
 // One wavefront sweeps kWinPerWave consecutive windows of one subtree task:
 // lane l holds depth t*64 + l of window t for each of them. The per-node
@@ -767,6 +768,9 @@ __device__ __forceinline__ void top_query_body(const SweepArgs& A, const QueryAr
   const double* zl = A.store + A.top_off[lo];
   const double* zh = hi >= 0 ? A.store + A.top_off[hi] : nullptr;
   double s = 0.0;
+  // unrolled so that several windows' loads are in flight before their sums
+  // (the sum order is unchanged: one running sum in window order)
+#pragma unroll 4
   for (int32_t d = lane; d < dl; d += kWin) {
     const double v = zl[d] - (d < dh ? zh[d] : 0.0);
     s = fma(v, v, s);
@@ -822,6 +826,18 @@ __global__ __launch_bounds__(256) void grouped_narrow_kernel(const FactorArgs* _
   }
 }
 
+// chain rows of many factors: one wavefront per top node, four per workgroup
+// (most top nodes of small graphs have a few windows of rows)
+__global__ __launch_bounds__(256) void grouped_chain_rows_kernel(const FactorArgs* __restrict__ fa,
+                                                                 const GroupItem* __restrict__ items, int64_t nitems) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int64_t b = blockIdx.x; b * 4 < nitems; b += gridDim.x) {
+    const int64_t i = b * 4 + wave;
+    if (i < nitems)
+      chain_rows_body(load_struct(&fa[load_uniform(&items[i].fa)].a), load_uniform(&items[i].local), threadIdx.x & 63, 64);
+  }
+}
+
 __global__ __launch_bounds__(64) void grouped_inv_base_kernel(const FactorArgs* __restrict__ fa,
                                                               const GroupItem* __restrict__ items, int64_t nitems) {
   __shared__ BaseTile Ls, Xs;
@@ -851,9 +867,7 @@ __global__ __launch_bounds__(256) void grouped_kernel(const FactorArgs* __restri
   for (int64_t i = blockIdx.x; i < nitems; i += gridDim.x) {
     const int32_t f = load_uniform(&items[i].fa);
     const int64_t local = load_uniform(&items[i].local);
-    if constexpr (KIND == GK_CHAIN_ROWS) {
-      chain_rows_body(load_struct(&fa[f].a), local);
-    } else if constexpr (KIND == GK_BOTTOM || KIND == GK_BOTTOM_WIDE) {
+    if constexpr (KIND == GK_BOTTOM || KIND == GK_BOTTOM_WIDE) {
       __shared__ BottomLds lds;
       bottom_body<KIND == GK_BOTTOM_WIDE>(load_struct(&fa[f].a), load_struct(&fa[f].q), local, lds);
     } else if constexpr (KIND == GK_REDUCE) {
@@ -883,7 +897,12 @@ hipError_t launch_grouped(int kind, const FactorArgs* fa, const GroupItem* items
       break;
     }
     case GK_INV_BASE: hipLaunchKernelGGL(grouped_inv_base_kernel, g, dim3(64), 0, s, fa, items, nitems); break;
-    case GK_CHAIN_ROWS: hipLaunchKernelGGL(grouped_kernel<GK_CHAIN_ROWS>, g, dim3(256), 0, s, fa, items, nitems); break;
+    case GK_CHAIN_ROWS: {
+      // four top nodes per workgroup
+      const dim3 gr((unsigned)std::max<int64_t>(1, (std::min(grid, nitems) + 3) / 4));
+      hipLaunchKernelGGL(grouped_chain_rows_kernel, gr, dim3(256), 0, s, fa, items, nitems);
+      break;
+    }
     case GK_BOTTOM:
       if ((int64_t)g.x == nitems)
         hipLaunchKernelGGL(grouped_bottom_once_kernel<false>, g, dim3(64 * kBottomWaves), 0, s, fa, items);
