@@ -503,6 +503,23 @@ Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int
       Q.tq_out.push_back(k);
     }
   }
+  if (!Q.tq_lo.empty()) {
+    // top queries by lower endpoint, so that the queries of one column run
+    // side by side and share its reads in the caches
+    std::vector<int64_t> ord(Q.tq_lo.size());
+    for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int64_t)i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) { return Q.tq_lo[x] < Q.tq_lo[y]; });
+    std::vector<int32_t> lo2(ord.size()), hi2(ord.size());
+    std::vector<int64_t> out2(ord.size());
+    for (size_t i = 0; i < ord.size(); ++i) {
+      lo2[i] = Q.tq_lo[ord[i]];
+      hi2[i] = Q.tq_hi[ord[i]];
+      out2[i] = Q.tq_out[ord[i]];
+    }
+    Q.tq_lo.swap(lo2);
+    Q.tq_hi.swap(hi2);
+    Q.tq_out.swap(out2);
+  }
   {
     // the sweep forms record byte offsets in 32 bits (one padding record)
     int64_t total = 0;
