@@ -1,25 +1,28 @@
 // HIP kernels of the implicit sweep (Section III-C eq 11, Section III-G eq 12).
 //
-//  * top tree (chains of separator nodes, see host/plan.h): gemm_kernel is a
-//    generic FP64 MFMA GEMM (v_mfma_f64_16x16x4f64; both operands stay in
-//    VGPRs, so neither LDS nor scalar registers carry the reuse) driven by task
-//    lists. It forms L_CC^{-1} of every chain by recursive 2x2 blocking on top
-//    of inv_base_kernel's 64 x 64 diagonal inverses; chain_rows_kernel writes
-//    the chain rows D^{-1/2} L_CC^{-1} of every top column; then, chain level
-//    by chain level, Z[rows above C, C] = Z[rows above C, U_C] B_C with the
-//    ancestor columns gathered straight from the top store.
-//  * bottom_kernel: one wavefront per (bottom subtree task, window). Nodes are
-//    visited in descending index, a topological order of every row's
-//    traversal; the values of the current root path live in a register stack
-//    indexed by local depth; values above the subtree come from the top
-//    store, requested one node ahead. Per-node records come through the
-//    scalar unit. Each query whose lower endpoint is the current node sums
-//    (z_u[d] - z_v[d])^2 over the window (eq 12); the sums are collected one
-//    query per lane and stored 64 at a time into window-major slots, so the
-//    final ordered sum reads coalesced.
-//  * finish kernels: ordered sum of each bottom query's window slots, the
-//    queries whose lower endpoint is a top node (both columns are in the top
-//    store), and the pairs whose resistance is exactly zero.
+//  * top tree (chains of separator nodes, see host/plan.h): FP64 MFMA GEMMs
+//    (v_mfma_f64_16x16x4f64, operands straight from global memory into
+//    registers) driven by task lists. At upload, gemm_kernel forms L_CC^{-1}
+//    of every chain by recursive 2x2 blocking on top of inv_base_kernel's
+//    64 x 64 diagonal inverses, and the transfer blocks B_C. Every sweep,
+//    chain_rows_kernel writes the chain rows D^{-1/2} L_CC^{-1} of every top
+//    column; then gemm_level_kernel, one launch per chain level, forms
+//    Z[rows above C, C] = Z[rows above C, U_C] B_C with the ancestor columns
+//    gathered from the top store (64 x 32 tiles for wide chains, one-wave
+//    64 x 16 tiles for narrow ones).
+//  * bottom_kernel: one wavefront per (bottom subtree task, group of two
+//    windows). Nodes are visited in descending index, a topological order of
+//    every row's traversal; the values of the current root path live in a
+//    register stack per window indexed by local depth; values above the
+//    subtree come from the top store, requested two nodes ahead. Per-node
+//    records come through the scalar unit. Each query whose lower endpoint is
+//    the current node sums (z_u[d] - z_v[d])^2 over the windows (eq 12); the
+//    per-lane sums go through a per-wave LDS block and are summed over the
+//    lanes 16 queries at a time into window-group slots.
+//  * finish kernels: ordered sum of each bottom query's window-group slots,
+//    the queries whose lower endpoint is a top node (both columns are in the
+//    top store), non-ancestor pairs, and the pairs whose resistance is exactly
+//    zero.
 #include "sweep_kernels.h"
 
 namespace peers {

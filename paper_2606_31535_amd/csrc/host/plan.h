@@ -11,10 +11,10 @@
 //
 // The tree is split in two:
 //  * bottom subtrees: maximal subtrees with at most kBottomMaxNodes nodes and
-//    height at most kBottomMaxHeight. A workgroup sweeps one of them for one
-//    window in descending index order (a topological order, Theorem 1),
-//    keeping the column values of the current root path in an LDS stack
-//    indexed by local depth; nothing else of Z is kept.
+//    height at most kBottomMaxHeight. A wavefront sweeps one of them for a
+//    group of windows in descending index order (a topological order,
+//    Theorem 1), keeping the column values of the current root path in a
+//    register stack indexed by local depth; nothing else of Z is kept.
 //  * the top tree (the separators of the nested dissection and everything
 //    above the bottom subtrees). It is cut into chains: maximal runs of top
 //    nodes a..b with parent(i) = i+1. For a chain C with diagonal block L_CC
@@ -22,8 +22,9 @@
 //    Z above C follow from eq 11 as one product
 //        Z[rows above C, C] = Z[rows above C, U_C] * B_C,
 //        B_C = -L_{U_C, C} L_CC^{-1}      (formed once per factor, on the GPU),
-//    and the rows inside C are Z[C, C] = D_C^{-1/2} L_CC^{-1}, produced every
-//    sweep by a recursive blocked triangular inverse. Every term is >= 0
+//    and the rows inside C are Z[C, C] = D_C^{-1/2} L_CC^{-1} (L_CC^{-1} by a
+//    recursive blocked triangular inverse at upload; the scaled rows written
+//    every sweep). Every term is >= 0
 //    (-L_ki >= 0 and L^{-1} >= 0 for a grounded Laplacian), so these blocked
 //    forms add nonnegative terms only. Chains depend only on their ancestor
 //    chains, so the top tree is a handful of levels of dense FP64 GEMMs. The
