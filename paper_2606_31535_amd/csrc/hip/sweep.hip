@@ -361,13 +361,6 @@ __device__ __forceinline__ void gemm_narrow_body(const GemmArgs* Gp, int64_t tas
     }
 }
 
-__global__ __launch_bounds__(256) void gemm_narrow_kernel(GemmArgs G, int64_t task0, int64_t ntasks) {
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t i = (int64_t)blockIdx.x * 4 + wave;
-  if (i >= ntasks) return;
-  gemm_narrow_body(&G, task0 + i);
-}
-
 // One chain level: the 64 x 32 tiles of its wide chains (first, in XCD runs)
 // and the 64 x 16 one-wave tiles of its narrow chains (after them) in one
 // launch, so the narrow tiles fill the device as the wide ones drain.
@@ -935,11 +928,6 @@ hipError_t launch_gemm_level(const GemmArgs& g, int64_t task0, int64_t ntasks, i
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_narrow(const GemmArgs& g, int64_t task0, int64_t ntasks, hipStream_t s) {
-  if (ntasks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gemm_narrow_kernel, dim3((unsigned)((ntasks + 3) / 4)), dim3(256), 0, s, g, task0, ntasks);
-  return hipGetLastError();
-}
 
 hipError_t launch_gemm(const GemmArgs& g, int64_t task0, int64_t ntasks, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;

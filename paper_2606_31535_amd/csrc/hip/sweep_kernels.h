@@ -97,7 +97,6 @@ constexpr int kReduceBlock = 256, kTopQueryBlock = 4, kZeroBlock = 256, kGeneral
 hipError_t launch_grouped(int kind, const FactorArgs* fa, const GroupItem* items, int64_t nitems, int64_t grid,
                           hipStream_t s);
 hipError_t launch_gemm(const GemmArgs& g, int64_t task0, int64_t ntasks, hipStream_t s);
-hipError_t launch_gemm_narrow(const GemmArgs& g, int64_t task0, int64_t ntasks, hipStream_t s);
 // wide tiles [task0, task0 + ntasks) and narrow tiles [ntask0, ntask0 + nntasks) of one chain level
 hipError_t launch_gemm_level(const GemmArgs& g, int64_t task0, int64_t ntasks, int64_t ntask0, int64_t nntasks,
                              hipStream_t s);
