@@ -113,20 +113,6 @@ __device__ __forceinline__ double wave_sum(double v) {
                           __builtin_amdgcn_readlane(__double2loint(v), 63));
 }
 
-// v_writelane_b32: lane `lane` of x (wave-uniform index) set to the
-// wave-uniform y (an ALU instruction with no compiler builtin here; with a
-// scalar data operand the lane index must come through M0).
-__device__ __forceinline__ int write_lane(int x, int lane, int y) {
-  asm("v_writelane_b32 %0, %1, m0" : "+v"(x) : "s"(y), "{m0}"(lane));
-  return x;
-}
-
-// x with lane `lane` (wave-uniform) replaced by the wave-uniform value y.
-__device__ __forceinline__ double set_lane(double x, int lane, double y) {
-  return __hiloint2double(write_lane(__double2hiint(x), lane, __double2hiint(y)),
-                          write_lane(__double2loint(x), lane, __double2loint(y)));
-}
-
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // Reduction loop of gemm_kernel for indices [e0, e1) in steps of 4 (one
