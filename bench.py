@@ -341,8 +341,8 @@ def main():
                     help="only run a plain device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (how it would shard is in the design "
-              "notes); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (the design notes describe how the "
+              "sweep would shard); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     if args.copy_calibration:
