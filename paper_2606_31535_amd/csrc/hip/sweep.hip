@@ -743,46 +743,62 @@ __global__ __launch_bounds__(256) void general_pair_kernel(SweepArgs A, QueryArg
 // eq 12 for a pair whose lower endpoint lo is a top node and whose partner
 // hi is an ancestor of it or the ground: R = sum_{d < depth(lo)} (z_lo[d] -
 // z_hi[d])^2 with z_hi[d] = 0 past depth(hi), both columns read from the top
-// store. Windows whose loads are issued together: 8 measured faster than 4
-// and 16.
-constexpr int kTopQueryUnroll = 8;
+// store. Every sweep writes each top column over whole windows (zeros past
+// the node's depth), so bounds are taken per window: a lane past a depth
+// reads zeros and adds a zero term, which leaves its sum unchanged, and each
+// pair's terms run in window order. Windows whose loads are issued together
+// per step: 2 measured faster than 4 and 8 with two pairs per wavefront.
+constexpr int kTopQueryUnroll = 2;
 __device__ __forceinline__ void top_query_body(const SweepArgs& A, const QueryArgs& Q, int64_t blk) {
-  // one pair per wavefront: its indices and column offsets are wave-uniform
-  // (scalar loads)
-  const int64_t q = blk * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // two consecutive pairs per wavefront (pairs are sorted by lower endpoint,
+  // so the two often share its column): indices and offsets are wave-uniform
+  const int64_t q0 = (blk * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) * 2;
   const int lane = threadIdx.x & 63;
-  if (q >= Q.ntq) return;
-  const int32_t lo = load_uniform(Q.tq_lo + q), hi = load_uniform(Q.tq_hi + q);
-  const int32_t dl = load_uniform(A.top_depth + lo);
-  const int32_t dh = hi >= 0 ? load_uniform(A.top_depth + hi) : 0;
-  const double* __restrict__ zl = A.store + load_uniform(A.top_off + lo) + lane;
-  const double* __restrict__ zh = A.store + (hi >= 0 ? load_uniform(A.top_off + hi) : 0) + lane;
-  // Every sweep writes each top column over whole windows (zeros past the
-  // node's depth), so bounds are taken per window: a lane past the depth
-  // reads a zero and adds a zero term, which leaves its sum unchanged. The
-  // loads of kTopQueryUnroll windows are in flight before their sums, which
-  // run in window order.
-  const int32_t nwl = (dl + kWin - 1) / kWin, nwh = (dh + kWin - 1) / kWin;
-  double s = 0.0;
-  int32_t w = 0;
-  for (; w + kTopQueryUnroll <= nwl; w += kTopQueryUnroll) {
-    double a[kTopQueryUnroll], b[kTopQueryUnroll];
+  if (q0 >= Q.ntq) return;
+  const bool two = q0 + 1 < Q.ntq;
+  const int64_t q1 = two ? q0 + 1 : q0;
+  const int32_t lo0 = load_uniform(Q.tq_lo + q0), hi0 = load_uniform(Q.tq_hi + q0);
+  const int32_t lo1 = load_uniform(Q.tq_lo + q1), hi1 = load_uniform(Q.tq_hi + q1);
+  const int32_t dl0 = load_uniform(A.top_depth + lo0), dl1 = load_uniform(A.top_depth + lo1);
+  const int32_t dh0 = hi0 >= 0 ? load_uniform(A.top_depth + hi0) : 0;
+  const int32_t dh1 = hi1 >= 0 ? load_uniform(A.top_depth + hi1) : 0;
+  const double* __restrict__ zl0 = A.store + load_uniform(A.top_off + lo0) + lane;
+  const double* __restrict__ zl1 = A.store + load_uniform(A.top_off + lo1) + lane;
+  const double* __restrict__ zh0 = A.store + (hi0 >= 0 ? load_uniform(A.top_off + hi0) : 0) + lane;
+  const double* __restrict__ zh1 = A.store + (hi1 >= 0 ? load_uniform(A.top_off + hi1) : 0) + lane;
+  const bool same = lo0 == lo1;
+  const int32_t nwl0 = (dl0 + kWin - 1) / kWin, nwh0 = (dh0 + kWin - 1) / kWin;
+  const int32_t nwl1 = (dl1 + kWin - 1) / kWin, nwh1 = (dh1 + kWin - 1) / kWin;
+  const int32_t nw = max(nwl0, nwl1);
+  double s0 = 0.0, s1 = 0.0;
+  for (int32_t w = 0; w < nw; w += kTopQueryUnroll) {
+    double a0[kTopQueryUnroll], b0[kTopQueryUnroll], a1[kTopQueryUnroll], b1[kTopQueryUnroll];
 #pragma unroll
-    for (int i = 0; i < kTopQueryUnroll; ++i) a[i] = zl[(int64_t)(w + i) * kWin];
+    for (int i = 0; i < kTopQueryUnroll; ++i) a0[i] = w + i < nwl0 ? zl0[(int64_t)(w + i) * kWin] : 0.0;
 #pragma unroll
-    for (int i = 0; i < kTopQueryUnroll; ++i) b[i] = w + i < nwh ? zh[(int64_t)(w + i) * kWin] : 0.0;
+    for (int i = 0; i < kTopQueryUnroll; ++i) b0[i] = w + i < nwh0 ? zh0[(int64_t)(w + i) * kWin] : 0.0;
+    if (same) {
+#pragma unroll
+      for (int i = 0; i < kTopQueryUnroll; ++i) a1[i] = a0[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < kTopQueryUnroll; ++i) a1[i] = w + i < nwl1 ? zl1[(int64_t)(w + i) * kWin] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < kTopQueryUnroll; ++i) b1[i] = w + i < nwh1 ? zh1[(int64_t)(w + i) * kWin] : 0.0;
 #pragma unroll
     for (int i = 0; i < kTopQueryUnroll; ++i) {
-      const double v = a[i] - b[i];
-      s = fma(v, v, s);
+      const double v0 = a0[i] - b0[i], v1 = a1[i] - b1[i];
+      s0 = fma(v0, v0, s0);
+      s1 = fma(v1, v1, s1);
     }
   }
-  for (; w < nwl; ++w) {
-    const double v = zl[(int64_t)w * kWin] - (w < nwh ? zh[(int64_t)w * kWin] : 0.0);
-    s = fma(v, v, s);
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  if (lane == 0) {
+    Q.R[load_uniform(Q.tq_out + q0)] = s0;
+    if (two) Q.R[load_uniform(Q.tq_out + q1)] = s1;
   }
-  s = wave_sum(s);
-  if (lane == 0) Q.R[load_uniform(Q.tq_out + q)] = s;
 }
 
 // Blocks of pairs go to the XCDs in runs of consecutive blocks, as the GEMM
@@ -986,7 +1002,8 @@ hipError_t launch_finish(const SweepArgs& a, const QueryArgs& q, hipStream_t s) 
   if (q.nbq > 0)
     hipLaunchKernelGGL(reduce_bottom_kernel, dim3((unsigned)((q.nbq + 255) / 256)), dim3(256), 0, s, q);
   if (q.ntq > 0)
-    hipLaunchKernelGGL(top_query_kernel, dim3((unsigned)xcd_grid((q.ntq + 3) / 4)), dim3(256), 0, s, a, q);
+    hipLaunchKernelGGL(top_query_kernel, dim3((unsigned)xcd_grid((q.ntq + kTopQueryBlock - 1) / kTopQueryBlock)),
+                       dim3(256), 0, s, a, q);
   if (q.nzero > 0)
     hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((q.nzero + 255) / 256)), dim3(256), 0, s, q);
   if (q.ngp > 0)

@@ -91,8 +91,9 @@ enum GroupKind : int {
   GK_BOTTOM_WIDE = 9
 };
 
-// Items per finish block of each kind (threads or wavefronts per item).
-constexpr int kReduceBlock = 256, kTopQueryBlock = 4, kZeroBlock = 256, kGeneralBlock = 4;
+// Items per finish block of each kind (threads, or wavefronts per item; the
+// top-node pairs take two per wavefront).
+constexpr int kReduceBlock = 256, kTopQueryBlock = 8, kZeroBlock = 256, kGeneralBlock = 4;
 
 hipError_t launch_grouped(int kind, const FactorArgs* fa, const GroupItem* items, int64_t nitems, int64_t grid,
                           hipStream_t s);
