@@ -35,6 +35,18 @@ __device__ __forceinline__ T load_uniform(const T* p) {
   return *(const __attribute__((address_space(4))) T*)p;
 }
 
+// A wave-uniform record of whole 8-byte words through the scalar unit.
+template <class T>
+__device__ __forceinline__ T load_struct(const T* p) {
+  static_assert(sizeof(T) % 8 == 0, "records are whole 8-byte words");
+  uint64_t w[sizeof(T) / 8];
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 8); ++i) w[i] = load_uniform((const uint64_t*)p + i);
+  T r;
+  __builtin_memcpy(&r, w, sizeof(T));
+  return r;
+}
+
 __device__ __forceinline__ BNode load_uniform(const BNode* p) {
   BNode r;
   r.isd = load_uniform(&p->isd);
@@ -396,8 +408,10 @@ __global__ __launch_bounds__(64) void inv_base_kernel(SweepArgs A) {
 // and the zero padding below the column's depth. One workgroup per top column.
 // (threads tid, tid + nthr, ... of the caller write top node k's rows)
 __device__ __forceinline__ void chain_rows_body(const SweepArgs& A, int64_t k, int tid, int nthr) {
-  const Chain c = A.chains[A.top_chain[k]];
-  const int32_t j = A.top_node[k] - c.a;
+  // the node's chain record and position through the scalar unit (k is
+  // wave-uniform)
+  const Chain c = load_struct(A.chains + load_uniform(A.top_chain + k));
+  const int32_t j = load_uniform(A.top_node + k) - c.a;
   const int64_t nrow = c.ld - c.dp;
   double* col = A.store + c.store_base + (int64_t)j * c.ld + c.dp;
   const double* xc = A.X + c.x_off + (int64_t)j * c.ldl;
@@ -749,6 +763,8 @@ __global__ __launch_bounds__(256) void general_pair_kernel(SweepArgs A, QueryArg
 // pair's terms run in window order. Windows whose loads are issued together
 // per step: 2 measured faster than 4 and 8 with two pairs per wavefront.
 constexpr int kTopQueryUnroll = 2;
+// pairs spanning this many windows or more take the one-pair-at-a-time path
+constexpr int32_t kTopQueryDeep = 16;
 __device__ __forceinline__ void top_query_body(const SweepArgs& A, const QueryArgs& Q, int64_t blk) {
   // two consecutive pairs per wavefront (pairs are sorted by lower endpoint,
   // so the two often share its column): indices and offsets are wave-uniform
@@ -771,26 +787,51 @@ __device__ __forceinline__ void top_query_body(const SweepArgs& A, const QueryAr
   const int32_t nwl1 = (dl1 + kWin - 1) / kWin, nwh1 = (dh1 + kWin - 1) / kWin;
   const int32_t nw = max(nwl0, nwl1);
   double s0 = 0.0, s1 = 0.0;
-  for (int32_t w = 0; w < nw; w += kTopQueryUnroll) {
-    double a0[kTopQueryUnroll], b0[kTopQueryUnroll], a1[kTopQueryUnroll], b1[kTopQueryUnroll];
+  if (nw >= kTopQueryDeep) {
+    // deep columns (few such pairs, long load chains): one pair after the
+    // other, with 4 * kTopQueryUnroll windows of loads in flight in the same
+    // registers
+    constexpr int U = 4 * kTopQueryUnroll;
+    auto one = [&](const double* __restrict__ zl, const double* __restrict__ zh, int32_t nwl, int32_t nwh) {
+      double s = 0.0;
+      for (int32_t w = 0; w < nwl; w += U) {
+        double a[U], b[U];
 #pragma unroll
-    for (int i = 0; i < kTopQueryUnroll; ++i) a0[i] = w + i < nwl0 ? zl0[(int64_t)(w + i) * kWin] : 0.0;
+        for (int i = 0; i < U; ++i) a[i] = w + i < nwl ? zl[(int64_t)(w + i) * kWin] : 0.0;
 #pragma unroll
-    for (int i = 0; i < kTopQueryUnroll; ++i) b0[i] = w + i < nwh0 ? zh0[(int64_t)(w + i) * kWin] : 0.0;
-    if (same) {
+        for (int i = 0; i < U; ++i) b[i] = w + i < nwh ? zh[(int64_t)(w + i) * kWin] : 0.0;
 #pragma unroll
-      for (int i = 0; i < kTopQueryUnroll; ++i) a1[i] = a0[i];
-    } else {
+        for (int i = 0; i < U; ++i) {
+          const double v = a[i] - b[i];
+          s = fma(v, v, s);
+        }
+      }
+      return s;
+    };
+    s0 = one(zl0, zh0, nwl0, nwh0);
+    if (two) s1 = one(zl1, zh1, nwl1, nwh1);
+  } else {
+    for (int32_t w = 0; w < nw; w += kTopQueryUnroll) {
+      double a0[kTopQueryUnroll], b0[kTopQueryUnroll], a1[kTopQueryUnroll], b1[kTopQueryUnroll];
 #pragma unroll
-      for (int i = 0; i < kTopQueryUnroll; ++i) a1[i] = w + i < nwl1 ? zl1[(int64_t)(w + i) * kWin] : 0.0;
-    }
+      for (int i = 0; i < kTopQueryUnroll; ++i) a0[i] = w + i < nwl0 ? zl0[(int64_t)(w + i) * kWin] : 0.0;
 #pragma unroll
-    for (int i = 0; i < kTopQueryUnroll; ++i) b1[i] = w + i < nwh1 ? zh1[(int64_t)(w + i) * kWin] : 0.0;
+      for (int i = 0; i < kTopQueryUnroll; ++i) b0[i] = w + i < nwh0 ? zh0[(int64_t)(w + i) * kWin] : 0.0;
+      if (same) {
 #pragma unroll
-    for (int i = 0; i < kTopQueryUnroll; ++i) {
-      const double v0 = a0[i] - b0[i], v1 = a1[i] - b1[i];
-      s0 = fma(v0, v0, s0);
-      s1 = fma(v1, v1, s1);
+        for (int i = 0; i < kTopQueryUnroll; ++i) a1[i] = a0[i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < kTopQueryUnroll; ++i) a1[i] = w + i < nwl1 ? zl1[(int64_t)(w + i) * kWin] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < kTopQueryUnroll; ++i) b1[i] = w + i < nwh1 ? zh1[(int64_t)(w + i) * kWin] : 0.0;
+#pragma unroll
+      for (int i = 0; i < kTopQueryUnroll; ++i) {
+        const double v0 = a0[i] - b0[i], v1 = a1[i] - b1[i];
+        s0 = fma(v0, v0, s0);
+        s1 = fma(v1, v1, s1);
+      }
     }
   }
   s0 = wave_sum(s0);
@@ -823,17 +864,6 @@ __global__ __launch_bounds__(256) void zero_kernel(QueryArgs Q) { zero_body(Q, b
 // launch of the step. A grid smaller than the item count makes the workgroups
 // loop over items with a fixed stride (persistent form). Every item computes
 // exactly what it computes in the factor's own launch.
-
-template <class T>
-__device__ __forceinline__ T load_struct(const T* p) {
-  static_assert(sizeof(T) % 8 == 0, "argument blocks are whole 8-byte words");
-  uint64_t w[sizeof(T) / 8];
-#pragma unroll
-  for (int i = 0; i < (int)(sizeof(T) / 8); ++i) w[i] = load_uniform((const uint64_t*)p + i);
-  T r;
-  __builtin_memcpy(&r, w, sizeof(T));
-  return r;
-}
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void grouped_gemm_kernel(const FactorArgs* __restrict__ fa,
                                                            const GroupItem* __restrict__ items, int64_t nitems) {
