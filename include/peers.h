@@ -149,6 +149,22 @@ typedef struct {
 } peers_sweep_timings;
 peers_status peers_factor_timings(peers_factor f, peers_sweep_timings* out);
 
+/* Columns of Z = D^{-1/2} L^{-1} exactly as one sweep forms them (Section
+ * III-C eq 11; Lemma 3 equates these implicit rows with triangular
+ * substitution), for checking the sweep's intermediate values against an
+ * independent inverse of the factor. For node x = nodes[i] (an original id,
+ * not the ground) with elimination index p and depth dp (root depth 1), row i
+ * of Z_out gets Z_out[i * ld + d] = Z[a_d(p), p] for d < dp, where a_d(p) is
+ * p's ancestor at depth d + 1 (so d = dp - 1 holds the diagonal D_p^{-1/2}),
+ * and zeros for dp <= d < ld. Columns of bottom-subtree nodes are staged by a
+ * sweep that runs only the subtrees holding them; top columns come from the
+ * top store. Z_out: host memory, k * ld doubles; ld at least the elimination
+ * tree height. Synchronous.
+ * Errors: INVALID_ARG (null, ld below the height, a ground node), NODE_RANGE,
+ * OVER_BUDGET, HIP. */
+peers_status peers_factor_export_columns(peers_factor f, int64_t k, const int32_t* nodes, int64_t ld,
+                                         double* Z_out, void* hip_stream);
+
 /* All-edge effective resistances (Section III-G, eq 12): R_out[e] for every
  * input edge e in input order (m values; self-loops give +0.0). */
 peers_status peers_query_all_edges(peers_factor f, double* R_out, uint32_t flags, void* hip_stream);

@@ -24,7 +24,10 @@ on the grounded Laplacian ``L_r`` of ``L_G = sum_e w_e e_e e_e^T`` (eq 1), with
              spanning-tree enumeration (Kirchhoff), for tiny graphs
   symbolic   elimination tree, factor pattern, supernodes and reach sets from their
              definitions (Lemma 1, Definition 2, Algorithm 3)
+  factor     oracles that take a factor L D L^T as data: per-pair LSolve (the
+             paper's accuracy protocol, Section V-A) and the dense columns of
+             Z = D^{-1/2} L^{-1} that the sweep produces implicitly (Lemma 3)
 """
-from . import laplacian, dense, sparse, exact, symbolic  # noqa: F401
+from . import laplacian, dense, sparse, exact, symbolic, factor  # noqa: F401
 
-__all__ = ["laplacian", "dense", "sparse", "exact", "symbolic"]
+__all__ = ["laplacian", "dense", "sparse", "exact", "symbolic", "factor"]

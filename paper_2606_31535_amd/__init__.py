@@ -108,6 +108,7 @@ SIGNATURES = {
     "peers_factor_release": (None, [_vp]),
     "peers_factor_footprint": (C.c_int, [_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     "peers_factor_timings": (C.c_int, [_vp, C.POINTER(peers_sweep_timings)]),
+    "peers_factor_export_columns": (C.c_int, [_vp, C.c_int64, _i32p, C.c_int64, _f64p, _vp]),
     "peers_query_all_edges": (C.c_int, [_vp, _vp, C.c_uint32, _vp]),
     "peers_query": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, C.c_uint32, _vp]),
     "peers_batch_query": (C.c_int, [_vp, C.c_int32, C.POINTER(_vp), _i64p, C.POINTER(_vp),
@@ -280,6 +281,16 @@ def peers_factor_timings(f) -> dict:
     o = peers_sweep_timings()
     _check(lib().peers_factor_timings(f, C.byref(o)), "peers_factor_timings")
     return o.as_dict()
+
+
+def peers_factor_export_columns(f, nodes, ld, stream=None):
+    """Columns of Z = D^{-1/2} L^{-1} as one sweep forms them, depth-indexed (k x ld)."""
+    nodes = _i32(nodes)
+    Z = np.empty((nodes.shape[0], int(ld)), np.float64)
+    _check(lib().peers_factor_export_columns(f, int(nodes.shape[0]), _ptr(nodes, C.c_int32), int(ld),
+                                             _ptr(Z, C.c_double), _stream_handle(stream)),
+           "peers_factor_export_columns")
+    return Z
 
 
 def peers_query_all_edges(f, R_out, flags=0, stream=None):

@@ -482,6 +482,46 @@ peers_status peers_factor_timings(peers_factor f, peers_sweep_timings* out) {
   return PEERS_OK;
 }
 
+peers_status peers_factor_export_columns(peers_factor f, int64_t k, const int32_t* nodes, int64_t ld,
+                                         double* Z_out, void* hip_stream) {
+  if (!f || k < 0 || (k > 0 && (!nodes || !Z_out))) { set_error("null argument"); return PEERS_E_INVALID_ARG; }
+  auto* F = reinterpret_cast<FactorHandle*>(f);
+  hipStream_t s = (hipStream_t)hip_stream;
+  std::lock_guard<std::mutex> g(F->mu);
+  if (ld < F->plan->height) { set_error("ld is below the elimination tree height"); return PEERS_E_INVALID_ARG; }
+  hipError_t he = hipSetDevice(F->dev->ordinal);
+  if (he != hipSuccess) return (peers_status)hip_fail(he, "hipSetDevice");
+  if (k == 0) return PEERS_OK;
+  std::vector<int32_t> xs(k);
+  for (int64_t i = 0; i < k; ++i) {
+    if (nodes[i] < 0 || nodes[i] >= F->n) { set_error("node " + std::to_string(i) + " outside [0, n)"); return PEERS_E_NODE_RANGE; }
+    if (nodes[i] == F->ground) { set_error("the ground node has no column"); return PEERS_E_INVALID_ARG; }
+    xs[i] = perm_index(*F, nodes[i]);
+  }
+  QueryPlan Q;
+  Status st = build_query_plan(F->first, F->depth, *F->plan, 0, nullptr, nullptr, Q, &F->anc, &xs);
+  if (st != OK) return (peers_status)st;
+  DeviceQueryPlan DQ;
+  st = upload_query_plan(*F, Q, DQ, s);
+  if (st == OK) st = ensure_workspace(*F, DQ.nslots, 1, DQ.stage_elems);
+  if (st == OK) st = run_sweep(*F, DQ, (double*)F->res, s, false);
+  for (int64_t i = 0; i < k && st == OK; ++i) {
+    const int32_t dp = F->depth[xs[i]];
+    const double* src = (Q.export_staged[i] ? (const double*)F->stage : (const double*)F->store) + Q.export_off[i];
+    he = hipMemcpyAsync(Z_out + i * ld, src, (size_t)dp * 8, hipMemcpyDeviceToHost, s);
+    if (he != hipSuccess) st = hip_fail(he, "hipMemcpyAsync(columns)");
+  }
+  he = hipStreamSynchronize(s);
+  free_query_plan(*F, DQ);
+  if (st != OK) return (peers_status)st;
+  if (he != hipSuccess) return (peers_status)hip_fail(he, "hipStreamSynchronize");
+  for (int64_t i = 0; i < k; ++i) {
+    const int32_t dp = F->depth[xs[i]];
+    std::fill(Z_out + i * ld + dp, Z_out + (i + 1) * ld, 0.0);
+  }
+  return PEERS_OK;
+}
+
 peers_status peers_query_all_edges(peers_factor f, double* R_out, uint32_t flags, void* hip_stream) {
   if (!f || (!R_out && reinterpret_cast<FactorHandle*>(f)->m > 0)) { set_error("null argument"); return PEERS_E_INVALID_ARG; }
   auto* F = reinterpret_cast<FactorHandle*>(f);

@@ -442,7 +442,7 @@ int32_t AncestorTable::lca(int32_t a, int32_t b) const {
 
 Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int32_t>& depth,
                         const FactorPlan& P, int64_t q, const int32_t* a, const int32_t* b, QueryPlan& Q,
-                        const AncestorTable* anc) {
+                        const AncestorTable* anc, const std::vector<int32_t>* export_nodes) {
   const int32_t N = P.N;
   Q = QueryPlan();
   Q.q = q;
@@ -501,6 +501,17 @@ Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int
       Q.tq_lo.push_back(P.top_index[lo]);
       Q.tq_hi.push_back(hi < 0 ? -1 : P.top_index[hi]);
       Q.tq_out.push_back(k);
+    }
+  }
+  if (export_nodes) {
+    if (stage_of.empty()) stage_of.assign(N, -1);
+    for (int32_t x : *export_nodes) {
+      int64_t off;
+      int32_t staged;
+      column(x, off, staged);
+      Q.export_off.push_back(off);
+      Q.export_staged.push_back((char)staged);
+      if (!staged) gp_top.push_back(x);
     }
   }
   if (!Q.tq_lo.empty()) {

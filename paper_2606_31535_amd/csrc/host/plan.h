@@ -253,14 +253,21 @@ struct QueryPlan {
   // is not every chain, and only those chains' top steps need to run
   std::vector<char> chain_need;
   bool prune_top = false;
+  // columns requested for export (in request order): element offset in the
+  // top store (export_staged 0) or in the staging buffer (1)
+  std::vector<int64_t> export_off;
+  std::vector<char> export_staged;
 };
 
 // a, b: permuted node indices (-1 = ground), per query; out = query number.
 // first/depth: subtree ranges and depths of the postordered elimination tree.
 // anc: ancestor table for non-ancestor pairs; without it such pairs are only
 // counted (n_general) and left out of the plan.
+// export_nodes (optional, permuted indices): columns the sweep must leave in
+// device memory for export (bottom columns are staged, top columns are in
+// the store); their locations land in export_off / export_staged.
 Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int32_t>& depth,
                         const FactorPlan& P, int64_t q, const int32_t* a, const int32_t* b, QueryPlan& Q,
-                        const AncestorTable* anc = nullptr);
+                        const AncestorTable* anc = nullptr, const std::vector<int32_t>* export_nodes = nullptr);
 
 }  // namespace peers

@@ -15,7 +15,7 @@ import scipy.sparse as sp
 
 import synth
 import paper_2606_31535_amd as P
-from oracle import symbolic, laplacian
+from oracle import symbolic, laplacian, dense, factor
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -97,6 +97,27 @@ def test_factor_reproduces_grounded_laplacian(name):
     assert np.all(Lx <= 0)
     colsum = np.asarray(-sp.csc_matrix((Lx, (ex["rowidx"], cols)), shape=(N, N)).sum(axis=0)).ravel()
     assert np.all(colsum <= 1 + 1e-12)
+
+
+@pytest.mark.parametrize("name", ["mesh32", "rand"])
+def test_library_factor_through_lsolve(name):
+    # the paper's accuracy protocol on the library's own host factor: per-pair
+    # triangular solves with the exported L and D against the dense oracle
+    g = GRAPHS[name]()
+    h = _create(g)
+    ex = P.peers_graph_export_symbolic(h)
+    Lx, D = P.peers_graph_export_factor(h)
+    P.peers_graph_destroy(h)
+    L = factor.unit_lower(g.n - 1, ex["colptr"], ex["rowidx"], Lx)
+    rng = np.random.default_rng(3)
+    sel = rng.choice(g.m, size=min(200, g.m), replace=False)
+    qu = np.concatenate([g.eu[sel], rng.integers(0, g.n, 40)])
+    qv = np.concatenate([g.ev[sel], np.full(40, g.ground)])
+    R = factor.resistances_lsolve(g.n, g.ground, ex["perm"], L, D, qu, qv)
+    Ro = dense.resistances(g, qu, qv)
+    nz = Ro > 0
+    assert np.all(R[~nz] == 0.0)
+    assert np.max(np.abs(R[nz] - Ro[nz]) / Ro[nz]) <= 1e-12
 
 
 def test_graph_ordering_without_coordinates():

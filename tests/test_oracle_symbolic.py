@@ -105,3 +105,33 @@ def test_golden_textbook_patterns():
         assert ri.tolist() == case["rowidx"], case["name"]
         assert symbolic.fundamental_supernodes(parent, cp).tolist() == case["snptr"], case["name"]
         assert symbolic.depths(parent).tolist() == case["depth"], case["name"]
+        if "postorder" in case:
+            # children visited in ascending index (the tie-break that makes the
+            # renumbered tree unique); hand-derived visiting order and ids
+            post = symbolic.canonical_postorder(parent)
+            assert post.tolist() == case["postorder"], case["name"]
+            assert perm[post].tolist() == case["postorder_ids"], case["name"]
+
+
+def _postorder_descending(parent):
+    """A plausible mistake: children visited in descending index."""
+    N = parent.shape[0]
+    children = [[] for _ in range(N)]
+    roots = []
+    for i in range(N):
+        (children[parent[i]] if parent[i] >= 0 else roots).append(i)
+    out = []
+
+    def visit(v):
+        for c in sorted(children[v], reverse=True):
+            visit(c)
+        out.append(v)
+    for r in roots:
+        visit(r)
+    return np.array(out, dtype=np.int64)
+
+
+def test_planted_descending_postorder_is_caught(monkeypatch):
+    monkeypatch.setattr(symbolic, "canonical_postorder", _postorder_descending)
+    with pytest.raises(AssertionError):
+        test_golden_textbook_patterns()
