@@ -117,6 +117,11 @@ peers_status peers_device_open(int32_t ordinal, uint64_t hbm_budget_bytes, peers
 void peers_device_close(peers_device d);
 /* Bytes currently held on the device by this library, and the budget. */
 peers_status peers_device_usage(peers_device d, uint64_t* used, uint64_t* budget);
+/* Change the HBM budget (0 = 90% of the device memory). Later reservations
+ * (uploads, per-call workspaces, server batch arenas) are checked against the
+ * new value; nothing already held is freed. Errors: OVER_BUDGET when the
+ * library already holds more than the new budget (the budget is unchanged). */
+peers_status peers_device_set_budget(peers_device d, uint64_t hbm_budget_bytes);
 
 /* Upload a graph's sweep data to HBM (the factor in the device layout, the
  * schedule and the resident edge-query plan). Errors: OVER_BUDGET, HIP. */
@@ -235,15 +240,41 @@ typedef struct {
   uint64_t submitted, completed, rejected, batches;
   double p50_us, p99_us, max_us;   /* submit -> result latency */
   double resistances_per_s;        /* completed pairs / busy wall time */
+  uint64_t memory_waits;           /* batches put back in the queue until memory freed up */
+  uint64_t arena_bytes;            /* device bytes the streams' batch arenas hold now */
+  uint64_t pending;                /* requests waiting in the queue now */
 } peers_server_stats;
 
+/* Start a server on device d. One worker thread forms batches from the
+ * queue; each batch runs on one of `streams` HIP streams with its own arena
+ * (query plans, launch layout, partial slots, staging and results), reserved
+ * against the device's HBM budget when the batch is formed. A batch that does
+ * not fit while other batches run waits at the head of the queue until one
+ * completes; idle streams give their arenas back to the budget. */
 peers_status peers_server_start(peers_device d, const peers_server_opts* opts, peers_server* out);
-/* Enqueue q pairs (original ids) against a resident factor; R_out (host, length
- * q) must stay valid until peers_server_wait returns for the ticket. */
+/* Enqueue q pairs (original ids) against a resident factor. The ids are
+ * copied. R_out (host, length q) is written by the library when the request's
+ * batch completes: it must stay valid until peers_server_wait returns for the
+ * ticket with a finished status, or until peers_server_cancel returns.
+ * peers_factor_release waits for the factor's queued and running requests.
+ * Errors: INVALID_ARG, NODE_RANGE, BUSY (queue_capacity requests already
+ * wait), CANCELLED (the server is stopping). */
 peers_status peers_server_submit(peers_server s, peers_factor f, int64_t q, const int32_t* qu,
                                  const int32_t* qv, double* R_out, uint64_t* ticket);
-/* Wait for a ticket; timeout_us < 0 waits forever. *result gets the request's status. */
+/* Wait for a ticket; timeout_us < 0 waits forever. On PEERS_OK, *result gets
+ * the request's status (PEERS_OK: R_out holds the results; OVER_BUDGET: it
+ * cannot fit even an idle device; CANCELLED) and the ticket is retired.
+ * PEERS_E_TIMEOUT: the request is still queued or running and may still
+ * write R_out; wait again or cancel it. Several threads may wait on one
+ * ticket. */
 peers_status peers_server_wait(peers_server s, uint64_t ticket, int64_t timeout_us, peers_status* result);
+/* Cancel a request. After this returns the library never writes the
+ * request's R_out: a queued request leaves the queue, a running one finishes
+ * without its results being copied out; either way its status becomes
+ * PEERS_E_CANCELLED (a request that had already finished keeps its status).
+ * The ticket stays valid for peers_server_wait. Errors: INVALID_ARG (unknown
+ * ticket). */
+peers_status peers_server_cancel(peers_server s, uint64_t ticket);
 peers_status peers_server_stats_get(peers_server s, peers_server_stats* out);
 peers_status peers_server_stop(peers_server s);
 

@@ -82,7 +82,8 @@ class peers_server_opts(C.Structure):
 class peers_server_stats(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("rejected", C.c_uint64),
                 ("batches", C.c_uint64), ("p50_us", C.c_double), ("p99_us", C.c_double),
-                ("max_us", C.c_double), ("resistances_per_s", C.c_double)]
+                ("max_us", C.c_double), ("resistances_per_s", C.c_double), ("memory_waits", C.c_uint64),
+                ("arena_bytes", C.c_uint64), ("pending", C.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -104,6 +105,7 @@ SIGNATURES = {
     "peers_device_open": (C.c_int, [C.c_int32, C.c_uint64, C.POINTER(_vp)]),
     "peers_device_close": (None, [_vp]),
     "peers_device_usage": (C.c_int, [_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+    "peers_device_set_budget": (C.c_int, [_vp, C.c_uint64]),
     "peers_factor_upload": (C.c_int, [_vp, _vp, _vp, C.POINTER(_vp)]),
     "peers_factor_release": (None, [_vp]),
     "peers_factor_footprint": (C.c_int, [_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
@@ -117,6 +119,7 @@ SIGNATURES = {
     "peers_server_start": (C.c_int, [_vp, C.POINTER(peers_server_opts), C.POINTER(_vp)]),
     "peers_server_submit": (C.c_int, [_vp, _vp, C.c_int64, _i32p, _i32p, _f64p, C.POINTER(C.c_uint64)]),
     "peers_server_wait": (C.c_int, [_vp, C.c_uint64, C.c_int64, C.POINTER(C.c_int)]),
+    "peers_server_cancel": (C.c_int, [_vp, C.c_uint64]),
     "peers_server_stats_get": (C.c_int, [_vp, C.POINTER(peers_server_stats)]),
     "peers_server_stop": (C.c_int, [_vp]),
     "peers_status_string": (C.c_char_p, [C.c_int]),
@@ -170,13 +173,66 @@ def _stream_handle(stream):
     raise TypeError("stream must be None, an int hipStream_t or a torch stream")
 
 
-def _buf_ptr(x):
-    """(pointer, is_device) of a numpy array or torch tensor."""
+# edge count of every factor uploaded through this binding (all-edge outputs
+# are checked against it); dropped on release
+_FACTOR_EDGES = {}
+
+
+def _is_tensor(x):
+    return hasattr(x, "data_ptr") and hasattr(x, "is_contiguous") and not isinstance(x, np.ndarray)
+
+
+def _ids(x, name):
+    """(pointer, is_device, keep-alive object, length) of a 1-D node-id array.
+
+    Host arrays of any integer type are converted to contiguous int32 (ids
+    that do not fit raise); torch tensors are passed as they are and must be
+    contiguous 1-D int32, since a device tensor cannot be converted here
+    without a copy the caller would not see.
+    """
+    if _is_tensor(x):
+        if x.dim() != 1 or not x.is_contiguous() or str(x.dtype) != "torch.int32":
+            raise ValueError(f"{name}: a tensor of node ids must be contiguous 1-D torch.int32 "
+                             f"(got {x.dtype}, shape {tuple(x.shape)})")
+        return int(x.data_ptr()), bool(x.is_cuda), x, int(x.shape[0])
+    a = np.asarray(x)
+    if a.ndim != 1:
+        raise ValueError(f"{name}: node ids must be a 1-D array")
+    if a.dtype != np.int32:
+        if a.size and not np.issubdtype(a.dtype, np.integer):
+            raise ValueError(f"{name}: node ids must be integers (got {a.dtype})")
+        b = a.astype(np.int32)
+        if not np.array_equal(b, a):
+            raise ValueError(f"{name}: node ids do not fit 32 bits")
+        a = b
+    a = np.ascontiguousarray(a)
+    return a.ctypes.data, False, a, int(a.shape[0])
+
+
+def _out(x, n, name):
+    """(pointer, is_device) of a resistance output: contiguous 1-D float64 of length n."""
+    if _is_tensor(x):
+        if str(x.dtype) != "torch.float64" or x.dim() != 1 or not x.is_contiguous():
+            raise ValueError(f"{name}: output tensor must be contiguous 1-D torch.float64 "
+                             f"(got {x.dtype}, shape {tuple(x.shape)})")
+        if int(x.shape[0]) != n:
+            raise ValueError(f"{name}: output holds {int(x.shape[0])} values, the call writes {n}")
+        return int(x.data_ptr()), bool(x.is_cuda)
     if isinstance(x, np.ndarray):
+        if x.dtype != np.float64 or x.ndim != 1 or not x.flags.c_contiguous or not x.flags.writeable:
+            raise ValueError(f"{name}: output array must be writeable contiguous 1-D float64 "
+                             f"(got {x.dtype}, shape {x.shape})")
+        if x.shape[0] != n:
+            raise ValueError(f"{name}: output holds {x.shape[0]} values, the call writes {n}")
         return x.ctypes.data, False
-    if hasattr(x, "data_ptr"):
-        return int(x.data_ptr()), bool(getattr(x, "is_cuda", False))
-    raise TypeError("expected a numpy array or a torch tensor")
+    raise TypeError(f"{name}: expected a numpy array or a torch tensor")
+
+
+def _factor_edges(f):
+    key = f.value if isinstance(f, C.c_void_p) else int(f)
+    if key not in _FACTOR_EDGES:
+        raise ValueError("unknown factor handle (upload factors with peers_factor_upload)")
+    return _FACTOR_EDGES[key]
 
 
 # --------------------------------------------------------------------------- graph
@@ -260,14 +316,21 @@ def peers_device_usage(d):
     return used.value, budget.value
 
 
+def peers_device_set_budget(d, hbm_budget_bytes):
+    _check(lib().peers_device_set_budget(d, int(hbm_budget_bytes)), "peers_device_set_budget")
+
+
 def peers_factor_upload(d, g, stream=None):
+    m = peers_graph_stats_get(g)["m"]
     h = _vp()
     _check(lib().peers_factor_upload(d, g, _stream_handle(stream), C.byref(h)), "peers_factor_upload")
+    _FACTOR_EDGES[h.value] = int(m)
     return h
 
 
 def peers_factor_release(f):
     if f:
+        _FACTOR_EDGES.pop(f.value if isinstance(f, C.c_void_p) else int(f), None)
         lib().peers_factor_release(f)
 
 
@@ -294,7 +357,7 @@ def peers_factor_export_columns(f, nodes, ld, stream=None):
 
 
 def peers_query_all_edges(f, R_out, flags=0, stream=None):
-    p, dev = _buf_ptr(R_out)
+    p, dev = _out(R_out, _factor_edges(f), "R_out")
     if dev:
         flags |= PEERS_OUT_DEVICE
     _check(lib().peers_query_all_edges(f, p, flags, _stream_handle(stream)), "peers_query_all_edges")
@@ -302,16 +365,17 @@ def peers_query_all_edges(f, R_out, flags=0, stream=None):
 
 
 def peers_query(f, qu, qv, R_out, flags=0, stream=None):
-    pu, du = _buf_ptr(qu)
-    pv, dv = _buf_ptr(qv)
-    pr, dr = _buf_ptr(R_out)
+    pu, du, ku, q = _ids(qu, "qu")
+    pv, dv, kv, qv_len = _ids(qv, "qv")
+    if q != qv_len:
+        raise ValueError(f"qu has {q} ids and qv {qv_len}")
+    pr, dr = _out(R_out, q, "R_out")
     if du != dv:
         raise ValueError("qu and qv must live on the same side")
     if du:
         flags |= PEERS_IN_DEVICE
     if dr:
         flags |= PEERS_OUT_DEVICE
-    q = int(qu.shape[0])
     _check(lib().peers_query(f, q, pu, pv, pr, flags, _stream_handle(stream)), "peers_query")
     return R_out
 
@@ -325,26 +389,36 @@ def peers_batch_query(d, factors, qus, qvs, R_outs, flags=0, stream=None):
     va = (_vp * nb)()
     ra = (_vp * nb)()
     devs = set()
+    ins = set()
+    keep = []
     for i in range(nb):
         if qus[i] is None:
             ua[i] = None
             va[i] = None
             qa[i] = 0
+            n_out = _factor_edges(factors[i])
         else:
-            pu, du = _buf_ptr(qus[i])
-            pv, dv = _buf_ptr(qvs[i])
-            if du or dv:
-                flags |= PEERS_IN_DEVICE
+            pu, du, ku, q = _ids(qus[i], f"qus[{i}]")
+            pv, dv, kv, q2 = _ids(qvs[i], f"qvs[{i}]")
+            if q != q2:
+                raise ValueError(f"qus[{i}] has {q} ids and qvs[{i}] {q2}")
+            keep += [ku, kv]
+            ins.update((du, dv))
             ua[i] = pu
             va[i] = pv
-            qa[i] = int(qus[i].shape[0])
-        p, dev = _buf_ptr(R_outs[i])
+            qa[i] = q
+            n_out = q
+        p, dev = _out(R_outs[i], n_out, f"R_outs[{i}]")
         ra[i] = p
         devs.add(dev)
         if dev:
             flags |= PEERS_OUT_DEVICE
     if len(devs) > 1:
         raise ValueError("all outputs of a batch must be host arrays or all device tensors")
+    if len(ins) > 1:
+        raise ValueError("all pair lists of a batch must be host arrays or all device tensors")
+    if True in ins:
+        flags |= PEERS_IN_DEVICE
     _check(lib().peers_batch_query(d, nb, fa, qa, ua, va, ra, flags, _stream_handle(stream)), "peers_batch_query")
     return R_outs
 
@@ -363,17 +437,31 @@ def peers_server_start(d, max_batch_pairs=0, max_wait_us=0, queue_capacity=0, st
 
 
 def peers_server_submit(s, f, qu, qv, R_out):
-    qu, qv = _i32(qu), _i32(qv)
+    """Enqueue a request; R_out (host float64, length q) must stay alive until a
+    peers_server_wait on the ticket returns PEERS_OK (or the server stops)."""
+    pu, du, ku, q = _ids(qu, "qu")
+    pv, dv, kv, q2 = _ids(qv, "qv")
+    if du or dv:
+        raise ValueError("server requests take host node ids")
+    if q != q2:
+        raise ValueError(f"qu has {q} ids and qv {q2}")
+    pr, dr = _out(R_out, q, "R_out")
+    if dr:
+        raise ValueError("server results go to host memory")
     t = C.c_uint64()
-    _check(lib().peers_server_submit(s, f, int(qu.shape[0]), _ptr(qu, C.c_int32), _ptr(qv, C.c_int32),
-                                     _ptr(R_out, C.c_double), C.byref(t)), "peers_server_submit")
-    return t.value, (qu, qv)
+    _check(lib().peers_server_submit(s, f, q, C.cast(pu, _i32p), C.cast(pv, _i32p), C.cast(pr, _f64p),
+                                     C.byref(t)), "peers_server_submit")
+    return t.value, (ku, kv, R_out)
 
 
 def peers_server_wait(s, ticket, timeout_us=-1):
     r = C.c_int()
     st = lib().peers_server_wait(s, int(ticket), int(timeout_us), C.byref(r))
     return st, r.value
+
+
+def peers_server_cancel(s, ticket):
+    _check(lib().peers_server_cancel(s, int(ticket)), "peers_server_cancel")
 
 
 def peers_server_stats_get(s) -> dict:

@@ -16,6 +16,10 @@ struct BatchEntry {
   FactorHandle* F = nullptr;
   const DeviceQueryPlan* plan = nullptr;
   double* R_dev = nullptr;  // results of the entry's plan (device)
+  // partial slots and staging of this entry; null = the factor's own
+  // workspace (the served form gives every batch workspaces of its own)
+  double* part = nullptr;
+  double* stage = nullptr;
 };
 
 struct BatchStage {

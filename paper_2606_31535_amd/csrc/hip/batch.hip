@@ -46,8 +46,8 @@ void batch_layout(const DeviceHandle& D, const std::vector<BatchEntry>& E, Batch
     L.fargs[i].g = F.gemm;
     L.fargs[i].a = F.sweep;
     L.fargs[i].q = E[i].plan->args;
-    L.fargs[i].q.part = (double*)F.part;
-    L.fargs[i].q.stage = (double*)F.stage;
+    L.fargs[i].q.part = E[i].part ? E[i].part : (double*)F.part;
+    L.fargs[i].q.stage = E[i].stage ? E[i].stage : (double*)F.stage;
     L.fargs[i].q.R = E[i].R_dev;
   }
   std::vector<GroupItem>& items = L.items;

@@ -4,10 +4,12 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cstring>
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 
 #include "../../../include/peers.h"
 #include "../host/graph_handle.h"
@@ -273,6 +275,19 @@ peers_status peers_device_usage(peers_device d, uint64_t* used, uint64_t* budget
   return PEERS_OK;
 }
 
+peers_status peers_device_set_budget(peers_device d, uint64_t hbm_budget_bytes) {
+  if (!d) { set_error("null device"); return PEERS_E_INVALID_ARG; }
+  auto* D = reinterpret_cast<DeviceHandle*>(d);
+  std::lock_guard<std::mutex> g(D->mu);
+  const uint64_t b = hbm_budget_bytes ? std::min<uint64_t>(hbm_budget_bytes, D->total) : (uint64_t)(0.9 * (double)D->total);
+  if (D->used > b) {
+    set_error("the library holds " + std::to_string(D->used) + " bytes, more than the new budget " + std::to_string(b));
+    return PEERS_E_OVER_BUDGET;
+  }
+  D->budget = b;
+  return PEERS_OK;
+}
+
 peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream, peers_factor* out) {
   if (!d || !g || !out) { set_error("null argument"); return PEERS_E_INVALID_ARG; }
   *out = nullptr;
@@ -430,6 +445,9 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
 void peers_factor_release(peers_factor f) {
   if (!f) return;
   auto* F = reinterpret_cast<FactorHandle*>(f);
+  // server requests on this factor (queued or running) finish first
+  while (F->server_refs.load() > 0) std::this_thread::sleep_for(std::chrono::microseconds(100));
+  { std::lock_guard<std::mutex> g(F->mu); }  // a plain or batched call on it has returned
   (void)hipSetDevice(F->dev->ordinal);
   (void)hipDeviceSynchronize();
   batch_cache_forget(*F->dev, F);

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <memory>
 #include <mutex>
 #include <vector>
@@ -69,7 +70,10 @@ struct FactorHandle {
   void* stage = nullptr;  // staged bottom columns of non-ancestor pairs
   uint64_t resident_bytes = 0, store_bytes = 0, part_bytes = 0, res_bytes = 0, stage_bytes = 0, reserved = 0;
   DeviceQueryPlan edges;  // all-edge queries, resident
-  std::mutex mu;          // one sweep at a time per factor (shared top store)
+  std::mutex mu;          // one sweep at a time on the factor's own workspace (part/res/stage)
+  // requests of any server that are queued or on the device for this factor;
+  // release waits for them
+  std::atomic<int64_t> server_refs{0};
   // per-phase timing of the last profiled sweep
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool timed = false;

@@ -5,15 +5,26 @@
 // stream: a batch takes the pending requests (oldest first, up to a pair cap),
 // merges those of the same factor into one pruned query plan, and runs the
 // plans of all its factors as one grouped launch sequence (the batched form's
-// steps). Requests that arrive while batches are on the device wait for the
-// next free slot, so work from different requests overlaps on the device.
-// Each factor is in at most one batch at a time (it has one top store and
-// one workspace). Every result is the same bits as the request run alone:
-// the plan computes each pair independently of the other pairs in it.
+// steps). Requests that arrive while batches are on the device go into the
+// next batch that a free stream forms, so work from different requests
+// overlaps on the device.
 //
-// Admission: factors are admitted when uploaded (their footprint against the
-// device's HBM budget); a batch's plans, partial slots and staging must also
-// fit the budget, else its requests fail with PEERS_E_OVER_BUDGET.
+// One factor may be in several batches at once. Each batch has its own
+// partial slots, staging and result buffers (in its stream's arena); the only
+// factor memory two batches share is the top store, and every sweep writes
+// the same values there (each top column is formed from the factor alone, in
+// a fixed order), so overlapping sweeps of one factor read exactly the values
+// a lone sweep reads. Every result is therefore the same bits as the request
+// run alone: the plan computes each pair independently of the other pairs.
+//
+// Admission by memory: factors are admitted at upload (their footprint
+// against the device's HBM budget). A batch's arena (plans, launch layout,
+// workspaces) is reserved against the same budget when the batch is formed.
+// If it does not fit while other batches are on the device, its requests go
+// back to the head of the queue and wait until a batch completes and frees
+// memory; idle streams give their arenas back. A batch that does not fit on
+// an otherwise idle device is cut to its first request, and only a single
+// request that cannot fit an idle device fails with PEERS_E_OVER_BUDGET.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,6 +50,9 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// an idle stream keeps its arena this long before giving it back to the budget
+constexpr auto kArenaIdleRelease = std::chrono::milliseconds(20);
+
 struct Request {
   uint64_t ticket = 0;
   FactorHandle* F = nullptr;
@@ -48,24 +62,28 @@ struct Request {
   Clock::time_point t_submit;
   peers_status status = PEERS_OK;
   bool done = false;
+  bool cancelled = false;  // results are not copied out
+  bool on_device = false;  // taken into a batch
 };
+using ReqPtr = std::shared_ptr<Request>;
 
 struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t ev = nullptr;
-  void* arena = nullptr;  // plans and batch layout of the batch in flight
+  void* arena = nullptr;  // plans, batch layout and workspaces of the batch in flight
   uint64_t arena_bytes = 0;
   double* pinned = nullptr;  // results, device -> host
   int64_t pinned_elems = 0;
   bool busy = false;
-  std::vector<Request*> reqs;
+  Clock::time_point idle_since = Clock::now();
+  std::vector<ReqPtr> reqs;
   std::vector<int64_t> req_off;  // each request's first result in `pinned`
-  std::vector<FactorHandle*> factors;
-  std::vector<std::unique_lock<std::mutex>> locks;
   std::vector<QueryPlan> hplans;
   std::vector<DeviceQueryPlan> dplans;
   BatchLayout L;
 };
+
+enum class Launch { Started, WaitForMemory, TooBig, Failed };
 
 }  // namespace
 
@@ -74,15 +92,15 @@ struct Server {
   peers_server_opts o{};
   std::mutex mu;
   std::condition_variable cv_req, cv_done;
-  std::deque<Request*> pending;
-  std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
+  std::deque<ReqPtr> pending;
+  std::unordered_map<uint64_t, ReqPtr> reqs;
   uint64_t next_ticket = 1;
   bool stopping = false;
+  bool mem_blocked = false;  // the head batch waits for a batch to complete
   std::vector<Slot> slots;
-  std::set<const FactorHandle*> in_flight;
   std::thread worker;
   // statistics
-  uint64_t submitted = 0, completed = 0, rejected = 0, batches = 0, pairs_done = 0;
+  uint64_t submitted = 0, completed = 0, rejected = 0, batches = 0, pairs_done = 0, memory_waits = 0;
   std::vector<double> lat_us;
   double busy_s = 0;
   Clock::time_point busy_since;
@@ -91,25 +109,47 @@ struct Server {
 
 namespace {
 
-// Grows a device buffer (budgeted); growth only, so steady serving allocates nothing.
-Status grow_device(DeviceHandle& D, void*& buf, uint64_t& have, uint64_t need, const char* what) {
-  if (need <= have) return OK;
-  need = std::max<uint64_t>(need, have + have / 2);
-  if (buf) {
-    (void)hipFree(buf);
-    D.release(have);
-    buf = nullptr;
-    have = 0;
+uint64_t align256(uint64_t x) { return (x + 255) / 256 * 256; }
+
+void free_arena(Server& S, Slot& sl) {
+  if (!sl.arena) return;
+  (void)hipFree(sl.arena);
+  S.D->release(sl.arena_bytes);
+  sl.arena = nullptr;
+  sl.arena_bytes = 0;
+}
+
+// Makes the slot's arena at least `need` bytes (budgeted). On a budget
+// refusal, idle slots give their arenas back and the reservation is tried
+// again; the result says whether it is worth waiting for busy slots.
+Launch reserve_arena(Server& S, Slot& sl, uint64_t need, Status& err) {
+  if (need <= sl.arena_bytes) return Launch::Started;
+  free_arena(S, sl);
+  need = std::max<uint64_t>(need, 1 << 20);
+  Status st = S.D->reserve(need);
+  if (st == E_OVER_BUDGET) {
+    for (Slot& o : S.slots)
+      if (&o != &sl && !o.busy) free_arena(S, o);
+    st = S.D->reserve(need);
   }
-  Status st = D.reserve(need);
-  if (st != OK) return st;
-  hipError_t e = hipMalloc(&buf, need);
+  if (st == E_OVER_BUDGET) {
+    for (Slot& o : S.slots)
+      if (&o != &sl && o.busy) return Launch::WaitForMemory;
+    err = st;
+    return Launch::TooBig;
+  }
+  if (st != OK) {
+    err = st;
+    return Launch::Failed;
+  }
+  hipError_t e = hipMalloc(&sl.arena, need);
   if (e != hipSuccess) {
-    D.release(need);
-    return hip_fail(e, what);
+    S.D->release(need);
+    err = hip_fail(e, "hipMalloc(server arena)");
+    return Launch::Failed;
   }
-  have = need;
-  return OK;
+  sl.arena_bytes = need;
+  return Launch::Started;
 }
 
 Status grow_pinned(Slot& sl, int64_t need) {
@@ -124,11 +164,14 @@ Status grow_pinned(Slot& sl, int64_t need) {
   return OK;
 }
 
+// (server lock held)
 void finish_request(Server& S, Request* r, peers_status st) {
-  r->status = st;
+  if (r->done) return;
+  r->status = r->cancelled && st == PEERS_OK ? PEERS_E_CANCELLED : st;
   r->done = true;
+  r->F->server_refs.fetch_sub(1);
   const double us = std::chrono::duration<double, std::micro>(Clock::now() - r->t_submit).count();
-  if (st == PEERS_OK) {
+  if (r->status == PEERS_OK) {
     S.completed++;
     S.pairs_done += (uint64_t)r->q;
     S.lat_us.push_back(us);
@@ -138,36 +181,35 @@ void finish_request(Server& S, Request* r, peers_status st) {
 }
 
 // Builds and launches one batch on a free slot (worker thread, server lock
-// not held). Requests whose factor could not be planned fail individually.
-void launch(Server& S, Slot& sl, std::vector<Request*> take) {
+// not held). Requests whose factor could not be planned fail individually
+// (reported through `failed`); a batch that does not fit the budget is not
+// launched and its requests stay with the caller.
+Launch launch(Server& S, Slot& sl, const std::vector<ReqPtr>& take,
+              std::vector<std::pair<ReqPtr, peers_status>>& failed, Status& err) {
   sl.reqs.clear();
   sl.req_off.clear();
-  sl.factors.clear();
   sl.hplans.clear();
   sl.dplans.clear();
   // group by factor, keeping submission order inside each factor
-  std::map<FactorHandle*, std::vector<Request*>> groups;
+  std::map<FactorHandle*, std::vector<ReqPtr>> groups;
   std::vector<FactorHandle*> forder;
-  for (Request* r : take) {
+  for (const ReqPtr& r : take) {
     if (!groups.count(r->F)) forder.push_back(r->F);
     groups[r->F].push_back(r);
   }
-  std::vector<std::pair<Request*, peers_status>> failed;
-  std::vector<FactorHandle*> planned;
-  int64_t total = 0;
   // host plans of the factors, in parallel (independent per factor)
   const size_t nf = forder.size();
   std::vector<QueryPlan> plans(nf);
   std::vector<Status> pst(nf, OK);
   auto plan_one = [&](size_t i) {
     FactorHandle* F = forder[i];
-    const std::vector<Request*>& G = groups[F];
+    const std::vector<ReqPtr>& G = groups.at(F);
     int64_t q = 0;
-    for (Request* r : G) q += r->q;
+    for (const ReqPtr& r : G) q += r->q;
     std::vector<int32_t> a, b;
     a.reserve(q);
     b.reserve(q);
-    for (Request* r : G) {
+    for (const ReqPtr& r : G) {
       a.insert(a.end(), r->a.begin(), r->a.end());
       b.insert(b.end(), r->b.begin(), r->b.end());
     }
@@ -179,108 +221,111 @@ void launch(Server& S, Slot& sl, std::vector<Request*> take) {
     if (nf) plan_one(0);
     for (auto& t : th) t.join();
   }
+  std::vector<FactorHandle*> planned;
+  std::vector<ReqPtr> reqs;
+  std::vector<int64_t> req_off;
+  int64_t total = 0;
   for (size_t i = 0; i < nf; ++i) {
     FactorHandle* F = forder[i];
-    std::vector<Request*>& G = groups[F];
-    Status st = pst[i];
-    if (st == OK) st = ensure_workspace(*F, plans[i].nslots, plans[i].q, plans[i].stage_elems);
-    if (st != OK) {
-      for (Request* r : G) failed.push_back({r, (peers_status)st});
+    if (pst[i] != OK) {
+      for (const ReqPtr& r : groups[F]) failed.push_back({r, (peers_status)pst[i]});
       continue;
     }
     sl.hplans.push_back(std::move(plans[i]));
     planned.push_back(F);
-    for (Request* r : G) {
-      sl.reqs.push_back(r);
-      sl.req_off.push_back(total);
+    for (const ReqPtr& r : groups[F]) {
+      reqs.push_back(r);
+      req_off.push_back(total);
       total += r->q;
     }
   }
-  // device image: plans, then the batch layout
-  std::vector<uint64_t> poff;
+  if (planned.empty()) return Launch::Started;  // nothing left to run
+  // arena: plans, then the batch layout, then per-plan workspaces
+  // (partial slots, results, staging)
+  const size_t np = planned.size();
+  std::vector<uint64_t> poff(np), woff(np);
   uint64_t bytes = 0;
-  for (const QueryPlan& Q : sl.hplans) {
-    poff.push_back(bytes);
-    bytes += (query_plan_bytes(Q) + 255) / 256 * 256;
+  for (size_t i = 0; i < np; ++i) {
+    poff[i] = bytes;
+    bytes += align256(query_plan_bytes(sl.hplans[i]));
   }
-  sl.dplans.resize(sl.hplans.size());
-  Status st = OK;
-  if (!planned.empty()) {
-    // the layout needs the plans' device addresses: size it with a first pass
-    std::vector<BatchEntry> be;
-    for (size_t i = 0; i < planned.size(); ++i) be.push_back(BatchEntry{planned[i], &sl.dplans[i], nullptr});
-    for (size_t i = 0; i < planned.size(); ++i) {
-      // host-side plan fields (counts, work lists) are what the layout reads
-      DeviceQueryPlan& d = sl.dplans[i];
-      d.work_task = sl.hplans[i].work_task;
-      d.work_win = sl.hplans[i].work_win;
-      d.args.nbq = sl.hplans[i].nbq();
-      d.args.ntq = (int64_t)sl.hplans[i].tq_out.size();
-      d.args.nzero = (int64_t)sl.hplans[i].zero_out.size();
-      d.args.ngp = (int64_t)sl.hplans[i].gp.size();
-    }
-    BatchLayout probe;
-    batch_layout(*S.D, be, probe);
-    const uint64_t need = bytes + probe.bytes;
-    st = grow_device(*S.D, sl.arena, sl.arena_bytes, need, "hipMalloc(server arena)");
-    if (st == OK) st = grow_pinned(sl, std::max<int64_t>(total, 1));
-    for (size_t i = 0; i < planned.size() && st == OK; ++i)
-      st = upload_query_plan_to(sl.hplans[i], sl.dplans[i], (char*)sl.arena + poff[i], sl.stream);
-    if (st == OK) {
-      for (size_t i = 0; i < planned.size(); ++i) be[i].R_dev = (double*)planned[i]->res;
-      batch_layout(*S.D, be, sl.L);
-      st = batch_upload(sl.L, (char*)sl.arena + bytes, sl.stream);
-    }
-    if (st == OK) st = batch_launch(sl.L, (char*)sl.arena + bytes, sl.stream);
-    // results of each factor, in request order, into the pinned buffer
-    int64_t off = 0;
-    for (size_t i = 0; i < planned.size() && st == OK; ++i) {
-      const int64_t q = sl.hplans[i].q;
-      if (q > 0) {
-        hipError_t e = hipMemcpyAsync(sl.pinned + off, planned[i]->res, (size_t)q * 8, hipMemcpyDeviceToHost,
-                                      sl.stream);
-        if (e != hipSuccess) st = hip_fail(e, "hipMemcpyAsync(server results)");
-      }
-      off += q;
-    }
-    if (st == OK) {
-      hipError_t e = hipEventRecord(sl.ev, sl.stream);
-      if (e != hipSuccess) st = hip_fail(e, "hipEventRecord(server)");
-    }
+  sl.dplans.resize(np);
+  std::vector<BatchEntry> be;
+  for (size_t i = 0; i < np; ++i) {
+    // host-side plan fields (counts, work lists) are what the layout reads
+    DeviceQueryPlan& d = sl.dplans[i];
+    d.work_task = sl.hplans[i].work_task;
+    d.work_win = sl.hplans[i].work_win;
+    d.chain_need = sl.hplans[i].chain_need;
+    d.prune_top = sl.hplans[i].prune_top;
+    d.args.nbq = sl.hplans[i].nbq();
+    d.args.ntq = (int64_t)sl.hplans[i].tq_out.size();
+    d.args.nzero = (int64_t)sl.hplans[i].zero_out.size();
+    d.args.ngp = (int64_t)sl.hplans[i].gp.size();
+    be.push_back(BatchEntry{planned[i], &sl.dplans[i], nullptr, nullptr, nullptr});
   }
-  std::lock_guard<std::mutex> g(S.mu);
-  for (auto& fr : failed) finish_request(S, fr.first, fr.second);
+  BatchLayout probe;
+  batch_layout(*S.D, be, probe);
+  const uint64_t layout_off = bytes;
+  bytes += align256(probe.bytes);
+  for (size_t i = 0; i < np; ++i) {
+    const QueryPlan& Q = sl.hplans[i];
+    woff[i] = bytes;
+    bytes += align256((uint64_t)std::max<int64_t>(Q.nslots, 1) * 8) + align256((uint64_t)std::max<int64_t>(Q.q, 1) * 8) +
+             align256((uint64_t)std::max<int64_t>(Q.stage_elems, 1) * 8);
+  }
+  Launch how = reserve_arena(S, sl, bytes, err);
+  if (how != Launch::Started) return how;
+  Status st = grow_pinned(sl, std::max<int64_t>(total, 1));
+  char* ar = (char*)sl.arena;
+  for (size_t i = 0; i < np && st == OK; ++i) {
+    const QueryPlan& Q = sl.hplans[i];
+    st = upload_query_plan_to(Q, sl.dplans[i], ar + poff[i], sl.stream);
+    be[i].part = (double*)(ar + woff[i]);
+    be[i].R_dev = (double*)(ar + woff[i] + align256((uint64_t)std::max<int64_t>(Q.nslots, 1) * 8));
+    be[i].stage = (double*)((char*)be[i].R_dev + align256((uint64_t)std::max<int64_t>(Q.q, 1) * 8));
+  }
+  if (st == OK) {
+    batch_layout(*S.D, be, sl.L);
+    st = batch_upload(sl.L, ar + layout_off, sl.stream);
+  }
+  if (st == OK) st = batch_launch(sl.L, ar + layout_off, sl.stream);
+  // results of each factor, in request order, into the pinned buffer
+  int64_t off = 0;
+  for (size_t i = 0; i < np && st == OK; ++i) {
+    const int64_t q = sl.hplans[i].q;
+    if (q > 0) {
+      hipError_t e = hipMemcpyAsync(sl.pinned + off, be[i].R_dev, (size_t)q * 8, hipMemcpyDeviceToHost, sl.stream);
+      if (e != hipSuccess) st = hip_fail(e, "hipMemcpyAsync(server results)");
+    }
+    off += q;
+  }
+  if (st == OK) {
+    hipError_t e = hipEventRecord(sl.ev, sl.stream);
+    if (e != hipSuccess) st = hip_fail(e, "hipEventRecord(server)");
+  }
   if (st != OK) {
     (void)hipStreamSynchronize(sl.stream);
-    for (Request* r : sl.reqs) finish_request(S, r, (peers_status)st);
-    sl.reqs.clear();
+    for (const ReqPtr& r : reqs) failed.push_back({r, (peers_status)st});
+    return Launch::Started;
   }
-  if (sl.reqs.empty()) {
-    // nothing in flight on this slot: release its factors now
-    for (FactorHandle* F : forder) S.in_flight.erase(F);
-    sl.locks.clear();
-    S.cv_done.notify_all();
-    return;
-  }
-  sl.factors = forder;
-  sl.busy = true;
-  if (S.busy_slots++ == 0) S.busy_since = Clock::now();
-  S.batches++;
-  if (!failed.empty()) S.cv_done.notify_all();
+  sl.reqs = std::move(reqs);
+  sl.req_off = std::move(req_off);
+  return Launch::Started;
 }
 
 // Hands a finished batch's results to its requests (server lock held).
 void complete(Server& S, Slot& sl, hipError_t e) {
   for (size_t i = 0; i < sl.reqs.size(); ++i) {
-    Request* r = sl.reqs[i];
-    if (e == hipSuccess && r->q > 0) std::memcpy(r->R_out, sl.pinned + sl.req_off[i], (size_t)r->q * 8);
+    Request* r = sl.reqs[i].get();
+    if (e == hipSuccess && r->q > 0 && !r->cancelled)
+      std::memcpy(r->R_out, sl.pinned + sl.req_off[i], (size_t)r->q * 8);
     finish_request(S, r, e == hipSuccess ? PEERS_OK : PEERS_E_HIP);
   }
   sl.reqs.clear();
-  for (FactorHandle* F : sl.factors) S.in_flight.erase(F);
-  sl.factors.clear();
-  sl.locks.clear();
   sl.busy = false;
+  sl.idle_since = Clock::now();
+  S.mem_blocked = false;
   if (--S.busy_slots == 0) S.busy_s += std::chrono::duration<double>(Clock::now() - S.busy_since).count();
   S.cv_done.notify_all();
 }
@@ -305,56 +350,85 @@ void run(Server& S) {
         free_slot = &sl;
         break;
       }
-    if (free_slot && !S.pending.empty()) {
+    if (free_slot && !S.pending.empty() && !S.mem_blocked) {
       // while another batch keeps the device busy, let a small batch wait a
       // little for batch-mates
       int64_t pend = 0;
-      for (Request* r : S.pending) pend += r->q;
+      for (const ReqPtr& r : S.pending) pend += r->q;
       const bool young = Clock::now() - S.pending.front()->t_submit < max_wait;
       if (!(S.busy_slots > 0 && pend < cap && young)) {
-        std::vector<Request*> take;
-        std::deque<Request*> keep;
-        std::set<FactorHandle*> claimed;
-        std::vector<std::unique_lock<std::mutex>> locks;
+        std::vector<ReqPtr> take;
         int64_t pairs = 0;
         while (!S.pending.empty()) {
-          Request* r = S.pending.front();
+          const ReqPtr& r = S.pending.front();
+          if (pairs > 0 && pairs + r->q > cap) break;
+          pairs += r->q;
+          r->on_device = true;
+          take.push_back(r);
           S.pending.pop_front();
-          bool ok = pairs == 0 || pairs + r->q <= cap;
-          if (ok && !claimed.count(r->F)) {
-            if (S.in_flight.count(r->F)) ok = false;
-            else {
-              std::unique_lock<std::mutex> fl(r->F->mu, std::try_to_lock);
-              if (fl.owns_lock()) {
-                locks.push_back(std::move(fl));
-                claimed.insert(r->F);
-              } else {
-                ok = false;
-              }
-            }
-          }
-          if (ok) {
-            take.push_back(r);
-            pairs += r->q;
-          } else {
-            keep.push_back(r);
-          }
         }
-        S.pending.swap(keep);
-        if (!take.empty()) {
-          for (FactorHandle* F : claimed) S.in_flight.insert(F);
-          free_slot->locks = std::move(locks);
+        // form and launch without the lock; a batch too large for an idle
+        // device is retried with its first request alone
+        for (;;) {
           lk.unlock();
-          launch(S, *free_slot, std::move(take));
+          std::vector<std::pair<ReqPtr, peers_status>> failed;
+          Status err = OK;
+          const Launch how = launch(S, *free_slot, take, failed, err);
           lk.lock();
-          progressed = true;
+          for (auto& fr : failed) finish_request(S, fr.first.get(), fr.second);
+          if (!failed.empty()) S.cv_done.notify_all();
+          // requests that failed to plan are finished: never queue them again
+          take.erase(std::remove_if(take.begin(), take.end(), [](const ReqPtr& r) { return r->done; }), take.end());
+          if (take.empty() && how != Launch::Started) break;
+          if (how == Launch::Started) {
+            if (!free_slot->reqs.empty()) {
+              free_slot->busy = true;
+              if (S.busy_slots++ == 0) S.busy_since = Clock::now();
+              S.batches++;
+            }
+            break;
+          }
+          if (how == Launch::WaitForMemory || (how == Launch::TooBig && take.size() > 1)) {
+            // back to the head of the queue, in order: all of them when
+            // memory frees up later, all but the first when the batch is
+            // too large even for an idle device
+            const size_t keep = how == Launch::WaitForMemory ? 0 : 1;
+            for (size_t i = take.size(); i > keep; --i) {
+              take[i - 1]->on_device = false;
+              S.pending.push_front(take[i - 1]);
+            }
+            take.resize(keep);
+            if (how == Launch::WaitForMemory) {
+              S.mem_blocked = true;
+              S.memory_waits++;
+              break;
+            }
+            continue;
+          }
+          // a lone request that does not fit, or a failure
+          for (const ReqPtr& r : take) finish_request(S, r.get(), (peers_status)(err != OK ? err : E_OVER_BUDGET));
+          S.cv_done.notify_all();
+          break;
         }
+        progressed = true;
       }
+    }
+    // idle streams give their arenas back to the budget
+    if (S.pending.empty()) {
+      const auto now = Clock::now();
+      for (Slot& sl : S.slots)
+        if (!sl.busy && sl.arena && now - sl.idle_since > kArenaIdleRelease) free_arena(S, sl);
     }
     if (S.stopping && S.pending.empty() && S.busy_slots == 0) break;
     if (!progressed) {
-      if (S.busy_slots > 0 || !S.pending.empty()) S.cv_req.wait_for(lk, std::chrono::microseconds(50));
-      else S.cv_req.wait(lk, [&] { return S.stopping || !S.pending.empty(); });
+      bool arenas = false;
+      for (Slot& sl : S.slots) arenas = arenas || (!sl.busy && sl.arena);
+      if (S.busy_slots > 0 || (!S.pending.empty() && !S.mem_blocked) || arenas)
+        S.cv_req.wait_for(lk, std::chrono::microseconds(50));
+      else if (S.busy_slots == 0 && S.mem_blocked)
+        S.mem_blocked = false;  // nothing on the device: try again
+      else
+        S.cv_req.wait(lk, [&] { return S.stopping || !S.pending.empty(); });
     }
   }
 }
@@ -413,7 +487,7 @@ peers_status peers_server_submit(peers_server s, peers_factor f, int64_t q, cons
   auto* S = reinterpret_cast<Server*>(s);
   auto* F = reinterpret_cast<FactorHandle*>(f);
   if (F->dev != S->D) { set_error("factor is on another device"); return PEERS_E_INVALID_ARG; }
-  std::unique_ptr<Request> r(new Request());
+  auto r = std::make_shared<Request>();
   r->F = F;
   r->q = q;
   r->R_out = R_out;
@@ -440,14 +514,14 @@ peers_status peers_server_submit(peers_server s, peers_factor f, int64_t q, cons
   r->t_submit = Clock::now();
   *ticket = r->ticket;
   S->submitted++;
+  F->server_refs.fetch_add(1);
+  S->reqs[r->ticket] = r;
   if (q == 0) {
     finish_request(*S, r.get(), PEERS_OK);
-    S->reqs[r->ticket] = std::move(r);
     S->cv_done.notify_all();
     return PEERS_OK;
   }
-  S->pending.push_back(r.get());
-  S->reqs[r->ticket] = std::move(r);
+  S->pending.push_back(r);
   S->cv_req.notify_one();
   return PEERS_OK;
 }
@@ -458,7 +532,7 @@ peers_status peers_server_wait(peers_server s, uint64_t ticket, int64_t timeout_
   std::unique_lock<std::mutex> lk(S->mu);
   auto it = S->reqs.find(ticket);
   if (it == S->reqs.end()) { set_error("unknown ticket"); return PEERS_E_INVALID_ARG; }
-  Request* r = it->second.get();
+  ReqPtr r = it->second;  // keeps the request alive for this waiter
   auto ready = [&] { return r->done; };
   if (timeout_us < 0) S->cv_done.wait(lk, ready);
   else if (!S->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) {
@@ -466,7 +540,27 @@ peers_status peers_server_wait(peers_server s, uint64_t ticket, int64_t timeout_
     return PEERS_E_TIMEOUT;
   }
   if (result) *result = r->status;
-  S->reqs.erase(it);
+  S->reqs.erase(ticket);  // (another waiter on the same ticket may have erased it)
+  return PEERS_OK;
+}
+
+peers_status peers_server_cancel(peers_server s, uint64_t ticket) {
+  if (!s) { set_error("null server"); return PEERS_E_INVALID_ARG; }
+  auto* S = reinterpret_cast<Server*>(s);
+  std::lock_guard<std::mutex> g(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) { set_error("unknown ticket"); return PEERS_E_INVALID_ARG; }
+  ReqPtr r = it->second;
+  if (r->done) return PEERS_OK;
+  r->cancelled = true;
+  if (!r->on_device) {
+    auto p = std::find(S->pending.begin(), S->pending.end(), r);
+    if (p != S->pending.end()) S->pending.erase(p);
+    finish_request(*S, r.get(), PEERS_E_CANCELLED);
+    S->cv_done.notify_all();
+  }
+  // a request on the device finishes as CANCELLED when its batch completes,
+  // without its results being copied out
   return PEERS_OK;
 }
 
@@ -485,6 +579,9 @@ peers_status peers_server_stats_get(peers_server s, peers_server_stats* out) {
   double busy = S->busy_s;
   if (S->busy_slots > 0) busy += std::chrono::duration<double>(Clock::now() - S->busy_since).count();
   out->resistances_per_s = busy > 0 ? (double)S->pairs_done / busy : 0.0;
+  out->memory_waits = S->memory_waits;
+  for (const Slot& sl : S->slots) out->arena_bytes += sl.arena_bytes;
+  out->pending = S->pending.size();
   return PEERS_OK;
 }
 
@@ -500,10 +597,7 @@ peers_status peers_server_stop(peers_server s) {
   (void)hipSetDevice(S->D->ordinal);
   for (Slot& sl : S->slots) {
     if (sl.stream) (void)hipStreamSynchronize(sl.stream);
-    if (sl.arena) {
-      (void)hipFree(sl.arena);
-      S->D->release(sl.arena_bytes);
-    }
+    free_arena(*S, sl);
     if (sl.pinned) (void)hipHostFree(sl.pinned);
     if (sl.ev) (void)hipEventDestroy(sl.ev);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
