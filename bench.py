@@ -7,9 +7,16 @@ buffer. Host preparation (ordering, symbolic, numeric L D L^T) and the upload
 are timed separately and reported beside the result, as the paper reports
 its factorization time separately from the query phase.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload C3|C2|C1]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload C3|C2|C1|C4|C5]
 
-Prints one JSON line. Only one GPU is used; --gpus above 1 exits with a message.
+Prints one JSON line. The default (the 1M-node PDN, C3) also carries the
+metric's other half measured in the same run: a "batched" sub-object (256
+random geometric graphs in one captured launch sequence, against the same
+sweeps issued one graph at a time) and a "served" sub-object (8 resident PDN
+factors under a Poisson request stream: saturation rate, p50/p99 latency at
+25/50/90% load, against serving one request at a time). The CPU oracle leg
+runs first, on a bounded edge sample over a forked process pool.
+Only one GPU is used; --gpus above 1 exits with a message.
 """
 from __future__ import annotations
 
@@ -42,22 +49,73 @@ WORKLOADS = {
 }
 
 
+_ORACLE = None  # (oracle, eu, ev) inherited by the forked workers of cpu_baseline
+
+
+def _oracle_chunk(idx):
+    # one BLAS thread per worker process: the pool already uses every core
+    from threadpoolctl import threadpool_limits
+    so, eu, ev = _ORACLE
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        R = so.resistances(eu[idx], ev[idx])
+        return R, time.perf_counter() - t0
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_workers() -> int:
+    """Worker processes for host-side pools: the cores this process may use, at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def cpu_baseline(g, sample: int, seed: int = 11):
-    """Time the CPU oracle (sparse per-pair solves, refined) on a bounded edge sample."""
+    """Time the CPU oracle (sparse per-pair solves, refined) on a bounded edge sample.
+
+    The oracle factors the grounded Laplacian once (its own nested dissection
+    and SuperLU), then a pool of forked worker processes, one per host core
+    up to 16, solves disjoint slices of a seeded edge sample. Must run before
+    this process touches the GPU (the workers are forked).
+    """
+    import multiprocessing
     from oracle import sparse
+    global _ORACLE
     t0 = time.time()
     so = sparse.SparseOracle(g, ordering="nd")
     t_setup = time.time() - t0
     rng = synth.rng_for(seed)
     sel = rng.choice(g.m, size=min(sample, g.m), replace=False)
-    t1 = time.time()
-    R = so.resistances(g.eu[sel], g.ev[sel])
-    t_solve = time.time() - t1
+    workers = host_workers()
+    chunks = [c for c in np.array_split(sel, workers * 4) if len(c)]
+    _ORACLE = (so, np.asarray(g.eu), np.asarray(g.ev))
+    t1 = time.perf_counter()
+    with multiprocessing.get_context("fork").Pool(workers) as pool:
+        parts = pool.map(_oracle_chunk, chunks)
+    t_solve = time.perf_counter() - t1
+    _ORACLE = None
+    R = np.concatenate([p[0] for p in parts])
+    cpu_s = sum(p[1] for p in parts)
     return {
-        "value": float(len(sel) / t_solve), "unit": "resistances/s", "cores": 1, "kind": "oracle",
-        "sample": (f"{len(sel)} seeded edges of the same graph, per-pair sparse LU solves with 2 extended-precision "
-                   f"refinement steps, single thread; oracle ordering+factorization {t_setup:.1f} s excluded "
-                   f"(solve time {t_solve:.1f} s)"),
+        "value": float(len(sel) / t_solve), "unit": "resistances/s", "cores": workers, "kind": "oracle",
+        "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+        "sample": (f"{len(sel)} seeded edges of the same graph, per-pair sparse LU solves (oracle's own nested "
+                   f"dissection + SuperLU) with 2 extended-precision refinement steps, {workers} forked worker "
+                   f"processes; solve wall {t_solve:.1f} s ({cpu_s:.1f} core-s); the oracle's ordering and "
+                   f"factorization ({t_setup:.1f} s, one core) are excluded"),
+        "per_edge_core_s": round(cpu_s / len(sel), 4),
     }, sel, R
 
 
@@ -116,7 +174,7 @@ def copy_calibration(nbytes: int, reps: int = 5) -> None:
                       "ms_per_copy": round(dt * 1e3, 4), "GB_per_s_read_plus_write": round(2 * n * 8 / dt / 1e9, 1)}))
 
 
-def bench_batch(args):
+def bench_batch(args, steps: int, warmup: int) -> dict:
     """Batched form: 256 random geometric graphs, all edges, one captured launch sequence per step.
 
     The step is the whole batch (every graph's all-edge sweep). The same graphs
@@ -148,34 +206,33 @@ def bench_batch(args):
     def run_bat():
         P.peers_batch_query(dev, fs, [None] * len(fs), [None] * len(fs), bat, stream=stream)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         run_seq()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         run_seq()
     torch.cuda.synchronize()
-    dt_seq = (time.perf_counter() - t0) / args.steps
+    dt_seq = (time.perf_counter() - t0) / steps
     t0 = time.perf_counter()
     run_bat()  # builds, autotunes and captures
     torch.cuda.synchronize()
     t_first = time.perf_counter() - t0
     info = P.peers_batch_last_info(dev)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         run_bat()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         run_bat()
     torch.cuda.synchronize()
-    dt_bat = (time.perf_counter() - t0) / args.steps
+    dt_bat = (time.perf_counter() - t0) / steps
     same = all(torch.equal(a.view(torch.int64), b.view(torch.int64)) for a, b in zip(seq, bat))
     foster = max(abs(math.fsum(g.w * o.cpu().numpy()) - (g.n - 1)) / (g.n - 1) for g, o in zip(graphs, bat))
     out = {
         "metric": "all-edge resistances/s, batch of 256 random geometric graphs (FP64), batched form",
-        "value": round(m_tot / dt_bat, 1), "unit": "resistances/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(dt_bat * 1e3, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "value": round(m_tot / dt_bat, 1), "unit": "resistances/s", "steps": steps, "warmup": warmup,
+        "ms_per_step": round(dt_bat * 1e3, 4), "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{len(graphs)} RGGs in the unit square, n ~ U[2000,50000], union of 6-NN, "
                                "w = 1/distance, ground 0, all edges",
                    "graphs": len(graphs), "sum_n": sum(g.n for g in graphs), "sum_m": m_tot},
@@ -193,13 +250,13 @@ def bench_batch(args):
     P.peers_device_close(dev)
     for h in hs:
         P.peers_graph_destroy(h)
-    print(json.dumps(out))
+    return out
 
 
 SERVED_SIDES = (128, 181, 222, 256, 320, 384, 448, 500)
 
 
-def bench_served(args):
+def bench_served(args) -> dict:
     """Served form: 8 resident PDN factors, Poisson requests of 1..100k pairs.
 
     Saturation throughput is measured with the whole trace submitted at once;
@@ -296,15 +353,15 @@ def bench_served(args):
                        "resistances_per_s": round(npairs / wall, 1),
                        "p50_us": round(st["p50_us"], 1), "p99_us": round(st["p99_us"], 1),
                        "max_us": round(st["max_us"], 1), "batches": st["batches"],
+                       "memory_waits": st["memory_waits"],
                        "one_at_a_time": {"p50_us": round(float(np.percentile(lat, 50)), 1),
                                          "p99_us": round(float(np.percentile(lat, 99)), 1),
                                          "max_us": round(float(lat.max()), 1)}})
     ref = levels[-1]
     out = {
         "metric": "served: resistances/s and p50/p99 latency, 8 resident PDN factors (FP64)",
-        "value": round(sat_rps, 1), "unit": "resistances/s", "n_gpus": 1, "steps": nreq, "warmup": 16,
-        "ms_per_step": round(wall * 1e3 / nreq, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "value": round(sat_rps, 1), "unit": "resistances/s", "requests": nreq,
+        "dtype": "f64", "data": "synthetic",
         "config": {"workload": "8 PDN meshes (4 layers, sides " + ",".join(map(str, SERVED_SIDES)) +
                                "), Poisson requests of 1..100000 pairs (log-uniform), 80% edges / 20% random pairs",
                    "factors": len(graphs), "nodes": [g.n for g in graphs], "requests": nreq, "pairs": pairs},
@@ -324,42 +381,14 @@ def bench_served(args):
     P.peers_device_close(dev)
     for h in hs:
         P.peers_graph_destroy(h)
-    print(json.dumps(out))
+    return out
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="C3", choices=sorted(WORKLOADS) + ["C4", "C5"])
-    ap.add_argument("--served-requests", type=int, default=200, help="requests per served trace (C5)")
-    ap.add_argument("--batch-count", type=int, default=256, help="graphs in the C4 batch")
-    ap.add_argument("--cpu-sample", type=int, default=64)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
-                    help="only run a plain device copy of BYTES (HBM counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the library has no multi-GPU path (the design notes describe how the "
-              "sweep would shard); run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
-
-    if args.copy_calibration:
-        copy_calibration(args.copy_calibration)
-        return
-    if args.workload == "C4":
-        bench_batch(args)
-        return
-    if args.workload == "C5":
-        bench_served(args)
-        return
-
+def bench_plain(args, g, desc, cpu=None) -> dict:
+    """The all-edge sweep of one resident factor (C1-C3); the headline line."""
     import torch
     import paper_2606_31535_amd as P
 
-    desc, gen = WORKLOADS[args.workload]
-    g = gen()
     t0 = time.time()
     h = P.peers_graph_create(g.n, g.eu, g.ev, g.w, g.ground, coords=g.coords)
     t_prep = time.time() - t0
@@ -383,7 +412,7 @@ def main():
     dt = (time.perf_counter() - t0) / args.steps
     Rh = R.cpu().numpy()
 
-    # per-phase HIP-event times on the same stream (separate profiled steps)
+    # per-phase HIP-event times on the sweep's stream (separate profiled steps)
     phases = []
     for _ in range(max(1, min(3, args.steps))):
         P.peers_query_all_edges(f, R, flags=P.PEERS_PROFILE, stream=stream)
@@ -393,16 +422,19 @@ def main():
     tm = phases[-1]
     if ph["top_ms"] >= ph["bottom_ms"]:
         kname, ms, flops, nl = "gemm_level_kernel", ph["top_ms"], tm["top_flops"], tm["top_launches"]
-        bound = "mfma"
+        bound, fdef = "mfma", "2 * (sum over top-column entries L_ki of depth(k))"
     else:
         kname, ms, flops, nl = "bottom_kernel", ph["bottom_ms"], tm["bottom_flops"], tm["bottom_launches"]
         bound = "alu"
+        fdef = ("2 * (sum over bottom-column entries L_ki of depth(k)) + 3 * (sum over edges whose lower "
+                "endpoint is a bottom node of its depth)")
     achieved = flops / (ms * 1e-3) / 1e12
     roofline = {"bound": bound, "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP64_TFLOPS, 5),
                 "traffic": recorded_traffic(kname, args.workload), "source_hash": kernel_source_hash(),
                 "kernel": kname, "launches_per_step": nl, "phase_ms": round(ms, 4),
-                "algorithmic_flops": flops}
+                "algorithmic_flops": flops, "flops_definition": fdef}
+    whole = tm["top_flops"] + tm["bottom_flops"] + tm["finish_flops"]
 
     # accuracy on the stored oracle sample, and Foster's theorem on all edges
     acc = {"foster_rel_residual": float(abs(math.fsum(g.w * Rh) - (g.n - 1)) / (g.n - 1))}
@@ -420,21 +452,86 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": desc, "n": g.n, "m": g.m, "seed": g.meta.get("seed"), "nnz_l": st["nnz_l"],
-                   "etree_height": st["height"], "f_sweep_fma": st["f_sweep"]},
+                   "etree_height": st["height"], "f_sweep_fma": st["f_sweep"], "acc_terms": st["acc_terms"]},
         "roofline": roofline, "phases_ms": {k: round(v, 4) for k, v in ph.items()},
+        "whole_step": {"algorithmic_flops": whole, "TFLOP_per_s": round(whole / dt / 1e12, 3),
+                       "frac_of_fp64_peak": round(whole / dt / 1e12 / PEAK_FP64_TFLOPS, 4)},
         "accuracy": acc,
         "t_prep_s": {"total": round(t_prep, 3), "ingest": round(st["t_ingest"], 3), "order": round(st["t_order"], 3),
                      "symbolic": round(st["t_symbolic"], 3), "numeric": round(st["t_numeric"], 3),
-                     "upload": round(t_upload, 3)},
+                     "upload": round(t_upload, 3), "upload_layout": round(tm["t_layout_s"], 3),
+                     "upload_edge_plan": round(tm["t_edge_plan_s"], 3),
+                     "upload_transfer": round(tm["t_transfer_s"], 3),
+                     "upload_transform": round(tm["t_transform_s"], 3)},
+        "t_query": {"plan_s": round(tm["t_edge_plan_s"], 4), "sweep_and_reduce_ms": round(dt * 1e3, 4),
+                    "result_copy_ms": 0.0,
+                    "resistances_per_s_including_plan": round(g.m / (tm["t_edge_plan_s"] + dt), 1),
+                    "note": "all-edge plan built once at upload; results stay in device memory"},
         "hbm_bytes": {"resident": resident, "workspace": workspace},
     }
-    if not args.no_cpu_baseline:
-        cb, sel, Rs = cpu_baseline(g, args.cpu_sample)
+    if cpu is not None:
+        cb, sel, Rs = cpu
         cb["max_rel_diff_vs_gpu"] = float(np.max(np.abs(Rh[sel] - Rs) / Rs))
         out["cpu_baseline"] = cb
     P.peers_factor_release(f)
     P.peers_device_close(dev)
     P.peers_graph_destroy(h)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="C3", choices=sorted(WORKLOADS) + ["C4", "C5"])
+    ap.add_argument("--served-requests", type=int, default=200, help="requests per served trace (C5)")
+    ap.add_argument("--batch-count", type=int, default=256, help="graphs in the C4 batch")
+    ap.add_argument("--cpu-sample", type=int, default=768)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="leave the batched sub-object out of the C3 line")
+    ap.add_argument("--no-served", action="store_true", help="leave the served sub-object out of the C3 line")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the library has no multi-GPU path (the design notes describe how the "
+              "sweep would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    if args.workload == "C4":
+        out = bench_batch(args, args.steps, args.warmup)
+        out.update({"n_gpus": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None})
+        print(json.dumps(out))
+        return
+    if args.workload == "C5":
+        out = bench_served(args)
+        out.update({"n_gpus": 1, "steps": out["requests"], "warmup": 16, "higher_is_better": True,
+                    "scaling": "weak", "vs_baseline": None})
+        print(json.dumps(out))
+        return
+
+    desc, gen = WORKLOADS[args.workload]
+    g = gen()
+    # the oracle's CPU leg first: its worker processes are forked, before
+    # anything here touches the GPU
+    cpu = None if args.no_cpu_baseline else cpu_baseline(g, args.cpu_sample)
+    out = bench_plain(args, g, desc, cpu)
+    print(json.dumps({"progress": "plain all-edge sweep done", "ms_per_step": out["ms_per_step"]}),
+          file=sys.stderr, flush=True)
+    if args.workload == "C3":
+        # the metric's other half, on the same GPU in the same run: the batched
+        # form (256 RGGs) and the served form (8 resident PDN factors)
+        if not args.no_batched:
+            out["batched"] = bench_batch(args, min(args.steps, 5), min(args.warmup, 2))
+            print(json.dumps({"progress": "batched form done"}), file=sys.stderr, flush=True)
+        if not args.no_served:
+            out["served"] = bench_served(args)
+            out["served_p50_us_at_90pct"] = out["served"]["p50_us_at_90pct"]
+            out["served_p99_us_at_90pct"] = out["served"]["p99_us_at_90pct"]
     print(json.dumps(out))
 
 

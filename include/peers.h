@@ -147,10 +147,20 @@ typedef struct {
   double total_ms;
   int32_t top_launches;
   int32_t bottom_launches;
-  double top_flops;     /* algorithmic FP64 flops of the top phase (2 per FMA) */
-  double bottom_flops;  /* algorithmic FP64 flops of the bottom phase */
+  /* Algorithmic work of the all-edge sweep, per phase: 2 flops per FMA of
+   * eq 11 (sum over L_ki != 0 of depth(k), restricted to the phase's columns)
+   * plus 3 flops per accumulation term of eq 12 (one subtraction, one FMA:
+   * sum over the pairs whose lower endpoint is in the phase of its depth). */
+  double top_flops;     /* chain rows and chain-level products (eq 11 only) */
+  double bottom_flops;  /* bottom subtrees: eq 11 and the fused eq 12 terms there */
   double top_bytes;     /* algorithmic HBM bytes of the top phase */
   double bottom_bytes;  /* algorithmic HBM bytes of the bottom phase */
+  double finish_flops;  /* eq 12 terms of pairs whose lower endpoint is a top node */
+  /* Host seconds spent when the factor was uploaded (peers_factor_upload):
+   * the device layout of the factor (chains, blocks, subtree records), the
+   * resident all-edge query plan, allocation and host-to-device copies, and
+   * forming L_CC^{-1} and B_C = -L_{U,C} L_CC^{-1} on the device. */
+  double t_layout_s, t_edge_plan_s, t_transfer_s, t_transform_s;
 } peers_sweep_timings;
 peers_status peers_factor_timings(peers_factor f, peers_sweep_timings* out);
 

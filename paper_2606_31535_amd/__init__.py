@@ -56,7 +56,8 @@ class peers_sweep_timings(C.Structure):
     _fields_ = [("top_ms", C.c_double), ("bottom_ms", C.c_double), ("finish_ms", C.c_double),
                 ("total_ms", C.c_double), ("top_launches", C.c_int32), ("bottom_launches", C.c_int32),
                 ("top_flops", C.c_double), ("bottom_flops", C.c_double), ("top_bytes", C.c_double),
-                ("bottom_bytes", C.c_double)]
+                ("bottom_bytes", C.c_double), ("finish_flops", C.c_double), ("t_layout_s", C.c_double),
+                ("t_edge_plan_s", C.c_double), ("t_transfer_s", C.c_double), ("t_transform_s", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

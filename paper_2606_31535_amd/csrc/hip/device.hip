@@ -306,11 +306,15 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
   F->first = G.sym.first;
   F->depth = G.sym.depth;
   F->plan.reset(new FactorPlan());
+  double tp = now_s();
   Status st = build_plan(G.sym, G.num, *F->plan);
   if (st != OK) return (peers_status)st;
+  F->t_layout = now_s() - tp;
   const FactorPlan& P = *F->plan;
   F->anc.build(G.sym.parent, G.sym.depth, P);
   // resident all-edge query plan
+  double acc_bottom = 0, acc_top = 0;
+  tp = now_s();
   {
     std::vector<int32_t> a(F->m), b(F->m);
     for (int64_t e = 0; e < F->m; ++e) {
@@ -322,6 +326,14 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
     st = build_query_plan(F->first, F->depth, P, F->m, a.data(), b.data(), Q);
     if (st != OK) return (peers_status)st;
     if (Q.n_general) { set_error("internal: an edge whose endpoints are not etree-related"); return PEERS_E_INTERNAL; }
+    F->t_edge_plan = now_s() - tp;
+    // eq 12 terms: depth of the lower endpoint, per pair with R > 0
+    for (int64_t e = 0; e < F->m; ++e) {
+      if (a[e] == b[e]) continue;
+      const int32_t lo = a[e] < 0 ? b[e] : (b[e] < 0 ? a[e] : std::min(a[e], b[e]));
+      (P.small[lo] ? acc_bottom : acc_top) += (double)G.sym.depth[lo];
+    }
+    tp = now_s();
     st = upload_query_plan(*F, Q, F->edges, s);
     if (st != OK) return (peers_status)st;
   }
@@ -384,6 +396,9 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
   if (he == hipSuccess && !P.luc.empty())
     he = hipMemcpyAsync(lucbuf, P.luc.data(), P.luc.size() * 8, hipMemcpyHostToDevice, s);
   if (he != hipSuccess) { (void)hipFree(lucbuf); D->release(luc_bytes); return (peers_status)hip_fail(he, "upload"); }
+  he = hipStreamSynchronize(s);
+  if (he != hipSuccess) { (void)hipFree(lucbuf); D->release(luc_bytes); return (peers_status)hip_fail(he, "upload"); }
+  F->t_transfer = now_s() - tp;
   {
     const double t0 = now_s();
     int32_t nl = 0;
@@ -428,7 +443,8 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
       else nt += (double)(G.sym.colptr[i + 1] - G.sym.colptr[i]);
     }
     F->top_flops = 2.0 * P.f_top;  // exact count; the blocked forms do f_top_gemm + f_top_inv
-    F->bottom_flops = 2.0 * fb;
+    F->bottom_flops = 2.0 * fb + 3.0 * acc_bottom;
+    F->finish_flops = 3.0 * acc_top;
     F->top_bytes = 12.0 * nt + 8.0 * (double)P.store_elems;
     F->bottom_bytes = 12.0 * nb + 16.0 * (double)F->m;
   }
@@ -485,6 +501,11 @@ peers_status peers_factor_timings(peers_factor f, peers_sweep_timings* out) {
   out->bottom_flops = F->bottom_flops;
   out->top_bytes = F->top_bytes;
   out->bottom_bytes = F->bottom_bytes;
+  out->finish_flops = F->finish_flops;
+  out->t_layout_s = F->t_layout;
+  out->t_edge_plan_s = F->t_edge_plan;
+  out->t_transfer_s = F->t_transfer;
+  out->t_transform_s = F->t_transform;
   if (!F->timed) return PEERS_OK;
   hipError_t e = hipEventSynchronize(F->ev[3]);
   if (e != hipSuccess) return (peers_status)hip_fail(e, "hipEventSynchronize");

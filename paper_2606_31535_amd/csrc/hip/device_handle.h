@@ -64,7 +64,7 @@ struct FactorHandle {
   void* xbuf = nullptr;   // L_CC^{-1} workspace
   void* tbuf = nullptr;   // recursion temporaries
   void* btbuf = nullptr;  // transfer blocks B_C (resident)
-  double t_transform = 0;
+  double t_transform = 0, t_layout = 0, t_edge_plan = 0, t_transfer = 0;
   void* part = nullptr;
   void* res = nullptr;
   void* stage = nullptr;  // staged bottom columns of non-ancestor pairs
@@ -78,7 +78,7 @@ struct FactorHandle {
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool timed = false;
   int32_t top_launches = 0, bottom_launches = 0;
-  double top_flops = 0, bottom_flops = 0, top_bytes = 0, bottom_bytes = 0;
+  double top_flops = 0, bottom_flops = 0, top_bytes = 0, bottom_bytes = 0, finish_flops = 0;
 };
 
 Status hip_fail(hipError_t e, const char* what);
