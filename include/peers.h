@@ -184,6 +184,16 @@ peers_status peers_factor_export_columns(peers_factor f, int64_t k, const int32_
  * input edge e in input order (m values; self-loops give +0.0). */
 peers_status peers_query_all_edges(peers_factor f, double* R_out, uint32_t flags, void* hip_stream);
 
+/* Node-to-ground resistances (eq 4 with t = g; eq 12 cases 2-3): R_out[x] =
+ * R_{x,g} = (L_r^{-1})_xx for every original id x, in id order (n values;
+ * R_out[g] = +0.0). This is the "weak link" screen of a power grid grounded
+ * at its supply: every node's resistance to the source. Their sum is
+ * trace(L_r^{-1}). The plan (one pair per node, accumulated at that node
+ * during the sweep) is built on the first call and kept with the factor.
+ * Output host or device (PEERS_OUT_DEVICE); stream-ordered like
+ * peers_query_all_edges. Errors: INVALID_ARG, OVER_BUDGET, HIP. */
+peers_status peers_query_all_to_ground(peers_factor f, double* R_out, uint32_t flags, void* hip_stream);
+
 /* Resistances for q arbitrary pairs given in original ids (eq 4 and eq 12):
  * pairs with u == v give +0.0, pairs with the ground use the grounded case.
  * A pair whose endpoints are ancestor-related in the elimination tree is
@@ -202,6 +212,22 @@ peers_status peers_query_all_edges(peers_factor f, double* R_out, uint32_t flags
  * records (about 178M such pairs; split the request). */
 peers_status peers_query(peers_factor f, int64_t q, const int32_t* qu, const int32_t* qv, double* R_out,
                          uint32_t flags, void* hip_stream);
+
+/* peers_query for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, kernels and results (bit for bit) as peers_query, but the
+ * call allocates no device memory: its query plan, launch layout, partial
+ * sums, staged columns and (for host output) result staging go into one
+ * fixed 64 MiB device array that each GPU holds from first use until the
+ * process ends. Calls through this entry point are serialized per GPU: each
+ * holds the array until its work has finished, and returns only then
+ * (host or device output). PEERS_PROFILE is not supported (INVALID_ARG).
+ * Errors: as peers_query, and OVER_BUDGET when the request needs more than
+ * the array holds (about 64 MiB of plan, partial sums and staging: e.g. tens
+ * of thousands of edge pairs, or about a thousand non-ancestor pairs on a
+ * 1M-node factor; split such requests or use peers_query). */
+peers_status peers_query_noalloc(peers_factor f, int64_t q, const int32_t* qu, const int32_t* qv, double* R_out,
+                                 uint32_t flags, void* hip_stream);
 
 /* Batched form (many graphs of uneven size): the sweeps of nb resident
  * factors on one device run as one sequence of grouped launches, one launch

@@ -113,7 +113,9 @@ SIGNATURES = {
     "peers_factor_timings": (C.c_int, [_vp, C.POINTER(peers_sweep_timings)]),
     "peers_factor_export_columns": (C.c_int, [_vp, C.c_int64, _i32p, C.c_int64, _f64p, _vp]),
     "peers_query_all_edges": (C.c_int, [_vp, _vp, C.c_uint32, _vp]),
+    "peers_query_all_to_ground": (C.c_int, [_vp, _vp, C.c_uint32, _vp]),
     "peers_query": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, C.c_uint32, _vp]),
+    "peers_query_noalloc": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, C.c_uint32, _vp]),
     "peers_batch_query": (C.c_int, [_vp, C.c_int32, C.POINTER(_vp), _i64p, C.POINTER(_vp),
                                     C.POINTER(_vp), C.POINTER(_vp), C.c_uint32, _vp]),
     "peers_batch_last_info": (C.c_int, [_vp, C.POINTER(peers_batch_info)]),
@@ -177,6 +179,7 @@ def _stream_handle(stream):
 # edge count of every factor uploaded through this binding (all-edge outputs
 # are checked against it); dropped on release
 _FACTOR_EDGES = {}
+_FACTOR_NODES = {}
 
 
 def _is_tensor(x):
@@ -322,16 +325,18 @@ def peers_device_set_budget(d, hbm_budget_bytes):
 
 
 def peers_factor_upload(d, g, stream=None):
-    m = peers_graph_stats_get(g)["m"]
+    st = peers_graph_stats_get(g)
     h = _vp()
     _check(lib().peers_factor_upload(d, g, _stream_handle(stream), C.byref(h)), "peers_factor_upload")
-    _FACTOR_EDGES[h.value] = int(m)
+    _FACTOR_EDGES[h.value] = int(st["m"])
+    _FACTOR_NODES[h.value] = int(st["n"])
     return h
 
 
 def peers_factor_release(f):
     if f:
         _FACTOR_EDGES.pop(f.value if isinstance(f, C.c_void_p) else int(f), None)
+        _FACTOR_NODES.pop(f.value if isinstance(f, C.c_void_p) else int(f), None)
         lib().peers_factor_release(f)
 
 
@@ -365,6 +370,18 @@ def peers_query_all_edges(f, R_out, flags=0, stream=None):
     return R_out
 
 
+def peers_query_all_to_ground(f, R_out, flags=0, stream=None):
+    """R_out[x] = resistance between node x and the ground, for every node (n values)."""
+    key = f.value if isinstance(f, C.c_void_p) else int(f)
+    if key not in _FACTOR_NODES:
+        raise ValueError("unknown factor handle (upload factors with peers_factor_upload)")
+    p, dev = _out(R_out, _FACTOR_NODES[key], "R_out")
+    if dev:
+        flags |= PEERS_OUT_DEVICE
+    _check(lib().peers_query_all_to_ground(f, p, flags, _stream_handle(stream)), "peers_query_all_to_ground")
+    return R_out
+
+
 def peers_query(f, qu, qv, R_out, flags=0, stream=None):
     pu, du, ku, q = _ids(qu, "qu")
     pv, dv, kv, qv_len = _ids(qv, "qv")
@@ -378,6 +395,23 @@ def peers_query(f, qu, qv, R_out, flags=0, stream=None):
     if dr:
         flags |= PEERS_OUT_DEVICE
     _check(lib().peers_query(f, q, pu, pv, pr, flags, _stream_handle(stream)), "peers_query")
+    return R_out
+
+
+def peers_query_noalloc(f, qu, qv, R_out, flags=0, stream=None):
+    """peers_query without any device allocation (fixed per-GPU scratch array)."""
+    pu, du, ku, q = _ids(qu, "qu")
+    pv, dv, kv, qv_len = _ids(qv, "qv")
+    if q != qv_len:
+        raise ValueError(f"qu has {q} ids and qv {qv_len}")
+    pr, dr = _out(R_out, q, "R_out")
+    if du != dv:
+        raise ValueError("qu and qv must live on the same side")
+    if du:
+        flags |= PEERS_IN_DEVICE
+    if dr:
+        flags |= PEERS_OUT_DEVICE
+    _check(lib().peers_query_noalloc(f, q, pu, pv, pr, flags, _stream_handle(stream)), "peers_query_noalloc")
     return R_out
 
 

@@ -55,6 +55,7 @@ Status batch_launch_stage(const BatchLayout& L, const BatchStage& st, void* mem,
 
 // One factor's sweep over a plan that reads only some top chains: the steps
 // run as grouped launches restricted to those chains' items.
-Status run_sweep_pruned(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t s, bool profile);
+Status run_sweep_pruned(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t s, bool profile,
+                        const SweepWork* work = nullptr);
 
 }  // namespace peers

@@ -161,11 +161,21 @@ Status batch_launch(const BatchLayout& L, void* mem, hipStream_t s) {
   return OK;
 }
 
-Status run_sweep_pruned(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t s, bool profile) {
-  std::vector<BatchEntry> be{BatchEntry{&F, &D, R_dev}};
+Status run_sweep_pruned(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t s, bool profile,
+                        const SweepWork* work) {
+  std::vector<BatchEntry> be{BatchEntry{&F, &D, R_dev, work ? work->part : nullptr, work ? work->stage : nullptr}};
   auto L = std::make_shared<BatchLayout>();
   batch_layout(*F.dev, be, *L);
-  if (L->bytes > D.layout_bytes) {
+  void* mem = D.layout_mem;
+  if (work && work->layout) {
+    // caller memory (nothing is allocated)
+    if (L->bytes > work->layout_cap) {
+      set_error("the launch layout needs " + std::to_string(L->bytes) + " bytes, " +
+                std::to_string(work->layout_cap) + " are left in the caller's workspace");
+      return E_OVER_BUDGET;
+    }
+    mem = work->layout;
+  } else if (L->bytes > D.layout_bytes) {
     if (D.layout_mem) {
       (void)hipFree(D.layout_mem);
       F.dev->release(D.layout_bytes);
@@ -180,8 +190,9 @@ Status run_sweep_pruned(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipS
       return hip_fail(e, "hipMalloc(pruned sweep)");
     }
     D.layout_bytes = L->bytes;
+    mem = D.layout_mem;
   }
-  Status st = batch_upload(*L, D.layout_mem, s);
+  Status st = batch_upload(*L, mem, s);
   if (st != OK) return st;
   D.layout_host = L;  // host image stays alive while the copies may be pending
   if (profile && !F.ev[0])
@@ -205,7 +216,7 @@ Status run_sweep_pruned(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipS
     if (profile && k == b1) (void)hipEventRecord(F.ev[1], s);
     if (profile && k == b2) (void)hipEventRecord(F.ev[2], s);
     if (k == nst) break;
-    st = batch_launch_stage(*L, L->stages[k], D.layout_mem, s);
+    st = batch_launch_stage(*L, L->stages[k], mem, s);
     if (st != OK) return st;
     if (L->stages[k].kind == GK_BOTTOM || L->stages[k].kind == GK_BOTTOM_WIDE) ++bottom;
     else if (k < b1) ++top;

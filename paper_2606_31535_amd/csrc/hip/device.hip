@@ -177,11 +177,12 @@ static Status run_chain_inverse(FactorHandle& F, hipStream_t s, int32_t& launche
   return OK;
 }
 
-Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t s, bool profile) {
-  if (D.prune_top) return run_sweep_pruned(F, D, R_dev, s, profile);
+Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t s, bool profile,
+                 const SweepWork* work) {
+  if (D.prune_top) return run_sweep_pruned(F, D, R_dev, s, profile, work);
   QueryArgs q = D.args;
-  q.part = (double*)F.part;
-  q.stage = (double*)F.stage;
+  q.part = work && work->part ? work->part : (double*)F.part;
+  q.stage = work && work->stage ? work->stage : (double*)F.stage;
   q.R = R_dev;
   const FactorPlan& P = *F.plan;
   if (profile && !F.ev[0])
@@ -468,6 +469,7 @@ void peers_factor_release(peers_factor f) {
   (void)hipDeviceSynchronize();
   batch_cache_forget(*F->dev, F);
   free_query_plan(*F, F->edges);
+  free_query_plan(*F, F->to_ground);
   if (F->base) (void)hipFree(F->base);
   if (F->store) (void)hipFree(F->store);
   if (F->xbuf) (void)hipFree(F->xbuf);
@@ -575,6 +577,42 @@ peers_status peers_query_all_edges(peers_factor f, double* R_out, uint32_t flags
   if (st != OK) return (peers_status)st;
   if (!dev_out) {
     he = hipMemcpyAsync(R_out, Rd, sizeof(double) * F->m, hipMemcpyDeviceToHost, s);
+    if (he != hipSuccess) return (peers_status)hip_fail(he, "hipMemcpyAsync(results)");
+  }
+  if (!dev_out || (flags & PEERS_SYNC)) {
+    he = hipStreamSynchronize(s);
+    if (he != hipSuccess) return (peers_status)hip_fail(he, "hipStreamSynchronize");
+  }
+  return PEERS_OK;
+}
+
+peers_status peers_query_all_to_ground(peers_factor f, double* R_out, uint32_t flags, void* hip_stream) {
+  if (!f || !R_out) { set_error("null argument"); return PEERS_E_INVALID_ARG; }
+  auto* F = reinterpret_cast<FactorHandle*>(f);
+  hipStream_t s = (hipStream_t)hip_stream;
+  std::lock_guard<std::mutex> g(F->mu);
+  hipError_t he = hipSetDevice(F->dev->ordinal);
+  if (he != hipSuccess) return (peers_status)hip_fail(he, "hipSetDevice");
+  if (!F->to_ground_ready) {
+    // pairs (x, g) for every original id x, in id order; (g, g) gives 0
+    std::vector<int32_t> a(F->n), b(F->n, -1);
+    for (int64_t x = 0; x < F->n; ++x) a[x] = perm_index(*F, (int32_t)x);
+    QueryPlan Q;
+    Status st = build_query_plan_handle(*F, F->n, a.data(), b.data(), Q);
+    if (st == OK) st = upload_query_plan(*F, Q, F->to_ground, s);
+    if (st == OK) st = ensure_workspace(*F, F->to_ground.nslots, F->n, F->to_ground.stage_elems);
+    if (st != OK) {
+      free_query_plan(*F, F->to_ground);
+      return (peers_status)st;
+    }
+    F->to_ground_ready = true;
+  }
+  const bool dev_out = flags & PEERS_OUT_DEVICE;
+  double* Rd = dev_out ? R_out : (double*)F->res;
+  Status st = run_sweep(*F, F->to_ground, Rd, s, flags & PEERS_PROFILE);
+  if (st != OK) return (peers_status)st;
+  if (!dev_out) {
+    he = hipMemcpyAsync(R_out, Rd, sizeof(double) * F->n, hipMemcpyDeviceToHost, s);
     if (he != hipSuccess) return (peers_status)hip_fail(he, "hipMemcpyAsync(results)");
   }
   if (!dev_out || (flags & PEERS_SYNC)) {

@@ -70,6 +70,8 @@ struct FactorHandle {
   void* stage = nullptr;  // staged bottom columns of non-ancestor pairs
   uint64_t resident_bytes = 0, store_bytes = 0, part_bytes = 0, res_bytes = 0, stage_bytes = 0, reserved = 0;
   DeviceQueryPlan edges;  // all-edge queries, resident
+  DeviceQueryPlan to_ground;  // every node with the ground, resident after its first use
+  bool to_ground_ready = false;
   std::mutex mu;          // one sweep at a time on the factor's own workspace (part/res/stage)
   // requests of any server that are queued or on the device for this factor;
   // release waits for them
@@ -88,7 +90,16 @@ uint64_t query_plan_bytes(const QueryPlan& Q);
 Status upload_query_plan_to(const QueryPlan& Q, DeviceQueryPlan& D, void* mem, hipStream_t s);
 void free_query_plan(FactorHandle& F, DeviceQueryPlan& D);
 Status ensure_workspace(FactorHandle& F, int64_t nslots, int64_t nres, int64_t nstage);
-Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t s, bool profile);
+// Workspace of one sweep given by the caller instead of the factor's own
+// (partial slots, staging, and the launch layout of a pruned sweep).
+struct SweepWork {
+  double* part = nullptr;
+  double* stage = nullptr;
+  void* layout = nullptr;
+  uint64_t layout_cap = 0;  // bytes available at `layout`
+};
+Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t s, bool profile,
+                 const SweepWork* work = nullptr);
 Status build_query_plan_handle(const FactorHandle& F, int64_t q, const int32_t* a, const int32_t* b,
                                QueryPlan& Q);
 // Validates q pairs of original ids, builds their plan and uploads it.

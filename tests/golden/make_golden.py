@@ -1,11 +1,13 @@
-"""Write oracle values for sampled edges of the full-size workloads.
+"""Write oracle values for sampled edges and nodes of the full-size workloads.
 
 Calls only ``oracle`` (and the seeded generators in ``synth``): the stored
 expected values never come from the library under test. For each workload the
-sample is: a seeded uniform sample of edges, the highest- and lowest-conductance
-edges, and (for the meshes) edges on the first and last wire of each layer.
+edge sample is: a seeded uniform sample of edges, and the highest- and
+lowest-conductance edges. The node sample (node-to-ground resistances, eq 4
+with t = g) is a seeded uniform sample of nodes.
 
-    python tests/golden/make_golden.py C2 C3       # writes tests/golden/<cfg>_edges.json
+    python tests/golden/make_golden.py C2 C3          # writes tests/golden/<cfg>_edges.json
+    python tests/golden/make_golden.py ground C2 C3   # writes tests/golden/<cfg>_ground.json
 """
 import json
 import os
@@ -37,8 +39,10 @@ def _init(cfg):
 
 
 def _solve(args):
+    from threadpoolctl import threadpool_limits
     qu, qv = args
-    return _ORACLE.resistances(qu, qv)
+    with threadpool_limits(limits=1):  # one BLAS thread per worker process
+        return _ORACLE.resistances(qu, qv)
 
 
 def sample_edges(g, cfg):
@@ -68,6 +72,34 @@ def make(cfg, workers=6):
     print(cfg, len(edges), "edges in", out["seconds"], "s")
 
 
+GROUND_SAMPLE = 300
+
+
+def make_ground(cfg, workers=6):
+    g = WORKLOADS[cfg]()
+    rng = synth.rng_for(7100 + int(cfg[1]))
+    nodes = np.array(sorted(rng.choice(np.array([x for x in range(g.n) if x != g.ground]), size=GROUND_SAMPLE,
+                                       replace=False).tolist()), dtype=np.int64)
+    chunks = np.array_split(nodes, workers * 4)
+    t0 = time.time()
+    with ProcessPoolExecutor(max_workers=workers, initializer=_init, initargs=(cfg,)) as ex:
+        parts = list(ex.map(_solve, [(c, np.full(len(c), g.ground)) for c in chunks]))
+    R = np.concatenate(parts)
+    out = {
+        "workload": cfg, "generator": g.name, "seed": g.meta.get("seed"), "n": g.n, "m": g.m, "ground": g.ground,
+        "oracle": "oracle.sparse.SparseOracle(ordering='nd'), 2 refinement steps, extended-precision residual",
+        "seconds": round(time.time() - t0, 1), "nodes": nodes.tolist(), "R": [repr(float(x)) for x in R],
+    }
+    with open(os.path.join(HERE, f"{cfg}_ground.json"), "w") as f:
+        json.dump(out, f)
+    print(cfg, len(nodes), "nodes in", out["seconds"], "s")
+
+
 if __name__ == "__main__":
-    for cfg in sys.argv[1:] or ["C2", "C3"]:
-        make(cfg)
+    args = sys.argv[1:]
+    if args and args[0] == "ground":
+        for cfg in args[1:] or ["C2", "C3"]:
+            make_ground(cfg)
+    else:
+        for cfg in args or ["C2", "C3"]:
+            make(cfg)
