@@ -52,7 +52,7 @@ Status build_graph(int64_t n, int64_t m, const int32_t* eu, const int32_t* ev, c
   st = symbolic_analyze(G.ing.A, order, G.sym);
   if (st != OK) return st;
   double t3 = now_s();
-  st = ldlt_numeric(G.ing.A, G.ing.diag, G.sym, o.threads, G.num);
+  st = ldlt_numeric(G.ing.A, G.ing.gnd, G.sym, o.threads, G.num);
   if (st != OK) return st;
   double t4 = now_s();
 

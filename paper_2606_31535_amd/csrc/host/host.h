@@ -51,7 +51,7 @@ struct Ingested {
   int32_t ground = 0;
   int32_t N = 0;               // n - 1 rows of L_r
   SymCsr A;                    // off-diagonal part of L_r
-  std::vector<double> diag;    // diagonal of L_r (weighted degrees, compensated sums)
+  std::vector<double> gnd;     // conductance from each node to the ground (its row sum in L_r; compensated sums)
   int64_t self_loops = 0;
 };
 
@@ -88,8 +88,10 @@ struct Numeric {
   std::vector<double> D;   // pivots
 };
 
-Status ldlt_numeric(const SymCsr& A, const std::vector<double>& diag, const Symbolic& S,
-                    int threads, Numeric& F);
+// gnd: per reduced id, the conductance to the ground; every pivot is formed
+// from it and the off-diagonal entries (no cancellation, see numeric.cpp).
+Status ldlt_numeric(const SymCsr& A, const std::vector<double>& gnd, const Symbolic& S, int threads,
+                    Numeric& F);
 
 // Simple fork-join helper: runs fn(i) for i in [0, n) over `threads` workers.
 template <class Fn>

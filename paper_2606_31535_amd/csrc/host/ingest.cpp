@@ -2,10 +2,12 @@
 //
 // L_G = sum over edges of w_ij (1_i - 1_j)(1_i - 1_j)^T: a self-loop adds
 // nothing and parallel edges add up. Grounding node g deletes its row and
-// column; the reduced matrix L_r is SPD iff the graph is connected. Diagonal
-// entries are sums of many conductances of very different size, so they are
-// accumulated with Neumaier's compensated summation: the rounding of the
-// diagonal is a perturbation of the problem itself, not of the sweep.
+// column; the reduced matrix L_r is SPD iff the graph is connected. L_r is
+// kept as its off-diagonal entries and, per node, its conductance to the
+// ground (the row sum of L_r); the factorization forms every pivot from
+// these, so the diagonal itself is never needed. Conductances to the ground
+// are sums of edges of very different size and are accumulated with
+// Neumaier's compensated summation.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -72,20 +74,20 @@ Status ingest(int64_t n, int64_t m, const int32_t* eu, const int32_t* ev, const 
   out.N = N;
   auto red = [ground](int32_t x) { return x < ground ? x : x - 1; };
 
-  std::vector<Kahan> dg(N);
+  std::vector<Kahan> gg(N);
   // off-diagonal coordinate list, both triangles
   std::vector<int64_t> cnt(N + 1, 0);
   int64_t self = 0;
   for (int64_t e = 0; e < m; ++e) {
     int32_t a = eu[e], b = ev[e];
     if (a == b) { ++self; continue; }
-    if (a != ground) dg[red(a)].add(w[e]);
-    if (b != ground) dg[red(b)].add(w[e]);
     if (a != ground && b != ground) { cnt[red(a) + 1]++; cnt[red(b) + 1]++; }
+    if (a == ground) gg[red(b)].add(w[e]);
+    if (b == ground) gg[red(a)].add(w[e]);
   }
   out.self_loops = self;
-  out.diag.resize(N);
-  for (int32_t i = 0; i < N; ++i) out.diag[i] = dg[i].value();
+  out.gnd.resize(N);
+  for (int32_t i = 0; i < N; ++i) out.gnd[i] = gg[i].value();
   for (int32_t i = 0; i < N; ++i) cnt[i + 1] += cnt[i];
   std::vector<int32_t> col(cnt[N]);
   std::vector<double> val(cnt[N]);

@@ -7,6 +7,21 @@
 // blocked right-looking L D L^T, and passes the Schur complement to its parent.
 // No pivoting: L_r is SPD, and a non-positive pivot is reported as E_NOT_SPD.
 //
+// Pivots without cancellation. Every Schur complement of a grounded
+// Laplacian is again a grounded Laplacian: its off-diagonal entries are <= 0,
+// and each row's sum r_i >= 0 is that node's (effective) conductance to the
+// ground. Eliminating node k changes them by adding same-signed terms only:
+// S_ij -= L_ik D_k L_jk (a positive amount taken from a value <= 0) and
+// r_i += (-L_ik) r_k. The usual diagonal update a_ii - sum l^2 d subtracts
+// nearly equal numbers once r_i is small against the off-diagonals (nodes far
+// from the ground), and the rounding then grows with the condition number of
+// L_r. Here the updated diagonal is never used; each pivot is assembled when its
+// column is eliminated as D_j = r_j + sum over rows i below j of (-S_ij), a
+// sum of nonnegative terms, with r carried through the fronts beside the
+// update matrices (extend-add of one more vector). This is the reformulation
+// Grassmann, Taksar and Heyman use for Markov chains; every entry of L and D
+// is then computed from same-signed sums, to high relative accuracy.
+//
 // Parallelism: independent subtrees of the supernodal tree run on separate
 // threads, each in postorder with its own update stack; the few large fronts
 // near the root run one at a time with a thread-parallel trailing update.
@@ -27,11 +42,12 @@ struct Ctx {
   const std::vector<int64_t>& aptr;  // permuted lower columns of A (strict lower)
   const std::vector<int32_t>& arow;
   const std::vector<double>& aval;
-  const std::vector<double>& adiag;  // permuted diagonal
+  const std::vector<double>& agnd;   // permuted conductance to the ground
   std::vector<int32_t> sn_of;
   std::vector<int32_t> snpar;
   std::vector<std::vector<int32_t>> children;
-  std::vector<std::vector<double>> upd;  // update matrix per supernode (lower, col-major)
+  std::vector<std::vector<double>> upd;   // update matrix per supernode (lower, col-major)
+  std::vector<std::vector<double>> updr;  // ground-conductance contributions to its rows
   Numeric& F;
   std::mutex err_mu;
   Status err = OK;
@@ -80,10 +96,11 @@ Status factor_front(Ctx& C, int32_t s, int inner_threads) {
   auto pos = [&](int32_t row) -> int64_t {
     return std::lower_bound(frow.begin(), frow.end(), row) - frow.begin();
   };
-  // original entries
+  // original entries; r starts as each pivot's own conductance to the ground
+  std::vector<double> r(nf, 0.0);
   for (int64_t t = 0; t < w; ++t) {
     const int32_t j = f + (int32_t)t;
-    Fm[t * nf + t] += C.adiag[j];
+    r[t] = C.agnd[j];
     for (int64_t p = C.aptr[j]; p < C.aptr[j + 1]; ++p) Fm[t * nf + pos(C.arow[p])] += C.aval[p];
   }
   // extend-add children
@@ -103,7 +120,10 @@ Status factor_front(Ctx& C, int32_t s, int inner_threads) {
       const double* src = Uc.data() + b * uc;
       for (int64_t a = b; a < uc; ++a) dst[map[a]] += src[a];
     }
+    const std::vector<double>& Rc = C.updr[c];
+    for (int64_t a = 0; a < uc; ++a) r[map[a]] += Rc[a];
     std::vector<double>().swap(Uc);
+    std::vector<double>().swap(C.updr[c]);
   }
   // blocked right-looking L D L^T on the first w columns
   constexpr int64_t NB = 32;
@@ -112,8 +132,12 @@ Status factor_front(Ctx& C, int32_t s, int inner_threads) {
     const int64_t j1 = std::min(w, j0 + NB);
     for (int64_t j = j0; j < j1; ++j) {
       double* cj = Fm + j * nf;
-      const double d = cj[j];
-      if (!(d > 0.0) || !std::isfinite(d)) {
+      // the pivot as a sum of nonnegative terms (see the header); the
+      // updated diagonal entry cj[j] is not used
+      double off = 0.0;
+      for (int64_t i = j + 1; i < nf; ++i) off -= cj[i];
+      const double d = r[j] + off;
+      if (!(d > 0.0) || !std::isfinite(d) || !(off >= 0.0)) {
         std::lock_guard<std::mutex> g(C.err_mu);
         C.err_msg = "non-positive pivot at column " + std::to_string(f + j);
         return E_NOT_SPD;
@@ -121,6 +145,8 @@ Status factor_front(Ctx& C, int32_t s, int inner_threads) {
       C.F.D[f + j] = d;
       const double inv = 1.0 / d;
       for (int64_t i = j + 1; i < nf; ++i) cj[i] *= inv;
+      // the remaining rows' conductances to the ground through node j
+      for (int64_t i = j + 1; i < nf; ++i) r[i] -= cj[i] * r[j];
       for (int64_t k = j + 1; k < j1; ++k) {
         const double a = cj[k] * d;
         double* ck = Fm + k * nf;
@@ -158,13 +184,14 @@ Status factor_front(Ctx& C, int32_t s, int inner_threads) {
     Us.assign((size_t)(u * u), 0.0);
     for (int64_t b = 0; b < u; ++b)
       for (int64_t a = b; a < u; ++a) Us[b * u + a] = Fm[(w + b) * nf + (w + a)];
+    C.updr[s].assign(r.begin() + w, r.end());
   }
   return OK;
 }
 
 }  // namespace
 
-Status ldlt_numeric(const SymCsr& A, const std::vector<double>& diag, const Symbolic& S, int threads,
+Status ldlt_numeric(const SymCsr& A, const std::vector<double>& gnd, const Symbolic& S, int threads,
                     Numeric& F) {
   const int32_t N = S.N;
   if (threads <= 0) threads = default_threads();
@@ -177,10 +204,10 @@ Status ldlt_numeric(const SymCsr& A, const std::vector<double>& diag, const Symb
     aptr[j + 1] = aptr[j] + c;
   }
   std::vector<int32_t> arow(aptr[N]);
-  std::vector<double> aval(aptr[N]), adiag(N);
+  std::vector<double> aval(aptr[N]), agnd(N);
   for (int32_t j = 0; j < N; ++j) {
     const int32_t r = S.perm[j];
-    adiag[j] = diag[r];
+    agnd[j] = gnd[r];
     int64_t q = aptr[j];
     for (int64_t p = A.ptr[r]; p < A.ptr[r + 1]; ++p) {
       const int32_t i = S.iperm[A.idx[p]];
@@ -189,7 +216,7 @@ Status ldlt_numeric(const SymCsr& A, const std::vector<double>& diag, const Symb
   }
   F.Lx.assign(S.colptr[N], 0.0);
   F.D.assign(N, 0.0);
-  Ctx C{S, aptr, arow, aval, adiag, {}, {}, {}, {}, F, {}, OK, {}};
+  Ctx C{S, aptr, arow, aval, agnd, {}, {}, {}, {}, {}, F, {}, OK, {}};
   const int32_t ns = (int32_t)S.snptr.size() - 1;
   C.sn_of.resize(N);
   for (int32_t s = 0; s < ns; ++s)
@@ -204,6 +231,7 @@ Status ldlt_numeric(const SymCsr& A, const std::vector<double>& diag, const Symb
     }
   }
   C.upd.assign(ns, {});
+  C.updr.assign(ns, {});
   // work per supernode and per subtree (supernodes are in postorder)
   std::vector<double> work(ns), sub(ns);
   double total = 0;
