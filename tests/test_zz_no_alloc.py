@@ -38,11 +38,16 @@ def _pairs(g, size, seed):
 def test_noalloc_matches_peers_query_twice(setup):
     import torch
     d, g, f = setup
-    used0 = P.peers_device_usage(d)[0]
+    cases = []
     for size, seed in ((3000, 1), (400, 2)):   # the second call is smaller
         u, v = _pairs(g, size, seed)
         ref = np.empty(len(u))
         P.peers_query(f, u, v, ref)
+        cases.append((u, v, ref))
+    torch.cuda.synchronize()
+    used0 = P.peers_device_usage(d)[0]
+    free0 = None
+    for u, v, ref in cases:
         got = np.full(len(u), np.nan)
         P.peers_query_noalloc(f, u, v, got)
         assert np.array_equal(got.view(np.int64), ref.view(np.int64))
@@ -50,7 +55,17 @@ def test_noalloc_matches_peers_query_twice(setup):
         P.peers_query_noalloc(f, u, v, gd)
         torch.cuda.synchronize()
         assert np.array_equal(gd.cpu().numpy().view(np.int64), ref.view(np.int64))
+        del gd
+        # nothing reserved by the library
         assert P.peers_device_usage(d)[0] == used0
+        # nothing taken from the device after the first call (which brings
+        # the fixed scratch array into the device's memory)
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        free = torch.cuda.mem_get_info()[0]
+        if free0 is None:
+            free0 = free
+        assert free >= free0 - (4 << 20)
 
 
 def test_noalloc_all_edges_through_pairs(setup):
