@@ -27,7 +27,9 @@ on the grounded Laplacian ``L_r`` of ``L_G = sum_e w_e e_e e_e^T`` (eq 1), with
   factor     oracles that take a factor L D L^T as data: per-pair LSolve (the
              paper's accuracy protocol, Section V-A) and the dense columns of
              Z = D^{-1/2} L^{-1} that the sweep produces implicitly (Lemma 3)
+  sparsify   Algorithm 1 (sampling edges by w_e R_e) with a counter-based
+             generator, for the device sparsifier
 """
-from . import laplacian, dense, sparse, exact, symbolic, factor  # noqa: F401
+from . import laplacian, dense, sparse, exact, symbolic, factor, sparsify  # noqa: F401
 
-__all__ = ["laplacian", "dense", "sparse", "exact", "symbolic", "factor"]
+__all__ = ["laplacian", "dense", "sparse", "exact", "symbolic", "factor", "sparsify"]
