@@ -229,6 +229,27 @@ peers_status peers_query(peers_factor f, int64_t q, const int32_t* qu, const int
 peers_status peers_query_noalloc(peers_factor f, int64_t q, const int32_t* qu, const int32_t* qv, double* R_out,
                                  uint32_t flags, void* hip_stream);
 
+/* Spectral sparsification by effective resistances (Section II-B,
+ * Algorithm 1): q independent draws of an edge with probability
+ * p_e proportional to w_e R_e; an edge drawn c_e times gets the weight
+ * c_e w_e / (q p_e). Inputs: m edges' conductances w and resistances R (host,
+ * or device with PEERS_IN_DEVICE: typically R straight from
+ * peers_query_all_edges with PEERS_OUT_DEVICE). Outputs: count[m] (int32)
+ * and w_new[m] (0 for edges never drawn), host or device (PEERS_OUT_DEVICE).
+ * How the draws are made, so that any implementation can reproduce them:
+ *   k_e = floor(2^s * fl(w_e * R_e)), s = 61 - ceil(log2 m), K = sum of k_e,
+ *   p_e = k_e / K (integer weights: the prefix sums are exact);
+ *   draw i (0 <= i < q) takes the first output word x of Philox4x64-10
+ *   (Salmon, Moraes, Dror, Shaw, SC 2011) at counter (i, 0, 0, 0) and key
+ *   (seed, 0) and picks the edge e with C_{e-1} <= floor(x K / 2^64) < C_e,
+ *   C the inclusive prefix sums of k;
+ *   w_new_e = c_e * w_e * (K / (q * k_e)) in FP64, in that order.
+ * Synchronous. Errors: INVALID_ARG (m < 1, q outside [0, 2^31 - 1], some
+ * w_e R_e not finite or outside [0, 2], or every k_e zero), OVER_BUDGET,
+ * HIP. */
+peers_status peers_sparsify(peers_device d, int64_t m, const double* w, const double* R, int64_t q, uint64_t seed,
+                            int32_t* count, double* w_new, uint32_t flags, void* hip_stream);
+
 /* Batched form (many graphs of uneven size): the sweeps of nb resident
  * factors on one device run as one sequence of grouped launches, one launch
  * per step of the sweep covering that step of every factor, captured as a HIP

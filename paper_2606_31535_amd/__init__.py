@@ -119,6 +119,7 @@ SIGNATURES = {
     "peers_batch_query": (C.c_int, [_vp, C.c_int32, C.POINTER(_vp), _i64p, C.POINTER(_vp),
                                     C.POINTER(_vp), C.POINTER(_vp), C.c_uint32, _vp]),
     "peers_batch_last_info": (C.c_int, [_vp, C.POINTER(peers_batch_info)]),
+    "peers_sparsify": (C.c_int, [_vp, C.c_int64, _vp, _vp, C.c_int64, C.c_uint64, _vp, _vp, C.c_uint32, _vp]),
     "peers_server_start": (C.c_int, [_vp, C.POINTER(peers_server_opts), C.POINTER(_vp)]),
     "peers_server_submit": (C.c_int, [_vp, _vp, C.c_int64, _i32p, _i32p, _f64p, C.POINTER(C.c_uint64)]),
     "peers_server_wait": (C.c_int, [_vp, C.c_uint64, C.c_int64, C.POINTER(C.c_int)]),
@@ -456,6 +457,46 @@ def peers_batch_query(d, factors, qus, qvs, R_outs, flags=0, stream=None):
         flags |= PEERS_IN_DEVICE
     _check(lib().peers_batch_query(d, nb, fa, qa, ua, va, ra, flags, _stream_handle(stream)), "peers_batch_query")
     return R_outs
+
+
+def _vals(x, n, name):
+    """(pointer, is_device, keep-alive) of a 1-D float64 input of length n."""
+    if _is_tensor(x):
+        if str(x.dtype) != "torch.float64" or x.dim() != 1 or not x.is_contiguous() or int(x.shape[0]) != n:
+            raise ValueError(f"{name}: expected a contiguous 1-D torch.float64 tensor of length {n}")
+        return int(x.data_ptr()), bool(x.is_cuda), x
+    a = np.ascontiguousarray(x, dtype=np.float64)
+    if a.ndim != 1 or a.shape[0] != n:
+        raise ValueError(f"{name}: expected {n} values")
+    return a.ctypes.data, False, a
+
+
+def peers_sparsify(d, w, R, q, seed, count, w_new, flags=0, stream=None):
+    """Algorithm 1: draw q edges with probability proportional to w_e R_e (see include/peers.h)."""
+    m = int(len(w))
+    pw, dw, kw = _vals(w, m, "w")
+    pR, dR, kR = _vals(R, m, "R")
+    if dw != dR:
+        raise ValueError("w and R must live on the same side")
+    if _is_tensor(count):
+        ok = str(count.dtype) == "torch.int32" and count.dim() == 1 and count.is_contiguous() and count.shape[0] == m
+        pc, dc = int(count.data_ptr()), bool(count.is_cuda)
+    else:
+        ok = isinstance(count, np.ndarray) and count.dtype == np.int32 and count.ndim == 1 and \
+            count.flags.c_contiguous and count.shape[0] == m
+        pc, dc = (count.ctypes.data if ok else 0), False
+    if not ok:
+        raise ValueError(f"count: expected a contiguous 1-D int32 array of length {m}")
+    pn, dn = _out(w_new, m, "w_new")
+    if dc != dn:
+        raise ValueError("count and w_new must live on the same side")
+    if dw:
+        flags |= PEERS_IN_DEVICE
+    if dn:
+        flags |= PEERS_OUT_DEVICE
+    _check(lib().peers_sparsify(d, m, pw, pR, int(q), int(seed), pc, pn, flags, _stream_handle(stream)),
+           "peers_sparsify")
+    return count, w_new
 
 
 def peers_batch_last_info(d) -> dict:
