@@ -447,6 +447,45 @@ def bench_plain(args, g, desc, cpu=None) -> dict:
         acc["max_rel_err_oracle_sample"] = float(np.max(np.abs(Rh[e] - Ro) / Ro))
         acc["oracle_sample_edges"] = int(len(e))
 
+    # second workload on the same factor: every node's resistance to the
+    # ground (eq 4, t = g), against the stored oracle sample
+    Rg = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    P.peers_query_all_to_ground(f, Rg, stream=stream)  # builds and keeps its plan
+    torch.cuda.synchronize()
+    nsteps = max(1, min(args.steps, 10))
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        P.peers_query_all_to_ground(f, Rg, stream=stream)
+    torch.cuda.synchronize()
+    dtg = (time.perf_counter() - t0) / nsteps
+    Rgh = Rg.cpu().numpy()
+    ground = {"value": round(g.n / dtg, 1), "unit": "resistances/s", "ms_per_step": round(dtg * 1e3, 4),
+              "sum_R_ug": math.fsum(Rgh), "what": "R between every node and the ground (resident plan)"}
+    gold = os.path.join(ROOT, "tests", "golden", f"{args.workload}_ground.json")
+    if os.path.exists(gold):
+        with open(gold) as fh:
+            d = json.load(fh)
+        nodes = np.array(d["nodes"])
+        Ro = np.array([float(x) for x in d["R"]])
+        ground["max_rel_err_oracle_sample"] = float(np.max(np.abs(Rgh[nodes] - Ro) / Ro))
+        ground["oracle_sample_nodes"] = int(len(nodes))
+    # Algorithm 1 on the device: sample 4n edges by w_e R_e from the sweep's
+    # resistances (already in device memory)
+    wd = torch.tensor(g.w, dtype=torch.float64, device="cuda")
+    cd = torch.empty(g.m, dtype=torch.int32, device="cuda")
+    nd = torch.empty(g.m, dtype=torch.float64, device="cuda")
+    qs = 4 * g.n
+    P.peers_sparsify(dev, wd, R, qs, 1, cd, nd, stream=stream)
+    t0 = time.perf_counter()
+    for k in range(nsteps):
+        P.peers_sparsify(dev, wd, R, qs, 1 + k, cd, nd, stream=stream)
+    torch.cuda.synchronize()
+    dts = (time.perf_counter() - t0) / nsteps
+    sparsifier = {"draws": qs, "ms_per_call": round(dts * 1e3, 4), "draws_per_s": round(qs / dts, 1),
+                  "edges_kept": int((cd > 0).sum().item()), "edges": g.m,
+                  "what": "Algorithm 1 on the all-edge resistances in device memory (synchronous call)"}
+    del wd, cd, nd
+
     out = {
         "metric": METRIC, "value": round(g.m / dt, 1), "unit": "resistances/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 4),
@@ -468,11 +507,26 @@ def bench_plain(args, g, desc, cpu=None) -> dict:
                     "resistances_per_s_including_plan": round(g.m / (tm["t_edge_plan_s"] + dt), 1),
                     "note": "all-edge plan built once at upload; results stay in device memory"},
         "hbm_bytes": {"resident": resident, "workspace": workspace},
+        "node_to_ground": ground,
+        "sparsifier": sparsifier,
     }
     if cpu is not None:
         cb, sel, Rs = cpu
         cb["max_rel_diff_vs_gpu"] = float(np.max(np.abs(Rh[sel] - Rs) / Rs))
         out["cpu_baseline"] = cb
+    if not args.no_cpu_scheme:
+        # the paper's own parallel scheme (Algorithms 3-8) on this host's
+        # cores, same factor and queries: the same-host context number
+        Rc = np.full(g.m, np.nan)
+        sc = P.peers_cpu_query(h, g.eu, g.ev, Rc, threads=host_workers())
+        pc = {"value": round(g.m / sc["t_rows_s"], 1), "unit": "resistances/s", "cores": sc["threads"],
+              "cpu_model": cpu_model(), "t_rows_s": round(sc["t_rows_s"], 3), "t_setup_s": round(sc["t_setup_s"], 3),
+              "what": "Algorithms 3-8 (CAS row claims, incremental DFS with rollback, row-wise accumulation) in C++ "
+                      "threads on the library's host factor, all edges",
+              "max_rel_diff_vs_gpu": float(np.max(np.abs(Rc - Rh)[Rh > 0] / Rh[Rh > 0]))}
+        if "oracle_sample_edges" in acc:
+            pc["max_rel_err_oracle_sample"] = float(np.max(np.abs(Rc[e] - Ro) / Ro))
+        out["cpu_paper_scheme"] = pc
     P.peers_factor_release(f)
     P.peers_device_close(dev)
     P.peers_graph_destroy(h)
@@ -489,6 +543,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=256, help="graphs in the C4 batch")
     ap.add_argument("--cpu-sample", type=int, default=768)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-scheme", action="store_true", help="leave out the paper's CPU scheme timing")
     ap.add_argument("--no-batched", action="store_true", help="leave the batched sub-object out of the C3 line")
     ap.add_argument("--no-served", action="store_true", help="leave the served sub-object out of the C3 line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",

@@ -90,12 +90,20 @@ class peers_server_stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class peers_cpu_stats(C.Structure):
+    _fields_ = [("threads", C.c_int32), ("rows", C.c_int64), ("t_setup_s", C.c_double), ("t_rows_s", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _vp = C.c_void_p
 _i32p = C.POINTER(C.c_int32)
 _i64p = C.POINTER(C.c_int64)
 _f64p = C.POINTER(C.c_double)
 
 # name -> (restype, argtypes); every name is an exported symbol of include/peers.h
+# or include/peers_cpu.h
 SIGNATURES = {
     "peers_graph_create": (C.c_int, [C.c_int64, C.c_int64, _i32p, _i32p, _f64p, C.c_int32,
                                      C.POINTER(peers_graph_opts), C.POINTER(_vp)]),
@@ -126,6 +134,7 @@ SIGNATURES = {
     "peers_server_cancel": (C.c_int, [_vp, C.c_uint64]),
     "peers_server_stats_get": (C.c_int, [_vp, C.POINTER(peers_server_stats)]),
     "peers_server_stop": (C.c_int, [_vp]),
+    "peers_cpu_query": (C.c_int, [_vp, C.c_int64, _i32p, _i32p, C.c_int32, _f64p, C.POINTER(peers_cpu_stats)]),
     "peers_status_string": (C.c_char_p, [C.c_int]),
     "peers_last_error": (C.c_char_p, []),
 }
@@ -549,6 +558,21 @@ def peers_server_stats_get(s) -> dict:
 def peers_server_stop(s):
     if s:
         _check(lib().peers_server_stop(s), "peers_server_stop")
+
+
+def peers_cpu_query(g, qu, qv, R_out, threads=0):
+    """The paper's CPU scheme (include/peers_cpu.h) on the graph's host factor; returns its statistics."""
+    pu, du, ku, q = _ids(qu, "qu")
+    pv, dv, kv, q2 = _ids(qv, "qv")
+    if du or dv or q != q2:
+        raise ValueError("host node ids of equal length expected")
+    pr, dr = _out(R_out, q, "R_out")
+    if dr:
+        raise ValueError("the CPU scheme writes host memory")
+    st = peers_cpu_stats()
+    _check(lib().peers_cpu_query(g, q, C.cast(pu, _i32p), C.cast(pv, _i32p), int(threads), C.cast(pr, _f64p),
+                                 C.byref(st)), "peers_cpu_query")
+    return st.as_dict()
 
 
 def peers_status_string(st) -> str:

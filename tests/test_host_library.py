@@ -181,10 +181,36 @@ def test_single_node_and_two_node_graphs():
 
 
 def test_library_exports_every_declared_symbol():
-    header = open(os.path.join(ROOT, "include", "peers.h")).read()
-    declared = set(re.findall(r"\b(peers_[a-z_]+)\s*\(", header))
+    declared = set()
+    for hname in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if hname.endswith(".h"):
+            header = open(os.path.join(ROOT, "include", hname)).read()
+            declared |= set(re.findall(r"\b(peers_[a-z_]+)\s*\(", header))
     assert declared, "no declarations parsed"
     assert declared == set(P.SIGNATURES), declared ^ set(P.SIGNATURES)
     L = P.lib()
     for name in declared:
         assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("name", ["mesh32", "rand", "tree", "rgg"])
+def test_paper_cpu_scheme_vs_dense_oracle(name):
+    # the paper's own CPU scheme (Algorithms 3-8) on the library's host factor:
+    # every edge and some node-to-ground and non-edge pairs against the
+    # dense oracle, with one and with several threads
+    g = GRAPHS[name]()
+    rng = np.random.default_rng(4)
+    qu = np.concatenate([g.eu, rng.integers(0, g.n, 200), [g.ground, 3]]).astype(np.int32)
+    qv = np.concatenate([g.ev, rng.integers(0, g.n, 200), [g.ground, g.ground]]).astype(np.int32)
+    Ro = dense.resistances(g, qu, qv)
+    h = _create(g)
+    try:
+        for threads in (1, 4):
+            R = np.full(len(qu), np.nan)
+            st = P.peers_cpu_query(h, qu, qv, R, threads=threads)
+            assert st["rows"] == g.n - 1 and st["threads"] == threads
+            nz = Ro > 0
+            assert np.all(R[~nz] == 0.0)
+            assert np.max(np.abs(R[nz] - Ro[nz]) / Ro[nz]) <= 1e-10
+    finally:
+        P.peers_graph_destroy(h)
