@@ -442,10 +442,10 @@ def bench_plain(args, g, desc, cpu=None) -> dict:
     if os.path.exists(gold):
         with open(gold) as fh:
             d = json.load(fh)
-        e = np.array(d["edges"])
-        Ro = np.array([float(x) for x in d["R"]])
-        acc["max_rel_err_oracle_sample"] = float(np.max(np.abs(Rh[e] - Ro) / Ro))
-        acc["oracle_sample_edges"] = int(len(e))
+        gold_e = np.array(d["edges"])
+        gold_R = np.array([float(x) for x in d["R"]])
+        acc["max_rel_err_oracle_sample"] = float(np.max(np.abs(Rh[gold_e] - gold_R) / gold_R))
+        acc["oracle_sample_edges"] = int(len(gold_e))
 
     # second workload on the same factor: every node's resistance to the
     # ground (eq 4, t = g), against the stored oracle sample
@@ -465,10 +465,10 @@ def bench_plain(args, g, desc, cpu=None) -> dict:
     if os.path.exists(gold):
         with open(gold) as fh:
             d = json.load(fh)
-        nodes = np.array(d["nodes"])
-        Ro = np.array([float(x) for x in d["R"]])
-        ground["max_rel_err_oracle_sample"] = float(np.max(np.abs(Rgh[nodes] - Ro) / Ro))
-        ground["oracle_sample_nodes"] = int(len(nodes))
+        gold_n = np.array(d["nodes"])
+        gold_Rg = np.array([float(x) for x in d["R"]])
+        ground["max_rel_err_oracle_sample"] = float(np.max(np.abs(Rgh[gold_n] - gold_Rg) / gold_Rg))
+        ground["oracle_sample_nodes"] = int(len(gold_n))
     # Algorithm 1 on the device: sample 4n edges by w_e R_e from the sweep's
     # resistances (already in device memory)
     wd = torch.tensor(g.w, dtype=torch.float64, device="cuda")
@@ -525,7 +525,7 @@ def bench_plain(args, g, desc, cpu=None) -> dict:
                       "threads on the library's host factor, all edges",
               "max_rel_diff_vs_gpu": float(np.max(np.abs(Rc - Rh)[Rh > 0] / Rh[Rh > 0]))}
         if "oracle_sample_edges" in acc:
-            pc["max_rel_err_oracle_sample"] = float(np.max(np.abs(Rc[e] - Ro) / Ro))
+            pc["max_rel_err_oracle_sample"] = float(np.max(np.abs(Rc[gold_e] - gold_R) / gold_R))
         out["cpu_paper_scheme"] = pc
     P.peers_factor_release(f)
     P.peers_device_close(dev)

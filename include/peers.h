@@ -76,6 +76,11 @@ typedef struct {
   int32_t leaf_size;          /* nested-dissection leaf size; 0 = 64 */
   int32_t store_offsets_64;   /* 1: the sweep addresses the top store with 64-bit offsets even
                                  when 32-bit ones suffice (they are used above 4 GB); for tests */
+  int32_t numeric_on_device;  /* 1: the numeric L D L^T is formed on the GPU by the first
+                                 peers_factor_upload of the graph (bottom subtrees, then the
+                                 top chains level by level with FP64 matrix-core products);
+                                 until then peers_graph_export_factor returns UNSUPPORTED and
+                                 t_numeric is 0; afterwards t_numeric is the device time */
 } peers_graph_opts;
 
 typedef struct {
@@ -107,7 +112,11 @@ peers_status peers_graph_stats_get(peers_graph g, peers_graph_stats* out);
  * snptr[n_supernodes+1]: fundamental supernode column ranges. Any pointer may be NULL. */
 peers_status peers_graph_export_symbolic(peers_graph g, int32_t* perm, int32_t* parent, int64_t* colptr,
                                          int32_t* rowidx, int32_t* snptr);
-/* Numeric factor: Lx[nnz_l] aligned with rowidx, D[N] pivots. Either may be NULL. */
+/* Numeric factor: Lx[nnz_l] aligned with rowidx, D[N] pivots. Either may be NULL.
+ * Every pivot is formed as a sum of nonnegative terms (the node's conductance
+ * to the ground plus its off-diagonal Schur magnitudes), so L and D carry
+ * small relative errors entry by entry. Errors: UNSUPPORTED when the graph
+ * was created with numeric_on_device and has not been uploaded yet. */
 peers_status peers_graph_export_factor(peers_graph g, double* Lx, double* D);
 void peers_graph_destroy(peers_graph g);
 

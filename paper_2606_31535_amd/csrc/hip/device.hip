@@ -13,6 +13,7 @@
 
 #include "../../../include/peers.h"
 #include "../host/graph_handle.h"
+#include "../host/numplan.h"
 #include "batch.h"
 #include "device_handle.h"
 #include "sweep_kernels.h"
@@ -308,8 +309,17 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
   F->depth = G.sym.depth;
   F->plan.reset(new FactorPlan());
   double tp = now_s();
-  Status st = build_plan(G.sym, G.num, *F->plan);
+  // a graph created with numeric_on_device has no factor values yet: the
+  // layout is built with placeholders and the device factorization fills them
+  const bool dev_numeric = !G.numeric_ready;
+  Status st = build_plan(G.sym, dev_numeric ? nullptr : &G.num, *F->plan);
   if (st != OK) return (peers_status)st;
+  std::unique_ptr<NumericPlan> NP;
+  if (dev_numeric) {
+    NP.reset(new NumericPlan());
+    st = build_numeric_plan(G.ing, G.sym, *F->plan, *NP);
+    if (st != OK) return (peers_status)st;
+  }
   F->t_layout = now_s() - tp;
   const FactorPlan& P = *F->plan;
   F->anc.build(G.sym.parent, G.sym.depth, P);
@@ -400,6 +410,20 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
   he = hipStreamSynchronize(s);
   if (he != hipSuccess) { (void)hipFree(lucbuf); D->release(luc_bytes); return (peers_status)hip_fail(he, "upload"); }
   F->t_transfer = now_s() - tp;
+  if (dev_numeric) {
+    // the factor on the device; its values are copied back into the graph
+    // handle (exports, later uploads, the host scheme)
+    GraphHandle& Gm = const_cast<GraphHandle&>(G);
+    double ms = 0;
+    st = device_factor(*F, G, *NP, const_cast<double*>(lcc_dev), (double*)lucbuf, s, &Gm.num, &ms);
+    if (st != OK) { (void)hipFree(lucbuf); D->release(luc_bytes); return (peers_status)st; }
+    Gm.numeric_ready = true;
+    Gm.stats.t_numeric = ms * 1e-3;
+    F->t_numeric_device = ms * 1e-3;
+    NP.reset();
+    std::vector<int64_t>().swap(F->plan->coef_p);
+    std::vector<int64_t>().swap(F->plan->coef_off);
+  }
   {
     const double t0 = now_s();
     int32_t nl = 0;

@@ -64,7 +64,7 @@ struct FactorHandle {
   void* xbuf = nullptr;   // L_CC^{-1} workspace
   void* tbuf = nullptr;   // recursion temporaries
   void* btbuf = nullptr;  // transfer blocks B_C (resident)
-  double t_transform = 0, t_layout = 0, t_edge_plan = 0, t_transfer = 0;
+  double t_transform = 0, t_layout = 0, t_edge_plan = 0, t_transfer = 0, t_numeric_device = 0;
   void* part = nullptr;
   void* res = nullptr;
   void* stage = nullptr;  // staged bottom columns of non-ancestor pairs
@@ -84,6 +84,14 @@ struct FactorHandle {
 };
 
 Status hip_fail(hipError_t e, const char* what);
+struct GraphHandle;
+struct NumericPlan;
+struct Numeric;
+// The numeric factorization on the device (factor.hip): fills the sweep
+// layout's coefficients, D^{-1/2}, L_CC (lcc_dev) and L_{U,C} (luc_dev), and
+// copies L and D into host_out.
+Status device_factor(FactorHandle& F, const GraphHandle& G, const NumericPlan& Q, double* lcc_dev, double* luc_dev,
+                     hipStream_t s, Numeric* host_out, double* device_ms);
 Status upload_query_plan(FactorHandle& F, const QueryPlan& Q, DeviceQueryPlan& D, hipStream_t s);
 // Device bytes of a plan, and its upload into caller memory (not owned by D).
 uint64_t query_plan_bytes(const QueryPlan& Q);

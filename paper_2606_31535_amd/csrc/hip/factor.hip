@@ -1,0 +1,460 @@
+// Numeric factorization P L_r P^T = L D L^T on the device (Algorithm 8,
+// step 1), following the plan of host/numplan.h: bottom subtrees (one
+// wavefront per task, right-looking in the factor's compressed columns), the
+// pulls of bottom contributions into the top columns' dense depth-indexed
+// fronts (the top store's layout, used as workspace), then per chain level
+// the diagonal blocks, the rows of U_C, the products L_{U,C} D_C L_{U,C}^T on
+// the matrix cores (the sweep's GEMM body) and the subtraction of those
+// products from the ancestor columns. Every pivot is the node's conductance to
+// the ground plus the magnitudes of its off-diagonal Schur entries, and every
+// update adds terms of the sign of what it updates, so no step cancels.
+// Each reduction and each update runs in a fixed order: the factor is the
+// same bits on every run.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "../host/graph_handle.h"
+#include "../host/numplan.h"
+#include "device_handle.h"
+#include "sweep_kernels.h"
+
+namespace peers {
+
+namespace {
+
+struct FacArgs {
+  const int64_t* colptr;
+  const int32_t* rowidx;
+  const int32_t* depth;
+  const int32_t* top_index;  // per node, -1 for bottom nodes
+  const int32_t* u_depth;
+  double* Lx;
+  double* D;
+  double* r;     // conductance to the ground, accumulated per node
+  double* rfin;  // r of each node when it is eliminated
+  double* e;     // per top index: r plus the sums of the rows above the chain
+  // bottom
+  const int32_t* bt_ptr;
+  const int32_t* bcol;
+  const int64_t* bpair_ptr;
+  const int64_t* bpair;
+  // pulls
+  const int32_t* tg_ptr;
+  const int32_t* tg_k;
+  const int64_t* tg_p;
+  // chains (the sweep layout's tables)
+  const Chain* chains;
+  const int32_t* top_node;
+  const int64_t* top_off;
+  double* T;
+  double* lcc;
+  double* luc;
+  double* lud;
+  double* G;
+  const int64_t* g_off;
+  const int32_t* lev_chain;
+  const int32_t* ur_chain;
+  const int32_t* ur_row0;
+  const int32_t* sc_dest;
+  const int32_t* sc_src_ptr;
+  const int32_t* sc_chain;
+  const int32_t* sc_pos;
+  // outputs into the sweep layout
+  const int64_t* top_pos;
+  const int64_t* top_src;
+  const int64_t* coef_p;
+  const int64_t* coef_off;
+  char* bnode_base;
+  char* bent_base;
+  const int32_t* bnode_node;
+  double* isd;
+  double* top_isd;
+};
+
+// Sum over the 64 lanes in a fixed order (butterfly), same value in every lane.
+__device__ __forceinline__ double wave_sum_all(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Top columns' fronts: element depth(i) - 1 of top column j holds A_ij.
+__global__ __launch_bounds__(64) void fac_front_init_kernel(FacArgs F, int32_t ntop) {
+  const int32_t t = blockIdx.x;
+  if (t >= ntop) return;
+  const int32_t j = F.top_node[t];
+  const int64_t base = F.top_off[t];
+  for (int64_t p = F.colptr[j] + threadIdx.x; p < F.colptr[j + 1]; p += 64)
+    F.T[base + F.depth[F.rowidx[p]] - 1] = F.Lx[p];
+}
+
+// One bottom task: its columns children first.
+__global__ __launch_bounds__(64) void fac_bottom_kernel(FacArgs F) {
+  const int32_t task = blockIdx.x;
+  const int lane = threadIdx.x;
+  for (int32_t x = F.bt_ptr[task]; x < F.bt_ptr[task + 1]; ++x) {
+    const int32_t k = F.bcol[x];
+    const int64_t p0 = F.colptr[k], p1 = F.colptr[k + 1];
+    double s = 0.0;
+    for (int64_t p = p0 + lane; p < p1; p += 64) s -= F.Lx[p];
+    s = wave_sum_all(s);
+    const double rk = F.r[k];
+    const double d = rk + s;
+    if (lane == 0) {
+      F.D[k] = d;
+      F.rfin[k] = rk;
+    }
+    for (int64_t p = p0 + lane; p < p1; p += 64) F.Lx[p] = F.Lx[p] / d;
+    __syncthreads();
+    // rows of the column that are bottom nodes: their ground conductance and
+    // their columns' entries below them
+    int64_t pb = F.bpair_ptr[x];
+    for (int64_t p = p0; p < p1; ++p) {
+      const int32_t j = F.rowidx[p];
+      if (F.top_index[j] >= 0) continue;
+      const double lp = F.Lx[p];
+      if (lane == 0) F.r[j] = fma(-lp, rk, F.r[j]);
+      const double sp = d * lp;
+      for (int64_t q = p + 1 + lane; q < p1; q += 64) {
+        const int64_t tgt = F.bpair[pb + (q - p - 1)];
+        F.Lx[tgt] = fma(-F.Lx[q], sp, F.Lx[tgt]);
+      }
+      pb += p1 - p - 1;
+    }
+    __syncthreads();
+  }
+}
+
+// Each top column subtracts the contributions of the bottom columns that
+// reach it, in the plan's order.
+__global__ __launch_bounds__(64) void fac_pull_kernel(FacArgs F, int32_t ntop) {
+  const int32_t t = blockIdx.x;
+  if (t >= ntop) return;
+  const int lane = threadIdx.x;
+  const int32_t j = F.top_node[t];
+  const int64_t base = F.top_off[t];
+  double racc = 0.0;
+  for (int32_t x = F.tg_ptr[t]; x < F.tg_ptr[t + 1]; ++x) {
+    const int32_t k = F.tg_k[x];
+    const int64_t p = F.tg_p[x];
+    const double lp = F.Lx[p];
+    const double sp = F.D[k] * lp;
+    racc = fma(-lp, F.rfin[k], racc);
+    for (int64_t q = p + 1 + lane; q < F.colptr[k + 1]; q += 64) {
+      double* dst = F.T + base + F.depth[F.rowidx[q]] - 1;
+      *dst = fma(-F.Lx[q], sp, *dst);
+    }
+    __syncthreads();
+  }
+  if (lane == 0) F.r[j] += racc;
+}
+
+// Diagonal block of one chain: the pivots in order. Column t of the chain
+// (node a+t) is the front at T + store_base + t*ld; its diagonal sits at depth
+// index dp + w - 1 - t, the chain rows above it at dp .. dp + w - 2 - t, the
+// rows of U_C below dp. e_t starts as r plus the sum of column t's U-row
+// magnitudes; eliminating column t adds (-L) * e_t and (-L) * r_t to the later
+// columns' e and r (the U rows' own updates are formed afterwards).
+constexpr int kDiagThreads = 256;
+__global__ __launch_bounds__(kDiagThreads) void fac_diag_kernel(FacArgs F, int32_t lev0) {
+  __shared__ double red[kDiagThreads / 64];
+  const Chain C = F.chains[F.lev_chain[lev0 + blockIdx.x]];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int32_t w = C.w, dp = C.dp;
+  const int32_t ta = F.top_index[C.a];
+  double* col0 = F.T + C.store_base;
+  for (int32_t t = tid; t < w; t += kDiagThreads) {
+    const double* col = col0 + (int64_t)t * C.ld;
+    double u = 0.0;
+    for (int32_t d = 0; d < dp; ++d) u -= col[d];
+    F.e[ta + t] = F.r[C.a + t] + u;
+  }
+  __syncthreads();
+  for (int32_t t = 0; t < w; ++t) {
+    double* col = col0 + (int64_t)t * C.ld;
+    const int32_t top = dp + w - 1 - t;  // depth index of the diagonal
+    double s = 0.0;
+    for (int32_t d = dp + tid; d < top; d += kDiagThreads) s -= col[d];
+    s = wave_sum_all(s);
+    if (lane == 0) red[wave] = s;
+    __syncthreads();
+    const double off = (red[0] + red[1]) + (red[2] + red[3]);
+    const double et = F.e[ta + t], rt = F.r[C.a + t];
+    const double dv = et + off;
+    if (tid == 0) {
+      F.D[C.a + t] = dv;
+      F.rfin[C.a + t] = rt;
+    }
+    double* lc = F.lcc + C.lcc_off + (int64_t)t * C.ldl;
+    for (int32_t d = dp + tid; d < top; d += kDiagThreads) {
+      const double l = col[d] / dv;
+      col[d] = l;
+      lc[C.b - (d - dp) - C.a] = l;  // row b - (d - dp)
+    }
+    if (tid == 0) lc[t] = 1.0;
+    __syncthreads();
+    // later columns t2 (node a+t2 at depth index dp + w - 1 - t2)
+    for (int32_t t2 = t + 1 + tid; t2 < w; t2 += kDiagThreads) {
+      const double l = col[dp + w - 1 - t2];
+      const double sl = dv * l;
+      double* c2 = col0 + (int64_t)t2 * C.ld;
+      for (int32_t d = dp; d < dp + w - 1 - t2; ++d) c2[d] = fma(-col[d], sl, c2[d]);
+      F.e[ta + t2] = fma(-l, et, F.e[ta + t2]);
+      F.r[C.a + t2] = fma(-l, rt, F.r[C.a + t2]);
+    }
+    __syncthreads();
+  }
+}
+
+// Rows of U_C: one thread per U node, left-looking over blocks of 16 chain
+// columns, L_{u,t} = (S_{u,t} - sum_{t' < t} L_{u,t'} D_{t'} L_{a+t,t'}) / D_t.
+// Writes L_{U,C} (luc) and D-scaled copies (lud) for the product.
+constexpr int kUrowBlock = 16;
+__global__ __launch_bounds__(64) void fac_urows_kernel(FacArgs F, int32_t ur0) {
+  const int32_t c = F.ur_chain[ur0 + blockIdx.x];
+  const Chain C = F.chains[c];
+  const int32_t e = F.ur_row0[ur0 + blockIdx.x] + threadIdx.x;
+  if (e >= C.nU) return;
+  const int32_t du = F.u_depth[C.u_begin + e] - 1;
+  const double* col0 = F.T + C.store_base;
+  double* lu = F.luc + C.luc_off + e;
+  double* ld = F.lud + C.bt_off + e;
+  const double* lc = F.lcc + C.lcc_off;
+  for (int32_t t0 = 0; t0 < C.w; t0 += kUrowBlock) {
+    const int32_t nb = min(kUrowBlock, C.w - t0);
+    double x[kUrowBlock];
+#pragma unroll
+    for (int i = 0; i < kUrowBlock; ++i) x[i] = i < nb ? col0[(int64_t)(t0 + i) * C.ld + du] : 0.0;
+    for (int32_t t = 0; t < t0; ++t) {
+      const double sl = ld[(int64_t)t * C.ldb];
+      const double* lct = lc + (int64_t)t * C.ldl + t0;
+#pragma unroll
+      for (int i = 0; i < kUrowBlock; ++i)
+        if (i < nb) x[i] = fma(-sl, lct[i], x[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < kUrowBlock; ++i) {
+      if (i < nb) {
+        const int32_t t = t0 + i;
+        const double dv = F.D[C.a + t];
+        const double l = x[i] / dv;
+        const double sl = l * dv;
+        lu[(int64_t)t * C.ldb] = l;
+        ld[(int64_t)t * C.ldb] = sl;
+        const double* lct = lc + (int64_t)t * C.ldl + t0;
+#pragma unroll
+        for (int i2 = 0; i2 < kUrowBlock; ++i2)
+          if (i2 > i && i2 < nb) x[i2] = fma(-sl, lct[i2], x[i2]);
+      }
+    }
+  }
+}
+
+// Each destination column subtracts the products of this level's chains
+// whose U_C holds it, in chain order, and takes their ground conductance.
+__global__ __launch_bounds__(64) void fac_scatter_kernel(FacArgs F, int32_t d0) {
+  const int32_t di = d0 + blockIdx.x;
+  const int32_t t = F.sc_dest[di];
+  const int lane = threadIdx.x;
+  const int64_t base = F.top_off[t];
+  double racc = 0.0;
+  for (int32_t x = F.sc_src_ptr[di]; x < F.sc_src_ptr[di + 1]; ++x) {
+    const Chain C = F.chains[F.sc_chain[x]];
+    const int32_t e = F.sc_pos[x];
+    const double* g = F.G + F.g_off[F.sc_chain[x]] + (int64_t)e * C.ldb;
+    for (int32_t i = e + 1 + lane; i < C.nU; i += 64) {
+      double* dst = F.T + base + F.u_depth[C.u_begin + i] - 1;
+      *dst -= g[i];
+    }
+    double rs = 0.0;
+    for (int32_t k = lane; k < C.w; k += 64) rs = fma(-F.luc[C.luc_off + (int64_t)k * C.ldb + e], F.rfin[C.a + k], rs);
+    racc += wave_sum_all(rs);
+    __syncthreads();
+  }
+  if (lane == 0) F.r[F.top_node[t]] += racc;
+}
+
+// The factor into the sweep's layout: top columns' L from L_CC / L_{U,C},
+// bottom records' coefficients -L_ki, and D^{-1/2}.
+__global__ __launch_bounds__(256) void fac_top_lx_kernel(FacArgs F, int64_t n) {
+  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (x >= n) return;
+  const int64_t src = F.top_src[x];
+  F.Lx[F.top_pos[x]] = (src & kLxFromLuc) ? F.luc[src & ~kLxFromLuc] : F.lcc[src];
+}
+
+__global__ __launch_bounds__(256) void fac_coef_kernel(FacArgs F, int64_t n) {
+  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (x >= n) return;
+  const int64_t off = F.coef_off[x];
+  char* dst = (off & kCoefInBent) ? F.bent_base + (off & ~kCoefInBent) : F.bnode_base + off;
+  *(double*)dst = -F.Lx[F.coef_p[x]];
+}
+
+__global__ __launch_bounds__(256) void fac_isd_kernel(FacArgs F, int32_t N, int32_t ntop, int64_t nrec) {
+  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (x < N) F.isd[x] = 1.0 / sqrt(F.D[x]);
+  if (x < ntop) F.top_isd[x] = 1.0 / sqrt(F.D[F.top_node[x]]);
+  if (x < nrec) *(double*)(F.bnode_base + x * (int64_t)sizeof(BNode)) = 1.0 / sqrt(F.D[F.bnode_node[x]]);
+}
+
+inline unsigned grid1(int64_t n, int64_t per) { return (unsigned)std::max<int64_t>(1, (n + per - 1) / per); }
+
+struct DevBufs {
+  std::vector<void*> ptrs;
+  uint64_t bytes = 0;
+  hipError_t err = hipSuccess;
+  template <class T>
+  T* put(const std::vector<T>& v, hipStream_t s) {
+    void* p = nullptr;
+    const size_t b = std::max<size_t>(v.size() * sizeof(T), 8);
+    if (err == hipSuccess) err = hipMalloc(&p, b);
+    if (err != hipSuccess) return nullptr;
+    ptrs.push_back(p);
+    bytes += b;
+    if (!v.empty()) err = hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+    return (T*)p;
+  }
+  template <class T>
+  T* alloc(size_t n) {
+    void* p = nullptr;
+    const size_t b = std::max<size_t>(n * sizeof(T), 8);
+    if (err == hipSuccess) err = hipMalloc(&p, b);
+    if (err != hipSuccess) return nullptr;
+    ptrs.push_back(p);
+    bytes += b;
+    return (T*)p;
+  }
+  void free_all() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+
+}  // namespace
+
+Status device_factor(FactorHandle& Fh, const GraphHandle& G, const NumericPlan& Q, double* lcc_dev, double* luc_dev,
+                     hipStream_t s, Numeric* host_out, double* device_ms) {
+  const FactorPlan& P = *Fh.plan;
+  const Symbolic& S = G.sym;
+  const int32_t N = S.N;
+  // device memory of the factorization, budgeted while it lives
+  const uint64_t est = (uint64_t)Q.nnz * 12 + (uint64_t)N * 48 + Q.bpair.size() * 8 + Q.tg_k.size() * 12 +
+                       (uint64_t)std::max<int64_t>(Q.g_elems, 1) * 8 + Q.top_pos.size() * 16 + P.coef_p.size() * 16 +
+                       (uint64_t)(1 << 24);
+  Status st = Fh.dev->reserve(est);
+  if (st != OK) return st;
+  DevBufs B;
+  FacArgs A{};
+  A.colptr = B.put(S.colptr, s);
+  A.rowidx = B.put(S.rowidx, s);
+  A.depth = B.put(S.depth, s);
+  A.top_index = B.put(P.top_index, s);
+  A.u_depth = B.put(P.u_depth, s);
+  A.Lx = B.put(Q.lx0, s);
+  A.D = B.alloc<double>(N);
+  A.r = B.put(Q.r0, s);
+  A.rfin = B.alloc<double>(N);
+  A.e = B.alloc<double>(std::max<int32_t>(P.ntop, 1));
+  A.bt_ptr = B.put(Q.bt_ptr, s);
+  A.bcol = B.put(Q.bcol, s);
+  A.bpair_ptr = B.put(Q.bpair_ptr, s);
+  A.bpair = B.put(Q.bpair, s);
+  A.tg_ptr = B.put(Q.tg_ptr, s);
+  A.tg_k = B.put(Q.tg_k, s);
+  A.tg_p = B.put(Q.tg_p, s);
+  A.chains = Fh.sweep.chains;
+  A.top_node = Fh.sweep.top_node;
+  A.top_off = Fh.sweep.top_off;
+  A.T = (double*)Fh.store;
+  A.lcc = lcc_dev;
+  A.luc = luc_dev;
+  A.lud = (double*)Fh.btbuf;
+  A.G = B.alloc<double>((size_t)std::max<int64_t>(Q.g_elems, 1));
+  A.g_off = B.put(Q.g_off, s);
+  A.lev_chain = B.put(Q.lev_chain, s);
+  A.ur_chain = B.put(Q.ur_chain, s);
+  A.ur_row0 = B.put(Q.ur_row0, s);
+  A.sc_dest = B.put(Q.sc_dest, s);
+  A.sc_src_ptr = B.put(Q.sc_src_ptr, s);
+  A.sc_chain = B.put(Q.sc_chain, s);
+  A.sc_pos = B.put(Q.sc_pos, s);
+  A.top_pos = B.put(Q.top_pos, s);
+  A.top_src = B.put(Q.top_src, s);
+  A.coef_p = B.put(P.coef_p, s);
+  A.coef_off = B.put(P.coef_off, s);
+  A.bnode_base = (char*)Fh.sweep.bnode;
+  A.bent_base = (char*)Fh.sweep.bent;
+  A.bnode_node = B.put(Q.bnode_node, s);
+  A.isd = const_cast<double*>(Fh.sweep.isd);
+  A.top_isd = const_cast<double*>(Fh.sweep.top_isd);
+  GemmArgs GA = Fh.gemm;
+  GA.probs = B.put(Q.probs, s);
+  GA.tasks = B.put(Q.tasks, s);
+  GA.buf[BUF_LUC] = luc_dev;
+  GA.buf[BUF_BT] = (double*)Fh.btbuf;
+  GA.buf[BUF_G] = A.G;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipError_t e = B.err;
+  auto finish = [&](Status r) {
+    (void)hipStreamSynchronize(s);
+    for (auto& x : ev)
+      if (x) (void)hipEventDestroy(x);
+    B.free_all();
+    Fh.dev->release(est);
+    return r;
+  };
+  if (e != hipSuccess) return finish(hip_fail(e, "device factorization buffers"));
+  e = hipEventCreate(&ev[0]);
+  if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+  if (e == hipSuccess) e = hipMemsetAsync(Fh.store, 0, (size_t)std::max<int64_t>(P.store_elems, kWin) * 8, s);
+  if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+  if (e != hipSuccess) return finish(hip_fail(e, "device factorization setup"));
+  const int32_t ntop = P.ntop;
+  const int32_t nbt = (int32_t)Q.bt_ptr.size() - 1;
+  if (ntop > 0) hipLaunchKernelGGL(fac_front_init_kernel, dim3(ntop), dim3(64), 0, s, A, ntop);
+  if (nbt > 0) hipLaunchKernelGGL(fac_bottom_kernel, dim3(nbt), dim3(64), 0, s, A);
+  if (ntop > 0) hipLaunchKernelGGL(fac_pull_kernel, dim3(ntop), dim3(64), 0, s, A, ntop);
+  for (int32_t step = 0; step < Q.steps; ++step) {
+    const int32_t nc = Q.lev_ptr[step + 1] - Q.lev_ptr[step];
+    if (nc > 0) hipLaunchKernelGGL(fac_diag_kernel, dim3(nc), dim3(kDiagThreads), 0, s, A, Q.lev_ptr[step]);
+    const int32_t nu = Q.ur_ptr[step + 1] - Q.ur_ptr[step];
+    if (nu > 0) hipLaunchKernelGGL(fac_urows_kernel, dim3(nu), dim3(64), 0, s, A, Q.ur_ptr[step]);
+    e = launch_gemm(GA, Q.gemm_ptr[step], Q.gemm_ptr[step + 1] - Q.gemm_ptr[step], s);
+    if (e != hipSuccess) return finish(hip_fail(e, "device factorization products"));
+    const int32_t nd = Q.sc_ptr[step + 1] - Q.sc_ptr[step];
+    if (nd > 0) hipLaunchKernelGGL(fac_scatter_kernel, dim3(nd), dim3(64), 0, s, A, Q.sc_ptr[step]);
+  }
+  const int64_t ntp = (int64_t)Q.top_pos.size(), ncoef = (int64_t)P.coef_p.size();
+  if (ntp > 0) hipLaunchKernelGGL(fac_top_lx_kernel, dim3(grid1(ntp, 256)), dim3(256), 0, s, A, ntp);
+  if (ncoef > 0) hipLaunchKernelGGL(fac_coef_kernel, dim3(grid1(ncoef, 256)), dim3(256), 0, s, A, ncoef);
+  const int64_t nmax = std::max<int64_t>({(int64_t)N, (int64_t)ntop, Q.bottom_records});
+  hipLaunchKernelGGL(fac_isd_kernel, dim3(grid1(nmax, 256)), dim3(256), 0, s, A, N, ntop, Q.bottom_records);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+  // the store's leading zero block again (windows past a column's depth read it)
+  if (e == hipSuccess) e = hipMemsetAsync(Fh.store, 0, (size_t)kStoreZeroBlock * 8, s);
+  if (e == hipSuccess && host_out) {
+    host_out->Lx.resize(Q.nnz);
+    host_out->D.resize(N);
+    e = hipMemcpyAsync(host_out->Lx.data(), A.Lx, (size_t)Q.nnz * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(host_out->D.data(), A.D, (size_t)N * 8, hipMemcpyDeviceToHost, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return finish(hip_fail(e, "device factorization"));
+  float ms = 0;
+  if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess && device_ms) *device_ms = ms;
+  if (host_out) {
+    for (int32_t i = 0; i < N; ++i)
+      if (!(host_out->D[i] > 0.0) || !std::isfinite(host_out->D[i])) {
+        set_error("non-positive pivot at column " + std::to_string(i));
+        return finish(E_NOT_SPD);
+      }
+  }
+  return finish(OK);
+}
+
+}  // namespace peers

@@ -52,8 +52,12 @@ Status build_graph(int64_t n, int64_t m, const int32_t* eu, const int32_t* ev, c
   st = symbolic_analyze(G.ing.A, order, G.sym);
   if (st != OK) return st;
   double t3 = now_s();
-  st = ldlt_numeric(G.ing.A, G.ing.gnd, G.sym, o.threads, G.num);
-  if (st != OK) return st;
+  G.numeric_on_device = o.numeric_on_device != 0;
+  G.numeric_ready = !G.numeric_on_device;
+  if (!G.numeric_on_device) {
+    st = ldlt_numeric(G.ing.A, G.ing.gnd, G.sym, o.threads, G.num);
+    if (st != OK) return st;
+  }
   double t4 = now_s();
 
   peers_graph_stats& s = G.stats;

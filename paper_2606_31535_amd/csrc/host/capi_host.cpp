@@ -97,6 +97,10 @@ peers_status peers_graph_export_symbolic(peers_graph g, int32_t* perm, int32_t* 
 peers_status peers_graph_export_factor(peers_graph g, double* Lx, double* D) {
   if (!g) { set_error("null graph"); return PEERS_E_INVALID_ARG; }
   const GraphHandle& G = *reinterpret_cast<GraphHandle*>(g);
+  if (!G.numeric_ready) {
+    set_error("the factor of this graph is formed on the device by its first peers_factor_upload");
+    return PEERS_E_UNSUPPORTED;
+  }
   if (Lx && !G.num.Lx.empty()) std::memcpy(Lx, G.num.Lx.data(), sizeof(double) * G.num.Lx.size());
   if (D && !G.num.D.empty()) std::memcpy(D, G.num.D.data(), sizeof(double) * G.num.D.size());
   return PEERS_OK;

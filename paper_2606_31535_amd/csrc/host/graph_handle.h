@@ -14,6 +14,10 @@ struct GraphHandle {
   peers_graph_stats stats{};
   std::vector<int32_t> eu, ev;  // the input edge list (all-edge queries in input order)
   bool store64 = false;         // peers_graph_opts::store_offsets_64
+  // numeric factor formed on the device by the first upload (num is filled
+  // then, from the device's result)
+  bool numeric_on_device = false;
+  bool numeric_ready = true;
 };
 
 Status build_graph(int64_t n, int64_t m, const int32_t* eu, const int32_t* ev, const double* w, int32_t ground,

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <functional>
 
 namespace peers {
@@ -15,13 +16,15 @@ inline int32_t nwin_grouped(int32_t depth) {
 }
 }  // namespace
 
-Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
+Status build_plan(const Symbolic& S, const Numeric* Fp, FactorPlan& P) {
   const int32_t N = S.N;
   P = FactorPlan();
   P.N = N;
   P.height = S.height;
+  const bool record = Fp == nullptr;
+  auto lval = [&](int64_t q) { return Fp ? Fp->Lx[q] : 0.0; };
   P.isd.resize(N);
-  for (int32_t i = 0; i < N; ++i) P.isd[i] = 1.0 / std::sqrt(F.D[i]);
+  for (int32_t i = 0; i < N; ++i) P.isd[i] = Fp ? 1.0 / std::sqrt(Fp->D[i]) : 1.0;
   // subtree size and height
   std::vector<int32_t> size(N, 1), hsub(N, 1);
   for (int32_t i = 0; i < N; ++i) {
@@ -148,8 +151,8 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
         P.lcc[c.lcc_off + (int64_t)j * c.ldl + j] = 1.0;
         for (int64_t p = S.colptr[v]; p < S.colptr[v + 1]; ++p) {
           const int32_t r = S.rowidx[p];
-          if (r <= c.b) P.lcc[c.lcc_off + (int64_t)j * c.ldl + (r - c.a)] = F.Lx[p];
-          else P.luc[c.luc_off + (int64_t)j * c.ldb + upos[r]] = F.Lx[p];
+          if (r <= c.b) P.lcc[c.lcc_off + (int64_t)j * c.ldl + (r - c.a)] = lval(p);
+          else P.luc[c.luc_off + (int64_t)j * c.ldb + upos[r]] = lval(p);
         }
         for (int64_t p = S.colptr[v]; p < S.colptr[v + 1]; ++p) P.f_top += S.depth[S.rowidx[p]];
       }
@@ -330,14 +333,21 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
       int32_t tinl[2] = {-1, -1};
       std::vector<BEnt> more_lds, more_top;
       int32_t nl = 0, nt = 0;
+      const int64_t bidx = (int64_t)P.bnode.size();
+      std::vector<std::pair<int64_t, int64_t>> lds_q, top_q;  // (CSC position, index in its overflow list)
       for (int64_t q = S.colptr[v]; q < S.colptr[v + 1]; ++q) {
         const int32_t k = S.rowidx[q];
-        const double c = -F.Lx[q];
+        const double c = -lval(q);
         if (P.small[k]) {
           if (nl < 3) {
             bn.lc[nl] = c;
             bn.slots |= slot_code(P.lslot[k]) << (kSlotBits * nl);
+            if (record) {
+              P.coef_p.push_back(q);
+              P.coef_off.push_back(bidx * (int64_t)sizeof(BNode) + (int64_t)offsetof(BNode, lc) + 8 * nl);
+            }
           } else {
+            if (record) lds_q.push_back({q, (int64_t)more_lds.size()});
             more_lds.push_back(BEnt{slot_code(P.lslot[k]), c});
           }
           ++nl;
@@ -346,10 +356,27 @@ Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P) {
             bn.tref[nt] = topref(k);
             bn.tc[nt] = c;
             tinl[nt] = k;
+            if (record) {
+              P.coef_p.push_back(q);
+              P.coef_off.push_back(bidx * (int64_t)sizeof(BNode) + (int64_t)offsetof(BNode, tc) + 8 * nt);
+            }
           } else {
+            if (record) top_q.push_back({q, (int64_t)more_top.size()});
             more_top.push_back(BEnt{topref(k), c});
           }
           ++nt;
+        }
+      }
+      if (record) {
+        const int64_t b0 = (int64_t)P.bent.size();
+        for (auto& e : lds_q) {
+          P.coef_p.push_back(e.first);
+          P.coef_off.push_back(kCoefInBent | ((b0 + e.second) * (int64_t)sizeof(BEnt) + (int64_t)offsetof(BEnt, coef)));
+        }
+        for (auto& e : top_q) {
+          P.coef_p.push_back(e.first);
+          P.coef_off.push_back(kCoefInBent | ((b0 + (int64_t)more_lds.size() + e.second) * (int64_t)sizeof(BEnt) +
+                                              (int64_t)offsetof(BEnt, coef)));
         }
       }
       bn.slots |= std::min(nl, 3) << kInlineCountShift;

@@ -66,7 +66,7 @@ constexpr int kWinPerWave = 2;        // windows per bottom wavefront (lane l: d
 constexpr int32_t kGroundCode = INT32_MIN;
 
 // Device buffers a GEMM operand can live in.
-enum GemmBuf : int32_t { BUF_STORE = 0, BUF_LCC = 1, BUF_X = 2, BUF_T = 3, BUF_BT = 4, BUF_LUC = 5, BUF_COUNT = 6 };
+enum GemmBuf : int32_t { BUF_STORE = 0, BUF_LCC = 1, BUF_X = 2, BUF_T = 3, BUF_BT = 4, BUF_LUC = 5, BUF_G = 6, BUF_COUNT = 7 };
 
 // C[M x N] = alpha * A[M x K] * B[K x N]; column-major unless `trans` says
 // otherwise for B or C. Column k of A starts at
@@ -179,9 +179,16 @@ struct FactorPlan {
   int32_t max_lslot = 0;
   // work statistics (FMAs)
   double f_top = 0, f_top_gemm = 0, f_top_inv = 0, f_bpre = 0, f_bottom_computed = 0;
+  // where the coefficient -L_ki of each bottom-column entry (CSC position)
+  // went: a byte offset into the bnode array, or (with kCoefInBent set) into
+  // the bent array; recorded only when the factor is computed on the device
+  std::vector<int64_t> coef_p, coef_off;
 };
+constexpr int64_t kCoefInBent = int64_t(1) << 62;
 
-Status build_plan(const Symbolic& S, const Numeric& F, FactorPlan& P);
+// F may be null: the layout is then built with zero coefficients and unit
+// pivots, and coef_p / coef_off record where the values belong.
+Status build_plan(const Symbolic& S, const Numeric* F, FactorPlan& P);
 
 // A query whose lower endpoint is a bottom node, or a staging entry.
 struct BQuery {

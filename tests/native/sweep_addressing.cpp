@@ -256,7 +256,7 @@ int main(int argc, char** argv) {
   Status st = build_graph(n, m, eu.data(), ev.data(), w.data(), ground, o, G);
   if (st != OK) { std::fprintf(stderr, "build_graph: %d %s\n", st, last_error()); return 3; }
   FactorPlan P;
-  st = build_plan(G.sym, G.num, P);
+  st = build_plan(G.sym, &G.num, P);
   if (st != OK) { std::fprintf(stderr, "build_plan: %d %s\n", st, last_error()); return 3; }
   AncestorTable anc;
   anc.build(G.sym.parent, G.sym.depth, P);
