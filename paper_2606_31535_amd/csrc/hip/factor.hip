@@ -2,14 +2,16 @@
 // step 1), following the plan of host/numplan.h: bottom subtrees (one
 // wavefront per task, right-looking in the factor's compressed columns), the
 // pulls of bottom contributions into the top columns' dense depth-indexed
-// fronts (the top store's layout, used as workspace), then per chain level
-// the diagonal blocks, the rows of U_C, the products L_{U,C} D_C L_{U,C}^T on
-// the matrix cores (the sweep's GEMM body) and the subtraction of those
-// products from the ancestor columns. Every pivot is the node's conductance to
-// the ground plus the magnitudes of its off-diagonal Schur entries, and every
-// update adds terms of the sign of what it updates, so no step cancels.
-// Each reduction and each update runs in a fixed order: the factor is the
-// same bits on every run.
+// fronts (the top store's layout, used as workspace), then per level of the
+// tree of chain pieces (at most 64 columns each) the pieces' diagonal blocks
+// in LDS, the rows of U_P, the products L_{U,P} D_P L_{U,P}^T on the matrix
+// cores (the sweep's GEMM body) and the subtraction of those products from
+// the ancestor columns. The factor's top values are left in the fronts and
+// copied into the sweep layout at the end. Every pivot is the node's
+// conductance to the ground plus the magnitudes of its off-diagonal Schur
+// entries, and every update adds terms of the sign of what it updates, so no
+// step cancels. Each reduction and each update runs in a fixed order: the
+// factor is the same bits on every run.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,12 +32,10 @@ struct FacArgs {
   const int32_t* rowidx;
   const int32_t* depth;
   const int32_t* top_index;  // per node, -1 for bottom nodes
-  const int32_t* u_depth;
   double* Lx;
   double* D;
   double* r;     // conductance to the ground, accumulated per node
   double* rfin;  // r of each node when it is eliminated
-  double* e;     // per top index: r plus the sums of the rows above the chain
   // bottom
   const int32_t* bt_ptr;
   const int32_t* bcol;
@@ -45,25 +45,27 @@ struct FacArgs {
   const int32_t* tg_ptr;
   const int32_t* tg_k;
   const int64_t* tg_p;
-  // chains (the sweep layout's tables)
-  const Chain* chains;
+  // pieces of the top chains
   const int32_t* top_node;
   const int64_t* top_off;
   double* T;
-  double* lcc;
-  double* luc;
-  double* lud;
+  const FacPiece* pieces;
+  const int32_t* pu_depth;
+  const int32_t* pu_top;
+  double* lu;   // L_{U,P} of the step's pieces
+  double* lud;  // the same scaled by D_P
   double* G;
-  const int64_t* g_off;
-  const int32_t* lev_chain;
-  const int32_t* ur_chain;
+  const int32_t* lev_piece;
+  const int32_t* ur_piece;
   const int32_t* ur_row0;
   const int32_t* sc_dest;
   const int32_t* sc_src_ptr;
-  const int32_t* sc_chain;
+  const int32_t* sc_piece;
   const int32_t* sc_pos;
   // outputs into the sweep layout
-  const int64_t* top_pos;
+  double* lcc;
+  double* luc;
+  const int64_t* top_x_ptr;
   const int64_t* top_src;
   const int64_t* coef_p;
   const int64_t* coef_off;
@@ -152,109 +154,114 @@ __global__ __launch_bounds__(64) void fac_pull_kernel(FacArgs F, int32_t ntop) {
   if (lane == 0) F.r[j] += racc;
 }
 
-// Diagonal block of one chain: the pivots in order. Column t of the chain
-// (node a+t) is the front at T + store_base + t*ld; its diagonal sits at depth
-// index dp + w - 1 - t, the chain rows above it at dp .. dp + w - 2 - t, the
-// rows of U_C below dp. e_t starts as r plus the sum of column t's U-row
-// magnitudes; eliminating column t adds (-L) * e_t and (-L) * r_t to the later
-// columns' e and r (the U rows' own updates are formed afterwards).
+// Diagonal block of one piece a..b, in LDS. Column t (node a+t) is the front
+// at T + col_base + t*ld; row a+i (i > t) of it sits at depth index
+// dp + w - 1 - i, the rows of U_P at their depth - 1 (below dp). e_t starts as
+// r plus the magnitudes of column t's U-row entries; eliminating column t
+// adds (-L_{a+i,a+t}) e_t and (-L_{a+i,a+t}) r_t to e and r of the later
+// columns (the U rows' own updates are formed afterwards, row by row). The
+// L values go back into the fronts.
 constexpr int kDiagThreads = 256;
 __global__ __launch_bounds__(kDiagThreads) void fac_diag_kernel(FacArgs F, int32_t lev0) {
-  __shared__ double red[kDiagThreads / 64];
-  const Chain C = F.chains[F.lev_chain[lev0 + blockIdx.x]];
+  __shared__ double blk[kFacPiece * kFacPiece];  // blk[t * 64 + i]: S_{a+i, a+t}, i > t
+  __shared__ double es[kFacPiece], rs[kFacPiece];
+  const FacPiece Pc = F.pieces[F.lev_piece[lev0 + blockIdx.x]];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int32_t w = C.w, dp = C.dp;
-  const int32_t ta = F.top_index[C.a];
-  double* col0 = F.T + C.store_base;
-  for (int32_t t = tid; t < w; t += kDiagThreads) {
-    const double* col = col0 + (int64_t)t * C.ld;
+  const int32_t w = Pc.w, dp = Pc.dp;
+  double* col0 = F.T + Pc.col_base;
+  for (int32_t x = tid; x < w * kFacPiece; x += kDiagThreads) {
+    const int32_t t = x >> 6, i = x & 63;
+    if (i > t && i < w) blk[x] = col0[(int64_t)t * Pc.ld + dp + w - 1 - i];
+  }
+  for (int32_t t = wave; t < w; t += kDiagThreads / 64) {
+    const double* col = col0 + (int64_t)t * Pc.ld;
     double u = 0.0;
-    for (int32_t d = 0; d < dp; ++d) u -= col[d];
-    F.e[ta + t] = F.r[C.a + t] + u;
+    for (int32_t e = lane; e < Pc.nU; e += 64) u -= col[F.pu_depth[Pc.u_begin + e] - 1];
+    u = wave_sum_all(u);
+    if (lane == 0) {
+      const double r = F.r[Pc.a + t];
+      es[t] = r + u;
+      rs[t] = r;
+    }
   }
   __syncthreads();
   for (int32_t t = 0; t < w; ++t) {
-    double* col = col0 + (int64_t)t * C.ld;
-    const int32_t top = dp + w - 1 - t;  // depth index of the diagonal
-    double s = 0.0;
-    for (int32_t d = dp + tid; d < top; d += kDiagThreads) s -= col[d];
-    s = wave_sum_all(s);
-    if (lane == 0) red[wave] = s;
-    __syncthreads();
-    const double off = (red[0] + red[1]) + (red[2] + red[3]);
-    const double et = F.e[ta + t], rt = F.r[C.a + t];
-    const double dv = et + off;
-    if (tid == 0) {
-      F.D[C.a + t] = dv;
-      F.rfin[C.a + t] = rt;
+    const double* bt = blk + t * kFacPiece;
+    // every wave forms the same pivot in the same order
+    const double s = wave_sum_all((lane > t && lane < w) ? -bt[lane] : 0.0);
+    const double et = es[t], rt = rs[t];
+    const double dv = et + s;
+    if (wave == 0) {
+      if (lane == 0) {
+        F.D[Pc.a + t] = dv;
+        F.rfin[Pc.a + t] = rt;
+      }
+      if (lane > t && lane < w) {
+        const double l = bt[lane] / dv;
+        col0[(int64_t)t * Pc.ld + dp + w - 1 - lane] = l;
+        es[lane] = fma(-l, et, es[lane]);
+        rs[lane] = fma(-l, rt, rs[lane]);
+      }
     }
-    double* lc = F.lcc + C.lcc_off + (int64_t)t * C.ldl;
-    for (int32_t d = dp + tid; d < top; d += kDiagThreads) {
-      const double l = col[d] / dv;
-      col[d] = l;
-      lc[C.b - (d - dp) - C.a] = l;  // row b - (d - dp)
-    }
-    if (tid == 0) lc[t] = 1.0;
-    __syncthreads();
-    // later columns t2 (node a+t2 at depth index dp + w - 1 - t2)
-    for (int32_t t2 = t + 1 + tid; t2 < w; t2 += kDiagThreads) {
-      const double l = col[dp + w - 1 - t2];
-      const double sl = dv * l;
-      double* c2 = col0 + (int64_t)t2 * C.ld;
-      for (int32_t d = dp; d < dp + w - 1 - t2; ++d) c2[d] = fma(-col[d], sl, c2[d]);
-      F.e[ta + t2] = fma(-l, et, F.e[ta + t2]);
-      F.r[C.a + t2] = fma(-l, rt, F.r[C.a + t2]);
+    // S_{a+i, a+t2} -= L_{a+i,a+t} D_t L_{a+t2,a+t} for t < t2 < i
+    if (lane > t + 1 && lane < w) {
+      const double li = bt[lane] / dv;
+      for (int32_t t2 = t + 1 + wave; t2 < lane; t2 += kDiagThreads / 64) {
+        const double sl = dv * (bt[t2] / dv);
+        blk[t2 * kFacPiece + lane] = fma(-li, sl, blk[t2 * kFacPiece + lane]);
+      }
     }
     __syncthreads();
   }
 }
 
-// Rows of U_C: one thread per U node, left-looking over blocks of 16 chain
-// columns, L_{u,t} = (S_{u,t} - sum_{t' < t} L_{u,t'} D_{t'} L_{a+t,t'}) / D_t.
-// Writes L_{U,C} (luc) and D-scaled copies (lud) for the product.
+// Rows of U_P: one thread per U node, left-looking over blocks of 16 piece
+// columns, L_{u,t} = (S_{u,t} - sum_{t' < t} L_{u,t'} D_{t'} L_{a+t,t'}) / D_t,
+// with L_{a+t,t'} read from the fronts. Writes L_{U,P} back into the fronts
+// and into the step's scratch (plain and D-scaled) for the product.
 constexpr int kUrowBlock = 16;
 __global__ __launch_bounds__(64) void fac_urows_kernel(FacArgs F, int32_t ur0) {
-  const int32_t c = F.ur_chain[ur0 + blockIdx.x];
-  const Chain C = F.chains[c];
+  const FacPiece Pc = F.pieces[F.ur_piece[ur0 + blockIdx.x]];
   const int32_t e = F.ur_row0[ur0 + blockIdx.x] + threadIdx.x;
-  if (e >= C.nU) return;
-  const int32_t du = F.u_depth[C.u_begin + e] - 1;
-  const double* col0 = F.T + C.store_base;
-  double* lu = F.luc + C.luc_off + e;
-  double* ld = F.lud + C.bt_off + e;
-  const double* lc = F.lcc + C.lcc_off;
-  for (int32_t t0 = 0; t0 < C.w; t0 += kUrowBlock) {
-    const int32_t nb = min(kUrowBlock, C.w - t0);
+  if (e >= Pc.nU) return;
+  const int32_t du = F.pu_depth[Pc.u_begin + e] - 1;
+  const int32_t dtop = Pc.dp + Pc.w - 1;  // depth index of row a
+  double* col0 = F.T + Pc.col_base;
+  double* lu = F.lu + Pc.luc_off + e;
+  double* ld = F.lud + Pc.luc_off + e;
+  for (int32_t t0 = 0; t0 < Pc.w; t0 += kUrowBlock) {
+    const int32_t nb = min(kUrowBlock, Pc.w - t0);
     double x[kUrowBlock];
 #pragma unroll
-    for (int i = 0; i < kUrowBlock; ++i) x[i] = i < nb ? col0[(int64_t)(t0 + i) * C.ld + du] : 0.0;
+    for (int i = 0; i < kUrowBlock; ++i) x[i] = i < nb ? col0[(int64_t)(t0 + i) * Pc.ld + du] : 0.0;
     for (int32_t t = 0; t < t0; ++t) {
-      const double sl = ld[(int64_t)t * C.ldb];
-      const double* lct = lc + (int64_t)t * C.ldl + t0;
+      const double sl = ld[(int64_t)t * Pc.ldu];
+      const double* lct = col0 + (int64_t)t * Pc.ld + dtop - t0;  // row a+t0+i at lct[-i]
 #pragma unroll
       for (int i = 0; i < kUrowBlock; ++i)
-        if (i < nb) x[i] = fma(-sl, lct[i], x[i]);
+        if (i < nb) x[i] = fma(-sl, lct[-i], x[i]);
     }
 #pragma unroll
     for (int i = 0; i < kUrowBlock; ++i) {
       if (i < nb) {
         const int32_t t = t0 + i;
-        const double dv = F.D[C.a + t];
+        const double dv = F.D[Pc.a + t];
         const double l = x[i] / dv;
         const double sl = l * dv;
-        lu[(int64_t)t * C.ldb] = l;
-        ld[(int64_t)t * C.ldb] = sl;
-        const double* lct = lc + (int64_t)t * C.ldl + t0;
+        lu[(int64_t)t * Pc.ldu] = l;
+        ld[(int64_t)t * Pc.ldu] = sl;
+        col0[(int64_t)t * Pc.ld + du] = l;
+        const double* lct = col0 + (int64_t)t * Pc.ld + dtop - t0;
 #pragma unroll
         for (int i2 = 0; i2 < kUrowBlock; ++i2)
-          if (i2 > i && i2 < nb) x[i2] = fma(-sl, lct[i2], x[i2]);
+          if (i2 > i && i2 < nb) x[i2] = fma(-sl, lct[-i2], x[i2]);
       }
     }
   }
 }
 
-// Each destination column subtracts the products of this level's chains
-// whose U_C holds it, in chain order, and takes their ground conductance.
+// Each destination column subtracts the products of this level's pieces
+// whose U_P holds it, in piece order, and takes their ground conductance.
 __global__ __launch_bounds__(64) void fac_scatter_kernel(FacArgs F, int32_t d0) {
   const int32_t di = d0 + blockIdx.x;
   const int32_t t = F.sc_dest[di];
@@ -262,28 +269,35 @@ __global__ __launch_bounds__(64) void fac_scatter_kernel(FacArgs F, int32_t d0) 
   const int64_t base = F.top_off[t];
   double racc = 0.0;
   for (int32_t x = F.sc_src_ptr[di]; x < F.sc_src_ptr[di + 1]; ++x) {
-    const Chain C = F.chains[F.sc_chain[x]];
+    const FacPiece Pc = F.pieces[F.sc_piece[x]];
     const int32_t e = F.sc_pos[x];
-    const double* g = F.G + F.g_off[F.sc_chain[x]] + (int64_t)e * C.ldb;
-    for (int32_t i = e + 1 + lane; i < C.nU; i += 64) {
-      double* dst = F.T + base + F.u_depth[C.u_begin + i] - 1;
+    const double* g = F.G + Pc.g_off + (int64_t)e * Pc.ldu;
+    for (int32_t i = e + 1 + lane; i < Pc.nU; i += 64) {
+      double* dst = F.T + base + F.pu_depth[Pc.u_begin + i] - 1;
       *dst -= g[i];
     }
-    double rs = 0.0;
-    for (int32_t k = lane; k < C.w; k += 64) rs = fma(-F.luc[C.luc_off + (int64_t)k * C.ldb + e], F.rfin[C.a + k], rs);
-    racc += wave_sum_all(rs);
+    double rsum = 0.0;
+    for (int32_t k = lane; k < Pc.w; k += 64) rsum = fma(-F.lu[Pc.luc_off + (int64_t)k * Pc.ldu + e], F.rfin[Pc.a + k], rsum);
+    racc += wave_sum_all(rsum);
     __syncthreads();
   }
   if (lane == 0) F.r[F.top_node[t]] += racc;
 }
 
-// The factor into the sweep's layout: top columns' L from L_CC / L_{U,C},
-// bottom records' coefficients -L_ki, and D^{-1/2}.
-__global__ __launch_bounds__(256) void fac_top_lx_kernel(FacArgs F, int64_t n) {
-  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (x >= n) return;
-  const int64_t src = F.top_src[x];
-  F.Lx[F.top_pos[x]] = (src & kLxFromLuc) ? F.luc[src & ~kLxFromLuc] : F.lcc[src];
+// The top columns' factor values from their fronts into the compressed
+// columns and the sweep's L_CC / L_{U,C} blocks.
+__global__ __launch_bounds__(64) void fac_top_lx_kernel(FacArgs F, int32_t ntop) {
+  const int32_t t = blockIdx.x;
+  if (t >= ntop) return;
+  const int32_t j = F.top_node[t];
+  const int64_t base = F.top_off[t], p0 = F.colptr[j], x0 = F.top_x_ptr[t];
+  for (int64_t p = p0 + threadIdx.x; p < F.colptr[j + 1]; p += 64) {
+    const double v = F.T[base + F.depth[F.rowidx[p]] - 1];
+    F.Lx[p] = v;
+    const int64_t src = F.top_src[x0 + (p - p0)];
+    if (src & kLxFromLuc) F.luc[src & ~kLxFromLuc] = v;
+    else F.lcc[src] = v;
+  }
 }
 
 __global__ __launch_bounds__(256) void fac_coef_kernel(FacArgs F, int64_t n) {
@@ -342,9 +356,10 @@ Status device_factor(FactorHandle& Fh, const GraphHandle& G, const NumericPlan& 
   const Symbolic& S = G.sym;
   const int32_t N = S.N;
   // device memory of the factorization, budgeted while it lives
-  const uint64_t est = (uint64_t)Q.nnz * 12 + (uint64_t)N * 48 + Q.bpair.size() * 8 + Q.tg_k.size() * 12 +
-                       (uint64_t)std::max<int64_t>(Q.g_elems, 1) * 8 + Q.top_pos.size() * 16 + P.coef_p.size() * 16 +
-                       (uint64_t)(1 << 24);
+  const uint64_t est = (uint64_t)Q.nnz * 12 + (uint64_t)N * 40 + Q.bpair.size() * 8 + Q.tg_k.size() * 12 +
+                       (uint64_t)(2 * std::max<int64_t>(Q.luc_elems, 1) + std::max<int64_t>(Q.g_elems, 1)) * 8 +
+                       Q.pieces.size() * sizeof(FacPiece) + Q.pu_depth.size() * 8 + Q.top_src.size() * 8 +
+                       P.coef_p.size() * 16 + (uint64_t)(1 << 24);
   Status st = Fh.dev->reserve(est);
   if (st != OK) return st;
   DevBufs B;
@@ -353,12 +368,10 @@ Status device_factor(FactorHandle& Fh, const GraphHandle& G, const NumericPlan& 
   A.rowidx = B.put(S.rowidx, s);
   A.depth = B.put(S.depth, s);
   A.top_index = B.put(P.top_index, s);
-  A.u_depth = B.put(P.u_depth, s);
   A.Lx = B.put(Q.lx0, s);
   A.D = B.alloc<double>(N);
   A.r = B.put(Q.r0, s);
   A.rfin = B.alloc<double>(N);
-  A.e = B.alloc<double>(std::max<int32_t>(P.ntop, 1));
   A.bt_ptr = B.put(Q.bt_ptr, s);
   A.bcol = B.put(Q.bcol, s);
   A.bpair_ptr = B.put(Q.bpair_ptr, s);
@@ -366,23 +379,25 @@ Status device_factor(FactorHandle& Fh, const GraphHandle& G, const NumericPlan& 
   A.tg_ptr = B.put(Q.tg_ptr, s);
   A.tg_k = B.put(Q.tg_k, s);
   A.tg_p = B.put(Q.tg_p, s);
-  A.chains = Fh.sweep.chains;
   A.top_node = Fh.sweep.top_node;
   A.top_off = Fh.sweep.top_off;
   A.T = (double*)Fh.store;
-  A.lcc = lcc_dev;
-  A.luc = luc_dev;
-  A.lud = (double*)Fh.btbuf;
+  A.pieces = B.put(Q.pieces, s);
+  A.pu_depth = B.put(Q.pu_depth, s);
+  A.pu_top = B.put(Q.pu_top, s);
+  A.lu = B.alloc<double>((size_t)std::max<int64_t>(Q.luc_elems, 1));
+  A.lud = B.alloc<double>((size_t)std::max<int64_t>(Q.luc_elems, 1));
   A.G = B.alloc<double>((size_t)std::max<int64_t>(Q.g_elems, 1));
-  A.g_off = B.put(Q.g_off, s);
-  A.lev_chain = B.put(Q.lev_chain, s);
-  A.ur_chain = B.put(Q.ur_chain, s);
+  A.lev_piece = B.put(Q.lev_piece, s);
+  A.ur_piece = B.put(Q.ur_piece, s);
   A.ur_row0 = B.put(Q.ur_row0, s);
   A.sc_dest = B.put(Q.sc_dest, s);
   A.sc_src_ptr = B.put(Q.sc_src_ptr, s);
-  A.sc_chain = B.put(Q.sc_chain, s);
+  A.sc_piece = B.put(Q.sc_piece, s);
   A.sc_pos = B.put(Q.sc_pos, s);
-  A.top_pos = B.put(Q.top_pos, s);
+  A.lcc = lcc_dev;
+  A.luc = luc_dev;
+  A.top_x_ptr = B.put(Q.top_x_ptr, s);
   A.top_src = B.put(Q.top_src, s);
   A.coef_p = B.put(P.coef_p, s);
   A.coef_off = B.put(P.coef_off, s);
@@ -394,8 +409,8 @@ Status device_factor(FactorHandle& Fh, const GraphHandle& G, const NumericPlan& 
   GemmArgs GA = Fh.gemm;
   GA.probs = B.put(Q.probs, s);
   GA.tasks = B.put(Q.tasks, s);
-  GA.buf[BUF_LUC] = luc_dev;
-  GA.buf[BUF_BT] = (double*)Fh.btbuf;
+  GA.buf[BUF_LUC] = A.lu;
+  GA.buf[BUF_BT] = A.lud;
   GA.buf[BUF_G] = A.G;
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipError_t e = B.err;
@@ -428,8 +443,8 @@ Status device_factor(FactorHandle& Fh, const GraphHandle& G, const NumericPlan& 
     const int32_t nd = Q.sc_ptr[step + 1] - Q.sc_ptr[step];
     if (nd > 0) hipLaunchKernelGGL(fac_scatter_kernel, dim3(nd), dim3(64), 0, s, A, Q.sc_ptr[step]);
   }
-  const int64_t ntp = (int64_t)Q.top_pos.size(), ncoef = (int64_t)P.coef_p.size();
-  if (ntp > 0) hipLaunchKernelGGL(fac_top_lx_kernel, dim3(grid1(ntp, 256)), dim3(256), 0, s, A, ntp);
+  const int64_t ncoef = (int64_t)P.coef_p.size();
+  if (ntop > 0) hipLaunchKernelGGL(fac_top_lx_kernel, dim3(ntop), dim3(64), 0, s, A, ntop);
   if (ncoef > 0) hipLaunchKernelGGL(fac_coef_kernel, dim3(grid1(ncoef, 256)), dim3(256), 0, s, A, ncoef);
   const int64_t nmax = std::max<int64_t>({(int64_t)N, (int64_t)ntop, Q.bottom_records});
   hipLaunchKernelGGL(fac_isd_kernel, dim3(grid1(nmax, 256)), dim3(256), 0, s, A, N, ntop, Q.bottom_records);

@@ -80,82 +80,96 @@ Status build_numeric_plan(const Ingested& ing, const Symbolic& S, const FactorPl
       }
     }
   }
-  // 3. chain levels, deepest first
-  const int32_t nch = (int32_t)P.chains.size();
-  std::vector<std::vector<int32_t>> lev(P.nchain_levels);
-  for (int32_t c = 0; c < nch; ++c) lev[P.chains[c].level].push_back(c);
+  // 3. pieces of the top chains and the tree they form
+  std::vector<int32_t> piece_of(N, -1);
+  for (int32_t c = 0; c < (int32_t)P.chains.size(); ++c) {
+    const Chain& C = P.chains[c];
+    for (int32_t a = C.a; a <= C.b; a += kFacPiece) {
+      FacPiece f{};
+      f.a = a;
+      f.b = std::min(C.b, a + kFacPiece - 1);
+      f.w = f.b - f.a + 1;
+      f.dp = S.depth[f.b] - 1;
+      f.col_base = C.store_base + (int64_t)(a - C.a) * C.ld;
+      f.ld = C.ld;
+      f.u_begin = (int64_t)Q.pu_depth.size();
+      for (int64_t p = S.colptr[f.b]; p < S.colptr[f.b + 1]; ++p) {
+        const int32_t u = S.rowidx[p];
+        if (P.top_index[u] < 0) { set_error("numeric plan: a row above a top chain is not a top node"); return E_INTERNAL; }
+        Q.pu_depth.push_back(S.depth[u]);
+        Q.pu_top.push_back(P.top_index[u]);
+      }
+      f.nU = (int32_t)((int64_t)Q.pu_depth.size() - f.u_begin);
+      f.ldu = (int64_t)((std::max(f.nU, 1) + 63) / 64) * 64;
+      for (int32_t v = f.a; v <= f.b; ++v) piece_of[v] = (int32_t)Q.pieces.size();
+      Q.pieces.push_back(f);
+    }
+  }
+  const int32_t np = (int32_t)Q.pieces.size();
+  // levels: parents first (a piece's parent holds parent(b), a larger index)
+  int32_t nlev = 0;
+  for (int32_t x = np - 1; x >= 0; --x) {
+    FacPiece& f = Q.pieces[x];
+    const int32_t pb = S.parent[f.b];
+    f.level = pb < 0 ? 0 : Q.pieces[piece_of[pb]].level + 1;
+    nlev = std::max(nlev, f.level + 1);
+  }
+  std::vector<std::vector<int32_t>> lev(nlev);
+  for (int32_t x = 0; x < np; ++x) lev[Q.pieces[x].level].push_back(x);
   Q.lev_ptr.assign(1, 0);
   Q.ur_ptr.assign(1, 0);
   Q.gemm_ptr.assign(1, 0);
   Q.sc_ptr.assign(1, 0);
   Q.sc_src_ptr.assign(1, 0);
-  Q.g_off.assign(nch, 0);
-  for (int32_t l = P.nchain_levels - 1; l >= 0; --l) {
-    int64_t goff = 0;
-    for (int32_t c : lev[l]) {
-      const Chain& C = P.chains[c];
-      Q.lev_chain.push_back(c);
-      if (C.nU == 0) continue;
-      for (int32_t e0 = 0; e0 < C.nU; e0 += 64) {
-        Q.ur_chain.push_back(c);
+  for (int32_t l = nlev - 1; l >= 0; --l) {
+    int64_t goff = 0, loff = 0;
+    std::vector<std::pair<int32_t, std::pair<int32_t, int32_t>>> dst;  // (top index, (piece, pos))
+    for (int32_t x : lev[l]) {
+      FacPiece& f = Q.pieces[x];
+      Q.lev_piece.push_back(x);
+      if (f.nU == 0) continue;
+      f.luc_off = loff;
+      loff += f.ldu * f.w;
+      f.g_off = goff;
+      goff += f.ldu * f.nU;
+      for (int32_t e0 = 0; e0 < f.nU; e0 += 64) {
+        Q.ur_piece.push_back(x);
         Q.ur_row0.push_back(e0);
       }
       GemmProb g{};
-      g.a_buf = BUF_LUC; g.a_off = C.luc_off; g.lda = C.ldb; g.aoff_begin = -1; g.gather = 0;
-      g.b_buf = BUF_BT; g.b_off = C.bt_off; g.ldb = C.ldb; g.trans = 1;  // (k, j) at k * ldb + j
-      g.c_buf = BUF_G; g.c_off = goff; g.ldc = C.ldb;
-      g.M = C.nU; g.N = C.nU; g.K = C.w; g.alpha = 1.0;
+      g.a_buf = BUF_LUC; g.a_off = f.luc_off; g.lda = f.ldu; g.aoff_begin = -1; g.gather = 0;
+      g.b_buf = BUF_BT; g.b_off = f.luc_off; g.ldb = f.ldu; g.trans = 1;  // (k, j) at k * ldb + j
+      g.c_buf = BUF_G; g.c_off = f.g_off; g.ldc = f.ldu;
+      g.M = f.nU; g.N = f.nU; g.K = f.w; g.alpha = 1.0;
       const int32_t pid = (int32_t)Q.probs.size();
       Q.probs.push_back(g);
-      for (int32_t r0 = 0; r0 < C.nU; r0 += kTileM)
-        for (int32_t c0 = 0; c0 < C.nU; c0 += kTileN)
-          if (r0 + kTileM - 1 > c0) Q.tasks.push_back(GemmTask{pid, r0, c0, 0, C.w});  // below the diagonal
-      Q.g_off[c] = goff;
-      goff += C.ldb * C.nU;
+      for (int32_t r0 = 0; r0 < f.nU; r0 += kTileM)
+        for (int32_t c0 = 0; c0 < f.nU; c0 += kTileN)
+          if (r0 + kTileM - 1 > c0) Q.tasks.push_back(GemmTask{pid, r0, c0, 0, f.w});  // below the diagonal
+      for (int32_t e = 0; e < f.nU; ++e) dst.push_back({Q.pu_top[f.u_begin + e], {x, e}});
     }
+    Q.luc_elems = std::max(Q.luc_elems, loff);
     Q.g_elems = std::max(Q.g_elems, goff);
-    Q.lev_ptr.push_back((int32_t)Q.lev_chain.size());
-    Q.ur_ptr.push_back((int32_t)Q.ur_chain.size());
+    Q.lev_ptr.push_back((int32_t)Q.lev_piece.size());
+    Q.ur_ptr.push_back((int32_t)Q.ur_piece.size());
     Q.gemm_ptr.push_back((int64_t)Q.tasks.size());
-  }
-  Q.steps = P.nchain_levels;
-  // scatter lists per step: U_C's nodes are known by their store offsets in
-  // the gather table, mapped back to top indices here
-  {
-    std::vector<std::pair<int64_t, int32_t>> off2t(P.ntop);
-    for (int32_t t = 0; t < P.ntop; ++t) off2t[t] = {P.top_off[t], t};
-    std::sort(off2t.begin(), off2t.end());
-    auto top_of_off = [&](int64_t off) -> int32_t {
-      auto it = std::lower_bound(off2t.begin(), off2t.end(), std::make_pair(off, (int32_t)-1));
-      return (it != off2t.end() && it->first == off) ? it->second : -1;
-    };
-    for (int32_t step = 0; step < Q.steps; ++step) {
-      std::vector<std::pair<int32_t, std::pair<int32_t, int32_t>>> dst;  // (top index, (chain, pos))
-      for (int32_t x = Q.lev_ptr[step]; x < Q.lev_ptr[step + 1]; ++x) {
-        const int32_t c = Q.lev_chain[x];
-        const Chain& C = P.chains[c];
-        for (int32_t e = 0; e < C.nU; ++e) {
-          const int32_t t = top_of_off(P.u_off[C.u_begin + e]);
-          if (t < 0) { set_error("numeric plan: a U column is not a top column"); return E_INTERNAL; }
-          dst.push_back({t, {c, e}});
-        }
+    std::stable_sort(dst.begin(), dst.end(), [](const auto& x, const auto& y) {
+      return x.first != y.first ? x.first < y.first : x.second.first < y.second.first;
+    });
+    for (size_t i = 0; i < dst.size(); ++i) {
+      if (i == 0 || dst[i].first != dst[i - 1].first) {
+        if (i) Q.sc_src_ptr.push_back((int32_t)Q.sc_piece.size());
+        Q.sc_dest.push_back(dst[i].first);
       }
-      std::stable_sort(dst.begin(), dst.end(), [](const auto& x, const auto& y) {
-        return x.first != y.first ? x.first < y.first : x.second.first < y.second.first;
-      });
-      for (size_t i = 0; i < dst.size(); ++i) {
-        if (i == 0 || dst[i].first != dst[i - 1].first) {
-          if (i) Q.sc_src_ptr.push_back((int32_t)Q.sc_chain.size());
-          Q.sc_dest.push_back(dst[i].first);
-        }
-        Q.sc_chain.push_back(dst[i].second.first);
-        Q.sc_pos.push_back(dst[i].second.second);
-      }
-      if (!dst.empty()) Q.sc_src_ptr.push_back((int32_t)Q.sc_chain.size());
-      Q.sc_ptr.push_back((int32_t)Q.sc_dest.size());
+      Q.sc_piece.push_back(dst[i].second.first);
+      Q.sc_pos.push_back(dst[i].second.second);
     }
+    if (!dst.empty()) Q.sc_src_ptr.push_back((int32_t)Q.sc_piece.size());
+    Q.sc_ptr.push_back((int32_t)Q.sc_dest.size());
   }
-  // 4. top columns' factor values come from L_CC (lcc) or L_{U,C} (luc)
+  Q.steps = nlev;
+  // 4. top columns' factor values go to L_CC (lcc) or L_{U,C} (luc)
+  Q.top_x_ptr.assign(1, 0);
   for (int32_t t = 0; t < P.ntop; ++t) {
     const int32_t j = P.top_node[t];
     const Chain& C = P.chains[P.top_chain[t]];
@@ -163,7 +177,6 @@ Status build_numeric_plan(const Ingested& ing, const Symbolic& S, const FactorPl
     int64_t e = 0;
     for (int64_t p = S.colptr[j]; p < S.colptr[j + 1]; ++p) {
       const int32_t i = S.rowidx[p];
-      Q.top_pos.push_back(p);
       if (i <= C.b) {
         Q.top_src.push_back(C.lcc_off + (int64_t)jj * C.ldl + (i - C.a));
       } else {
@@ -175,6 +188,7 @@ Status build_numeric_plan(const Ingested& ing, const Symbolic& S, const FactorPl
         Q.top_src.push_back(kLxFromLuc | (C.luc_off + (int64_t)jj * C.ldb + e));
       }
     }
+    Q.top_x_ptr.push_back((int64_t)Q.top_src.size());
   }
   Q.bnode_node = P.bnode_node;
   Q.bottom_records = (int64_t)P.bnode_node.size();

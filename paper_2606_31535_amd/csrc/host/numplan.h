@@ -21,13 +21,19 @@
 //     Schur complement entry of its ancestor at depth d+1 in element d. Each
 //     top column pulls the contributions of the bottom columns that reach it,
 //     in a fixed order.
-//  3. Per chain level: each chain's diagonal block is factored in one
-//     workgroup (its pivots need only the block and the running sums of the
-//     rows above it, carried like r); the rows of U_C (the chain's outside
-//     ancestors) are then solved (L_{U,C}) one row per thread; the products
-//     L_{U,C} D_C L_{U,C}^T are dense GEMMs on the matrix cores; and each
-//     destination column subtracts its share of them, and adds its r, in a
-//     fixed order of source chains.
+//  3. The top chains are cut into pieces of at most kFacPiece consecutive
+//     columns; a piece P = a..b has the outside rows U_P = struct(b) (the
+//     pattern of its last column holds every row above the piece that any of
+//     its columns reaches). Per level of the tree of pieces, deepest first:
+//     each piece's diagonal block is factored in one workgroup (its pivots
+//     need only the block and the running sums of the rows above it, carried
+//     like r); the rows of U_P are solved one row per thread (L_{U,P}); the
+//     products L_{U,P} D_P L_{U,P}^T are dense GEMMs on the matrix cores; and
+//     each destination column subtracts its share of them, and adds its r, in
+//     a fixed order of source pieces.
+//  4. The factor values of the top columns are read back from the fronts,
+//     and the sweep layout (L_CC and L_{U,C} blocks, bottom records,
+//     D^{-1/2}) is filled from the factor.
 #pragma once
 
 #include <cstdint>
@@ -37,6 +43,18 @@
 #include "plan.h"
 
 namespace peers {
+
+constexpr int32_t kFacPiece = 64;  // columns per piece of a top chain
+
+// A piece a..b of a top chain (parent(i) = i+1 inside it).
+struct FacPiece {
+  int32_t a, b, w, dp;    // dp = depth of parent(b): rows above the piece
+  int32_t nU, level;      // |U_P|, depth in the tree of pieces
+  int64_t col_base, ld;   // front of column a+t at col_base + t*ld (the top store)
+  int64_t u_begin;        // into pu_depth / pu_top
+  int64_t luc_off, ldu;   // L_{U,P} in its step's scratch, column-major, ld = ldu = roundup64(nU)
+  int64_t g_off;          // its product in the step's product buffer (column-major, ld = ldu)
+};
 
 struct NumericPlan {
   int32_t N = 0;
@@ -54,24 +72,27 @@ struct NumericPlan {
   std::vector<int32_t> tg_ptr;
   std::vector<int32_t> tg_k;
   std::vector<int64_t> tg_p;
-  // 3. chain levels, deepest first
-  std::vector<int32_t> lev_ptr;   // per step: chains in lev_chain
-  std::vector<int32_t> lev_chain;
-  std::vector<int32_t> ur_ptr;    // per step: U-row tiles in ur_chain / ur_row0
-  std::vector<int32_t> ur_chain, ur_row0;
-  std::vector<GemmProb> probs;    // L_{U,C} D_C L_{U,C}^T of every chain (lower-triangle tiles)
+  // 3. pieces of the top chains, by level of the piece tree, deepest first
+  std::vector<FacPiece> pieces;
+  std::vector<int32_t> pu_depth;  // per piece, U_P ascending (depth descending): depths
+  std::vector<int32_t> pu_top;    // ... and top indices
+  std::vector<int32_t> lev_ptr;   // per step: pieces in lev_piece
+  std::vector<int32_t> lev_piece;
+  std::vector<int32_t> ur_ptr;    // per step: U-row tiles in ur_piece / ur_row0
+  std::vector<int32_t> ur_piece, ur_row0;
+  std::vector<GemmProb> probs;    // L_{U,P} D_P L_{U,P}^T of every piece (tiles below the diagonal)
   std::vector<GemmTask> tasks;
   std::vector<int64_t> gemm_ptr;  // per step: its tiles in tasks
-  std::vector<int64_t> g_off;     // per chain: offset of its product in the step's product buffer
+  int64_t luc_elems = 0;          // largest step's L_{U,P} scratch (and its D-scaled copy)
   int64_t g_elems = 0;            // largest step's product buffer
   std::vector<int32_t> sc_ptr;    // per step: destination top indices in sc_dest
   std::vector<int32_t> sc_dest;
-  std::vector<int32_t> sc_src_ptr;  // per destination: its (chain, position in U_C) sources
-  std::vector<int32_t> sc_chain, sc_pos;
+  std::vector<int32_t> sc_src_ptr;  // per destination: its (piece, position in U_P) sources
+  std::vector<int32_t> sc_piece, sc_pos;
   int32_t steps = 0;
   // 4. outputs into the sweep layout
+  std::vector<int64_t> top_x_ptr;   // per top index: its factor positions' entries in top_src
   std::vector<int64_t> top_src;     // per top-column factor position: lcc index, or luc index | kLxFromLuc
-  std::vector<int64_t> top_pos;     // those factor positions
   std::vector<int32_t> bnode_node;  // per bottom record: its node (for D^{-1/2})
   int64_t bottom_records = 0;
 };
