@@ -486,6 +486,36 @@ def bench_plain(args, g, desc, cpu=None) -> dict:
                   "what": "Algorithm 1 on the all-edge resistances in device memory (synchronous call)"}
     del wd, cd, nd
 
+    # Algorithm 8 step 1 on the device: a second handle of the same graph
+    # whose factor is formed by its upload; HIP-event time of the
+    # factorization, its factor against the host one, and its resistances
+    hd = P.peers_graph_create(g.n, g.eu, g.ev, g.w, g.ground, coords=g.coords, numeric_on_device=True)
+    t0 = time.time()
+    fd = P.peers_factor_upload(dev, hd, stream)
+    torch.cuda.synchronize()
+    t_upload_d = time.time() - t0
+    std = P.peers_graph_stats_get(hd)
+    Ld, Dd = P.peers_graph_export_factor(hd)
+    Lh, Dh = P.peers_graph_export_factor(h)
+    Rd = torch.empty(g.m, dtype=torch.float64, device="cuda")
+    P.peers_query_all_edges(fd, Rd, stream=stream)
+    Rdh = Rd.cpu().numpy()
+    nzR = Rh > 0
+    device_factor = {
+        "t_numeric_ms": round(std["t_numeric"] * 1e3, 3), "host_t_numeric_s": round(st["t_numeric"], 3),
+        "speedup_vs_host_numeric": round(st["t_numeric"] / std["t_numeric"], 1),
+        "upload_with_factorization_s": round(t_upload_d, 3),
+        "max_rel_diff_L_vs_host": float(np.max(np.abs(Ld - Lh) / np.maximum(np.abs(Lh), 1e-300))) if len(Lh) else 0.0,
+        "max_rel_diff_D_vs_host": float(np.max(np.abs(Dd - Dh) / Dh)),
+        "max_rel_diff_R_vs_host_factor": float(np.max(np.abs(Rdh[nzR] - Rh[nzR]) / Rh[nzR])),
+        "what": "cancellation-free L D L^T on the device (bottom subtrees per wavefront, chain pieces of <= 64 "
+                "columns per level, L_U D L_U^T on the matrix cores); HIP-event time on the upload stream"}
+    if "oracle_sample_edges" in acc:
+        device_factor["max_rel_err_oracle_sample"] = float(np.max(np.abs(Rdh[gold_e] - gold_R) / gold_R))
+    del Ld, Lh, Rd
+    P.peers_factor_release(fd)
+    P.peers_graph_destroy(hd)
+
     out = {
         "metric": METRIC, "value": round(g.m / dt, 1), "unit": "resistances/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 4),
@@ -509,6 +539,7 @@ def bench_plain(args, g, desc, cpu=None) -> dict:
         "hbm_bytes": {"resident": resident, "workspace": workspace},
         "node_to_ground": ground,
         "sparsifier": sparsifier,
+        "device_factor": device_factor,
     }
     if cpu is not None:
         cb, sel, Rs = cpu

@@ -270,7 +270,12 @@ peers_status peers_sparsify(peers_device d, int64_t m, const double* w, const do
  *   R_out[i]: host, or device with PEERS_OUT_DEVICE.
  * The first call for a set of factors and outputs times the candidate
  * schedules of the bottom step (subtree work items to workgroups) and keeps
- * the fastest; all-edge batches keep their captured graph and replay it on
+ * the fastest, remembered per device under a signature of the batch's
+ * structure (factor sizes, tree height, top-tree shape and GEMM tiles per
+ * chain level, bottom work items, query entries; for pair batches the
+ * counts that depend on the pairs to within a factor of two), so batches of
+ * the same structure skip the timing;
+ * all-edge batches keep their captured graph and replay it on
  * later calls with the same factors and outputs (released factors and grown
  * workspaces drop it). Blocks until done unless every entry is all-edge with
  * device output and PEERS_SYNC is not set.
@@ -291,6 +296,8 @@ typedef struct {
   char schedule_name[96];
   int32_t graph_reused;      /* 1 if the call replayed a cached graph */
   double last_ms;            /* graph execution time of the call (0 if not synchronized) */
+  int32_t schedule_cached;   /* 1 if the schedule came from the signature memo (no timing) */
+  uint64_t signature;        /* structure signature the schedule is remembered under */
 } peers_batch_info;
 peers_status peers_batch_last_info(peers_device d, peers_batch_info* out);
 

@@ -66,7 +66,8 @@ class peers_sweep_timings(C.Structure):
 class peers_batch_info(C.Structure):
     _fields_ = [("factors", C.c_int32), ("stages", C.c_int32), ("bottom_items", C.c_int64),
                 ("schedule", C.c_int32), ("candidates", C.c_int32), ("candidate_ms", C.c_double * 8),
-                ("schedule_name", C.c_char * 96), ("graph_reused", C.c_int32), ("last_ms", C.c_double)]
+                ("schedule_name", C.c_char * 96), ("graph_reused", C.c_int32), ("last_ms", C.c_double),
+                ("schedule_cached", C.c_int32), ("signature", C.c_uint64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

@@ -7,7 +7,11 @@
 // The bottom step's schedule (the order in which subtree work items are
 // handed to workgroups, and whether workgroups are one per item or a
 // persistent grid looping over items) is picked by timing the candidates on
-// the first call of a batch and kept with the captured graph.
+// the first call of a batch and kept with the captured graph. The choice is
+// also remembered under a signature of the batch's structure (per factor:
+// sizes, elimination-tree height, top-tree shape and the GEMM tiles of every
+// chain level, bottom work items and query entries), so a later batch of
+// other factors with the same structure skips the timing.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,6 +22,7 @@
 #include <mutex>
 #include <numeric>
 #include <string>
+#include <unordered_map>
 
 #include "../../../include/peers.h"
 #include "batch.h"
@@ -250,6 +255,8 @@ struct BatchExec {
   uint64_t bytes = 0;
   int schedule = -1;
   double cand_ms[kBatchSchedules] = {0, 0, 0, 0};
+  bool schedule_cached = false;  // taken from the signature memo, not timed
+  uint64_t signature = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   ~BatchExec() {
@@ -262,8 +269,14 @@ struct BatchExec {
   }
 };
 
+struct ScheduleMemo {
+  int schedule = 0;
+  double cand_ms[kBatchSchedules] = {0, 0, 0, 0};
+};
+
 struct BatchCache {
   std::list<std::unique_ptr<BatchExec>> execs;  // most recent first
+  std::unordered_map<uint64_t, ScheduleMemo> schedules;  // by batch signature
   peers_batch_info last{};
 };
 
@@ -311,6 +324,39 @@ Status build_exec(DeviceHandle& D, std::vector<Entry>& E, BatchExec& X, hipStrea
     if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize(batch upload)");
   }
   return st;
+}
+
+// Structure signature of a batch (splitmix64 over the fields, in order).
+uint64_t batch_signature(const std::vector<Entry>& E, bool all_edges) {
+  uint64_t h = 0x6a09e667f3bcc909ull;
+  auto mix = [&](uint64_t x) {
+    uint64_t z = (h ^ x) + 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    h = z ^ (z >> 31);
+  };
+  mix(E.size());
+  mix(all_edges ? 1 : 0);
+  for (const Entry& e : E) {
+    const FactorPlan& P = *e.F->plan;
+    const DeviceQueryPlan& Q = *e.plan;
+    mix((uint64_t)e.F->n);
+    mix((uint64_t)e.F->m);
+    mix((uint64_t)P.height);
+    mix((uint64_t)P.ntop);
+    mix(P.chains.size());
+    mix(P.btask_nwin.size());
+    mix(P.bnode_node.size());
+    mix(P.t2_ptr.size());
+    for (size_t l = 0; l + 1 < P.t2_ptr.size(); ++l) mix((uint64_t)(P.t2_ptr[l + 1] - P.t2_ptr[l]));
+    for (size_t l = 0; l + 1 < P.t2n_ptr.size(); ++l) mix((uint64_t)(P.t2n_ptr[l + 1] - P.t2n_ptr[l]));
+    // pair batches: the query-dependent counts to within a factor of two
+    auto bucket = [&](uint64_t x) { return all_edges ? x : (uint64_t)(64 - __builtin_clzll(x | 1)); };
+    mix(bucket(Q.work_task.size()));
+    mix(bucket((uint64_t)Q.args.nbq));
+    mix(bucket((uint64_t)e.q));
+  }
+  return h;
 }
 
 // Times each bottom schedule (after one pass of the top steps, which the
@@ -478,8 +524,24 @@ peers_status peers_batch_query(peers_device d, int32_t nb, const peers_factor* f
   if (st == OK && !X) {
     owned.reset(new BatchExec());
     owned->key = key;
+    owned->signature = batch_signature(E, all_edges);
     st = build_exec(*D, E, *owned, s);
-    if (st == OK) st = autotune(*owned, s);
+    if (st == OK) {
+      auto it = C.schedules.find(owned->signature);
+      if (it != C.schedules.end() && owned->L.bottom_stage >= 0) {
+        owned->schedule = it->second.schedule;
+        std::copy(it->second.cand_ms, it->second.cand_ms + kBatchSchedules, owned->cand_ms);
+        owned->schedule_cached = true;
+        owned->L.use_schedule(owned->schedule);
+      } else {
+        st = autotune(*owned, s);
+        if (st == OK && owned->L.bottom_stage >= 0) {
+          ScheduleMemo& m = C.schedules[owned->signature];
+          m.schedule = owned->schedule;
+          std::copy(owned->cand_ms, owned->cand_ms + kBatchSchedules, m.cand_ms);
+        }
+      }
+    }
     if (st == OK) st = capture(*owned);
     if (st == OK) X = owned.get();
   }
@@ -514,6 +576,8 @@ peers_status peers_batch_query(peers_device d, int32_t nb, const peers_factor* f
     for (int c = 0; c < kBatchSchedules; ++c) I.candidate_ms[c] = X->cand_ms[c];
     std::snprintf(I.schedule_name, sizeof(I.schedule_name), "%s", kBatchScheduleNames[std::max(0, X->schedule)]);
     I.graph_reused = reused ? 1 : 0;
+    I.schedule_cached = X->schedule_cached ? 1 : 0;
+    I.signature = X->signature;
     if (must_sync && hipEventElapsedTime(&total_ms, ev[0], ev[1]) == hipSuccess) I.last_ms = total_ms;
   }
   for (auto& e : ev)

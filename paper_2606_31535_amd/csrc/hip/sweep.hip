@@ -427,8 +427,10 @@ __global__ __launch_bounds__(256) void chain_rows_kernel(SweepArgs A) { chain_ro
 // One wavefront sweeps kWinPerWave consecutive windows of one subtree task:
 // lane l holds depth t*64 + l of window t for each of them. The per-node
 // records, address arithmetic and query reductions are shared by the windows.
-// Per-wave LDS blocks of the bottom sweep's query sums (33 KB per workgroup).
-constexpr int kQBlock = 16, kQRowPad = kWin + 1;
+// Per-wave LDS blocks of the bottom sweep's query sums (32 KB per workgroup).
+// Rows are not padded: the transposed reads of a flush conflict in the LDS
+// banks, which measured slightly cheaper than padded rows.
+constexpr int kQBlock = 16, kQRowPad = kWin;
 typedef double BottomLds[kBottomWaves][kQBlock][kQRowPad];
 
 template <bool WIDE>
@@ -500,8 +502,7 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
   int32_t jb = load_uniform(Q.bq_ptr + p0);
   // Per-lane values of the task's entries are summed over the lanes in
   // blocks of kQBlock entries through LDS: entry jb + c's 64 values go to row
-  // c of the wave's block (rows padded to 65 doubles so that the transposed
-  // reads below hit distinct banks); at the end of a block lane l adds up
+  // c of the wave's block; at the end of a block lane l adds up
   // the 16 values of row l/4 starting at 16 (l % 4), in a fixed tree, and
   // two butterflies inside each group of four lanes complete the row sums,
   // which are stored into the window-major partial slots.

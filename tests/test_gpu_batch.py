@@ -158,3 +158,39 @@ def test_batch_with_wide_store_factor(dev, batch):
     finally:
         P.peers_factor_release(f)
         P.peers_graph_destroy(h)
+
+
+def test_schedule_memo_by_structure(dev, batch):
+    # other factor handles of the same graphs (a fresh upload of each) have the
+    # batch's structure signature: the new batch takes the remembered schedule
+    # without timing, and still gives every factor's single-call bits
+    graphs, fs = batch
+    outs = [np.full(g.m, np.nan) for g in graphs]
+    P.peers_batch_query(dev, fs, [None] * len(fs), [None] * len(fs), outs)
+    first = P.peers_batch_last_info(dev)
+    hs, fs2 = [], []
+    try:
+        for g in graphs:
+            h = P.peers_graph_create(g.n, g.eu, g.ev, g.w, g.ground, coords=g.coords)
+            hs.append(h)
+            fs2.append(P.peers_factor_upload(dev, h))
+        outs2 = [np.full(g.m, np.nan) for g in graphs]
+        P.peers_batch_query(dev, fs2, [None] * len(fs2), [None] * len(fs2), outs2)
+        info = P.peers_batch_last_info(dev)
+        print("memo", first["signature"], info["signature"], info["schedule_name"])
+        assert info["graph_reused"] == 0 and info["schedule_cached"] == 1
+        assert info["signature"] == first["signature"] and info["schedule"] == first["schedule"]
+        for f, g, o in zip(fs2, graphs, outs2):
+            R = np.full(g.m, np.nan)
+            P.peers_query_all_edges(f, R)
+            assert np.array_equal(_bits(R), _bits(o))
+        # a batch of another structure is timed
+        outs3 = [np.full(g.m, np.nan) for g in graphs[:3]]
+        P.peers_batch_query(dev, fs2[:3], [None] * 3, [None] * 3, outs3)
+        info3 = P.peers_batch_last_info(dev)
+        assert info3["signature"] != first["signature"] and info3["schedule_cached"] == 0
+    finally:
+        for f in fs2:
+            P.peers_factor_release(f)
+        for h in hs:
+            P.peers_graph_destroy(h)
