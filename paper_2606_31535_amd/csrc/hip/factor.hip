@@ -36,6 +36,7 @@ struct FacArgs {
   double* D;
   double* r;     // conductance to the ground, accumulated per node
   double* rfin;  // r of each node when it is eliminated
+  double* e;     // per top index: r plus the magnitudes of the column's U-row entries
   // bottom
   const int32_t* bt_ptr;
   const int32_t* bcol;
@@ -154,13 +155,36 @@ __global__ __launch_bounds__(64) void fac_pull_kernel(FacArgs F, int32_t ntop) {
   if (lane == 0) F.r[j] += racc;
 }
 
+// e_t = r + the magnitudes of column t's entries in the rows of U_P, for
+// every column of this level's pieces: one wavefront per column (four
+// columns per workgroup, 16 workgroups per piece), the rows in four
+// interleaved lane-strided sums added in a fixed order.
+__global__ __launch_bounds__(256) void fac_esum_kernel(FacArgs F, int32_t lev0) {
+  const FacPiece Pc = F.pieces[F.lev_piece[lev0 + blockIdx.x / 16]];
+  const int lane = threadIdx.x & 63;
+  const int32_t t = (int32_t)(blockIdx.x % 16) * 4 + (int32_t)(threadIdx.x >> 6);
+  if (t >= Pc.w) return;
+  const double* col = F.T + Pc.col_base + (int64_t)t * Pc.ld;
+  const int32_t* pd = F.pu_depth + Pc.u_begin;
+  double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
+  int32_t e = lane;
+  for (; e + 192 < Pc.nU; e += 256) {
+    u0 -= col[pd[e] - 1];
+    u1 -= col[pd[e + 64] - 1];
+    u2 -= col[pd[e + 128] - 1];
+    u3 -= col[pd[e + 192] - 1];
+  }
+  for (; e < Pc.nU; e += 64) u0 -= col[pd[e] - 1];
+  const double u = wave_sum_all((u0 + u1) + (u2 + u3));
+  if (lane == 0) F.e[F.top_index[Pc.a] + t] = F.r[Pc.a + t] + u;
+}
+
 // Diagonal block of one piece a..b, in LDS. Column t (node a+t) is the front
 // at T + col_base + t*ld; row a+i (i > t) of it sits at depth index
-// dp + w - 1 - i, the rows of U_P at their depth - 1 (below dp). e_t starts as
-// r plus the magnitudes of column t's U-row entries; eliminating column t
-// adds (-L_{a+i,a+t}) e_t and (-L_{a+i,a+t}) r_t to e and r of the later
-// columns (the U rows' own updates are formed afterwards, row by row). The
-// L values go back into the fronts.
+// dp + w - 1 - i. e_t (from fac_esum_kernel) is r plus the magnitudes of
+// column t's U-row entries; eliminating column t adds (-L_{a+i,a+t}) e_t and
+// (-L_{a+i,a+t}) r_t to e and r of the later columns (the U rows' own updates
+// are formed afterwards, row by row). The L values go back into the fronts.
 constexpr int kDiagThreads = 256;
 __global__ __launch_bounds__(kDiagThreads) void fac_diag_kernel(FacArgs F, int32_t lev0) {
   __shared__ double blk[kFacPiece * kFacPiece];  // blk[t * 64 + i]: S_{a+i, a+t}, i > t
@@ -173,16 +197,9 @@ __global__ __launch_bounds__(kDiagThreads) void fac_diag_kernel(FacArgs F, int32
     const int32_t t = x >> 6, i = x & 63;
     if (i > t && i < w) blk[x] = col0[(int64_t)t * Pc.ld + dp + w - 1 - i];
   }
-  for (int32_t t = wave; t < w; t += kDiagThreads / 64) {
-    const double* col = col0 + (int64_t)t * Pc.ld;
-    double u = 0.0;
-    for (int32_t e = lane; e < Pc.nU; e += 64) u -= col[F.pu_depth[Pc.u_begin + e] - 1];
-    u = wave_sum_all(u);
-    if (lane == 0) {
-      const double r = F.r[Pc.a + t];
-      es[t] = r + u;
-      rs[t] = r;
-    }
+  if (tid < w) {
+    es[tid] = F.e[F.top_index[Pc.a] + tid];
+    rs[tid] = F.r[Pc.a + tid];
   }
   __syncthreads();
   for (int32_t t = 0; t < w; ++t) {
@@ -203,59 +220,55 @@ __global__ __launch_bounds__(kDiagThreads) void fac_diag_kernel(FacArgs F, int32
         rs[lane] = fma(-l, rt, rs[lane]);
       }
     }
-    // S_{a+i, a+t2} -= L_{a+i,a+t} D_t L_{a+t2,a+t} for t < t2 < i
+    // S_{a+i, a+t2} -= L_{a+i,a+t} D_t L_{a+t2,a+t} = L_{a+i,a+t} S_{a+t2,a+t}
+    // for t < t2 < i
     if (lane > t + 1 && lane < w) {
       const double li = bt[lane] / dv;
-      for (int32_t t2 = t + 1 + wave; t2 < lane; t2 += kDiagThreads / 64) {
-        const double sl = dv * (bt[t2] / dv);
-        blk[t2 * kFacPiece + lane] = fma(-li, sl, blk[t2 * kFacPiece + lane]);
-      }
+      for (int32_t t2 = t + 1 + wave; t2 < lane; t2 += kDiagThreads / 64)
+        blk[t2 * kFacPiece + lane] = fma(-li, bt[t2], blk[t2 * kFacPiece + lane]);
     }
     __syncthreads();
   }
 }
 
-// Rows of U_P: one thread per U node, left-looking over blocks of 16 piece
-// columns, L_{u,t} = (S_{u,t} - sum_{t' < t} L_{u,t'} D_{t'} L_{a+t,t'}) / D_t,
-// with L_{a+t,t'} read from the fronts. Writes L_{U,P} back into the fronts
-// and into the step's scratch (plain and D-scaled) for the product.
-constexpr int kUrowBlock = 16;
-__global__ __launch_bounds__(64) void fac_urows_kernel(FacArgs F, int32_t ur0) {
+// Rows of U_P: one thread per U node (kFacRowTile rows per workgroup). The
+// row's 64 entries S_{u,a+t} stay in registers and are finished in column
+// order: L_{u,t} = S_{u,t} / D_t, then S_{u,t2} -= L_{u,t} D_t L_{a+t2,t} for
+// the later columns (so each entry takes its terms in increasing t), with the
+// piece's L block and pivots staged in LDS. Writes L_{U,P} back into the
+// fronts and into the step's scratch (plain and D-scaled) for the product.
+__global__ __launch_bounds__(kFacRowTile) void fac_urows_kernel(FacArgs F, int32_t ur0) {
+  __shared__ double lpp[kFacPiece * kFacPiece];  // lpp[t * 64 + i] = L_{a+i, a+t}, i > t
+  __shared__ double dsh[kFacPiece];
   const FacPiece Pc = F.pieces[F.ur_piece[ur0 + blockIdx.x]];
+  double* col0 = F.T + Pc.col_base;
+  const int32_t w = Pc.w;
+  const int32_t dtop = Pc.dp + w - 1;  // depth index of row a
+  for (int32_t x = threadIdx.x; x < w * kFacPiece; x += kFacRowTile) {
+    const int32_t t = x >> 6, i = x & 63;
+    if (i > t && i < w) lpp[x] = col0[(int64_t)t * Pc.ld + dtop - i];
+  }
+  if ((int32_t)threadIdx.x < w) dsh[threadIdx.x] = F.D[Pc.a + threadIdx.x];
+  __syncthreads();
   const int32_t e = F.ur_row0[ur0 + blockIdx.x] + threadIdx.x;
   if (e >= Pc.nU) return;
   const int32_t du = F.pu_depth[Pc.u_begin + e] - 1;
-  const int32_t dtop = Pc.dp + Pc.w - 1;  // depth index of row a
-  double* col0 = F.T + Pc.col_base;
   double* lu = F.lu + Pc.luc_off + e;
   double* ld = F.lud + Pc.luc_off + e;
-  for (int32_t t0 = 0; t0 < Pc.w; t0 += kUrowBlock) {
-    const int32_t nb = min(kUrowBlock, Pc.w - t0);
-    double x[kUrowBlock];
+  double x[kFacPiece];
 #pragma unroll
-    for (int i = 0; i < kUrowBlock; ++i) x[i] = i < nb ? col0[(int64_t)(t0 + i) * Pc.ld + du] : 0.0;
-    for (int32_t t = 0; t < t0; ++t) {
-      const double sl = ld[(int64_t)t * Pc.ldu];
-      const double* lct = col0 + (int64_t)t * Pc.ld + dtop - t0;  // row a+t0+i at lct[-i]
+  for (int t = 0; t < kFacPiece; ++t) x[t] = t < w ? col0[(int64_t)t * Pc.ld + du] : 0.0;
 #pragma unroll
-      for (int i = 0; i < kUrowBlock; ++i)
-        if (i < nb) x[i] = fma(-sl, lct[-i], x[i]);
-    }
+  for (int t = 0; t < kFacPiece; ++t) {
+    if (t < w) {
+      const double dv = dsh[t];
+      const double l = x[t] / dv;
+      const double sl = l * dv;
+      lu[(int64_t)t * Pc.ldu] = l;
+      ld[(int64_t)t * Pc.ldu] = sl;
+      col0[(int64_t)t * Pc.ld + du] = l;
 #pragma unroll
-    for (int i = 0; i < kUrowBlock; ++i) {
-      if (i < nb) {
-        const int32_t t = t0 + i;
-        const double dv = F.D[Pc.a + t];
-        const double l = x[i] / dv;
-        const double sl = l * dv;
-        lu[(int64_t)t * Pc.ldu] = l;
-        ld[(int64_t)t * Pc.ldu] = sl;
-        col0[(int64_t)t * Pc.ld + du] = l;
-        const double* lct = col0 + (int64_t)t * Pc.ld + dtop - t0;
-#pragma unroll
-        for (int i2 = 0; i2 < kUrowBlock; ++i2)
-          if (i2 > i && i2 < nb) x[i2] = fma(-sl, lct[-i2], x[i2]);
-      }
+      for (int t2 = t + 1; t2 < kFacPiece; ++t2) x[t2] = fma(-sl, lpp[t * kFacPiece + t2], x[t2]);
     }
   }
 }
@@ -356,7 +369,7 @@ Status device_factor(FactorHandle& Fh, const GraphHandle& G, const NumericPlan& 
   const Symbolic& S = G.sym;
   const int32_t N = S.N;
   // device memory of the factorization, budgeted while it lives
-  const uint64_t est = (uint64_t)Q.nnz * 12 + (uint64_t)N * 40 + Q.bpair.size() * 8 + Q.tg_k.size() * 12 +
+  const uint64_t est = (uint64_t)Q.nnz * 12 + (uint64_t)N * 40 + (uint64_t)P.ntop * 8 + Q.bpair.size() * 8 + Q.tg_k.size() * 12 +
                        (uint64_t)(2 * std::max<int64_t>(Q.luc_elems, 1) + std::max<int64_t>(Q.g_elems, 1)) * 8 +
                        Q.pieces.size() * sizeof(FacPiece) + Q.pu_depth.size() * 8 + Q.top_src.size() * 8 +
                        P.coef_p.size() * 16 + (uint64_t)(1 << 24);
@@ -372,6 +385,7 @@ Status device_factor(FactorHandle& Fh, const GraphHandle& G, const NumericPlan& 
   A.D = B.alloc<double>(N);
   A.r = B.put(Q.r0, s);
   A.rfin = B.alloc<double>(N);
+  A.e = B.alloc<double>((size_t)std::max<int32_t>(P.ntop, 1));
   A.bt_ptr = B.put(Q.bt_ptr, s);
   A.bcol = B.put(Q.bcol, s);
   A.bpair_ptr = B.put(Q.bpair_ptr, s);
@@ -435,9 +449,12 @@ Status device_factor(FactorHandle& Fh, const GraphHandle& G, const NumericPlan& 
   if (ntop > 0) hipLaunchKernelGGL(fac_pull_kernel, dim3(ntop), dim3(64), 0, s, A, ntop);
   for (int32_t step = 0; step < Q.steps; ++step) {
     const int32_t nc = Q.lev_ptr[step + 1] - Q.lev_ptr[step];
-    if (nc > 0) hipLaunchKernelGGL(fac_diag_kernel, dim3(nc), dim3(kDiagThreads), 0, s, A, Q.lev_ptr[step]);
+    if (nc > 0) {
+      hipLaunchKernelGGL(fac_esum_kernel, dim3(nc * 16), dim3(256), 0, s, A, Q.lev_ptr[step]);
+      hipLaunchKernelGGL(fac_diag_kernel, dim3(nc), dim3(kDiagThreads), 0, s, A, Q.lev_ptr[step]);
+    }
     const int32_t nu = Q.ur_ptr[step + 1] - Q.ur_ptr[step];
-    if (nu > 0) hipLaunchKernelGGL(fac_urows_kernel, dim3(nu), dim3(64), 0, s, A, Q.ur_ptr[step]);
+    if (nu > 0) hipLaunchKernelGGL(fac_urows_kernel, dim3(nu), dim3(kFacRowTile), 0, s, A, Q.ur_ptr[step]);
     e = launch_gemm(GA, Q.gemm_ptr[step], Q.gemm_ptr[step + 1] - Q.gemm_ptr[step], s);
     if (e != hipSuccess) return finish(hip_fail(e, "device factorization products"));
     const int32_t nd = Q.sc_ptr[step + 1] - Q.sc_ptr[step];

@@ -132,7 +132,7 @@ Status build_numeric_plan(const Ingested& ing, const Symbolic& S, const FactorPl
       loff += f.ldu * f.w;
       f.g_off = goff;
       goff += f.ldu * f.nU;
-      for (int32_t e0 = 0; e0 < f.nU; e0 += 64) {
+      for (int32_t e0 = 0; e0 < f.nU; e0 += kFacRowTile) {
         Q.ur_piece.push_back(x);
         Q.ur_row0.push_back(e0);
       }

@@ -44,7 +44,8 @@
 
 namespace peers {
 
-constexpr int32_t kFacPiece = 64;  // columns per piece of a top chain
+constexpr int32_t kFacPiece = 64;     // columns per piece of a top chain
+constexpr int32_t kFacRowTile = 256;  // rows of U_P per U-row workgroup
 
 // A piece a..b of a top chain (parent(i) = i+1 inside it).
 struct FacPiece {
@@ -78,7 +79,7 @@ struct NumericPlan {
   std::vector<int32_t> pu_top;    // ... and top indices
   std::vector<int32_t> lev_ptr;   // per step: pieces in lev_piece
   std::vector<int32_t> lev_piece;
-  std::vector<int32_t> ur_ptr;    // per step: U-row tiles in ur_piece / ur_row0
+  std::vector<int32_t> ur_ptr;    // per step: U-row tiles (kFacRowTile rows) in ur_piece / ur_row0
   std::vector<int32_t> ur_piece, ur_row0;
   std::vector<GemmProb> probs;    // L_{U,P} D_P L_{U,P}^T of every piece (tiles below the diagonal)
   std::vector<GemmTask> tasks;

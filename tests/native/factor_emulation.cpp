@@ -231,10 +231,8 @@ int main(int argc, char** argv) {
         }
         for (int32_t i = t + 2; i < w; ++i) {
           const double li = blk[t * kFacPiece + i] / dv;
-          for (int32_t t2 = t + 1; t2 < i; ++t2) {
-            const double sl = dv * (blk[t * kFacPiece + t2] / dv);
-            blk[t2 * kFacPiece + i] = std::fma(-li, sl, blk[t2 * kFacPiece + i]);
-          }
+          for (int32_t t2 = t + 1; t2 < i; ++t2)
+            blk[t2 * kFacPiece + i] = std::fma(-li, blk[t * kFacPiece + t2], blk[t2 * kFacPiece + i]);
         }
       }
       // U_P: the rows of column b above the piece, depth descending
@@ -253,14 +251,13 @@ int main(int argc, char** argv) {
       const int32_t ta = P.top_index[Pc.a];
       REQUIRE(Pc.ldu >= Pc.nU && Pc.ldu % 64 == 0, "piece %d ldu", pi);
       lu.range(Pc.luc_off, Pc.luc_off + Pc.ldu * Pc.w);
-      for (int32_t e = Q.ur_row0[x]; e < std::min(Q.ur_row0[x] + 64, Pc.nU); ++e) {
+      for (int32_t e = Q.ur_row0[x]; e < std::min(Q.ur_row0[x] + kFacRowTile, Pc.nU); ++e) {
         const int32_t du = Q.pu_depth[Pc.u_begin + e] - 1;
         const int32_t dtop = Pc.dp + Pc.w - 1;
         REQUIRE(du < Pc.dp, "row %d of piece %d inside the piece", e, pi);
         std::vector<double> xv(Pc.w);
         for (int32_t t = 0; t < Pc.w; ++t) xv[t] = T(fidx(ta + t, du));
         for (int32_t t = 0; t < Pc.w; ++t) {
-          // the kernel subtracts earlier columns blockwise; the terms are the same
           const double dv = D(Pc.a + t), l = xv[t] / dv, sl = l * dv;
           lu(Pc.luc_off + (int64_t)t * Pc.ldu + e) = l;
           lud(Pc.luc_off + (int64_t)t * Pc.ldu + e) = sl;
