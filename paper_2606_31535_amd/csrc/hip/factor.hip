@@ -22,6 +22,7 @@
 #include "../host/numplan.h"
 #include "device_handle.h"
 #include "sweep_kernels.h"
+#include "wave_ops.h"
 
 namespace peers {
 
@@ -77,13 +78,6 @@ struct FacArgs {
   double* top_isd;
 };
 
-// Sum over the 64 lanes in a fixed order (butterfly), same value in every lane.
-__device__ __forceinline__ double wave_sum_all(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
-
 // Top columns' fronts: element depth(i) - 1 of top column j holds A_ij.
 __global__ __launch_bounds__(64) void fac_front_init_kernel(FacArgs F, int32_t ntop) {
   const int32_t t = blockIdx.x;
@@ -103,7 +97,7 @@ __global__ __launch_bounds__(64) void fac_bottom_kernel(FacArgs F) {
     const int64_t p0 = F.colptr[k], p1 = F.colptr[k + 1];
     double s = 0.0;
     for (int64_t p = p0 + lane; p < p1; p += 64) s -= F.Lx[p];
-    s = wave_sum_all(s);
+    s = wave_sum(s);
     const double rk = F.r[k];
     const double d = rk + s;
     if (lane == 0) {
@@ -175,59 +169,59 @@ __global__ __launch_bounds__(256) void fac_esum_kernel(FacArgs F, int32_t lev0) 
     u3 -= col[pd[e + 192] - 1];
   }
   for (; e < Pc.nU; e += 64) u0 -= col[pd[e] - 1];
-  const double u = wave_sum_all((u0 + u1) + (u2 + u3));
+  const double u = wave_sum((u0 + u1) + (u2 + u3));
   if (lane == 0) F.e[F.top_index[Pc.a] + t] = F.r[Pc.a + t] + u;
 }
 
-// Diagonal block of one piece a..b, in LDS. Column t (node a+t) is the front
-// at T + col_base + t*ld; row a+i (i > t) of it sits at depth index
+// Diagonal block of one piece a..b, one wavefront: lane i holds row i of
+// the block (x[t] = S_{a+i,a+t}) in registers. Column t (node a+t) is the
+// front at T + col_base + t*ld; row a+i (i > t) of it sits at depth index
 // dp + w - 1 - i. e_t (from fac_esum_kernel) is r plus the magnitudes of
-// column t's U-row entries; eliminating column t adds (-L_{a+i,a+t}) e_t and
-// (-L_{a+i,a+t}) r_t to e and r of the later columns (the U rows' own updates
-// are formed afterwards, row by row). The L values go back into the fronts.
-constexpr int kDiagThreads = 256;
-__global__ __launch_bounds__(kDiagThreads) void fac_diag_kernel(FacArgs F, int32_t lev0) {
-  __shared__ double blk[kFacPiece * kFacPiece];  // blk[t * 64 + i]: S_{a+i, a+t}, i > t
-  __shared__ double es[kFacPiece], rs[kFacPiece];
+// column t's U-row entries, so column t's pivot is e_t plus the magnitudes of
+// its entries below the diagonal (a wave sum). Eliminating column t adds
+// (-L_{a+i,a+t}) e_t and (-L_{a+i,a+t}) r_t to e and r of the later rows
+// (the U rows' own updates are formed afterwards, row by row) and subtracts
+// L_{a+i,a+t} S_{a+t2,a+t} from the entries (i, t2), t < t2, with column t
+// broadcast through LDS (entries at or above the diagonal are updated too;
+// they are never read). The L values go back into the fronts.
+__global__ __launch_bounds__(64) void fac_diag_kernel(FacArgs F, int32_t lev0) {
+  __shared__ double colS[kFacPiece];
   const FacPiece Pc = F.pieces[F.lev_piece[lev0 + blockIdx.x]];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lane = threadIdx.x;
   const int32_t w = Pc.w, dp = Pc.dp;
   double* col0 = F.T + Pc.col_base;
-  for (int32_t x = tid; x < w * kFacPiece; x += kDiagThreads) {
-    const int32_t t = x >> 6, i = x & 63;
-    if (i > t && i < w) blk[x] = col0[(int64_t)t * Pc.ld + dp + w - 1 - i];
+  double x[kFacPiece];
+#pragma unroll
+  for (int t = 0; t < kFacPiece; ++t) x[t] = (t < w && lane > t && lane < w) ? col0[(int64_t)t * Pc.ld + dp + w - 1 - lane] : 0.0;
+  double er = 0.0, rr = 0.0;
+  if (lane < w) {
+    er = F.e[F.top_index[Pc.a] + lane];
+    rr = F.r[Pc.a + lane];
   }
-  if (tid < w) {
-    es[tid] = F.e[F.top_index[Pc.a] + tid];
-    rs[tid] = F.r[Pc.a + tid];
-  }
-  __syncthreads();
-  for (int32_t t = 0; t < w; ++t) {
-    const double* bt = blk + t * kFacPiece;
-    // every wave forms the same pivot in the same order
-    const double s = wave_sum_all((lane > t && lane < w) ? -bt[lane] : 0.0);
-    const double et = es[t], rt = rs[t];
-    const double dv = et + s;
-    if (wave == 0) {
+  const bool live = lane < w;
+#pragma unroll
+  for (int t = 0; t < kFacPiece; ++t) {
+    if (t < w) {
+      const double et = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(er), t),
+                                         __builtin_amdgcn_readlane(__double2loint(er), t));
+      const double rt = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(rr), t),
+                                         __builtin_amdgcn_readlane(__double2loint(rr), t));
+      const bool below = live && lane > t;
+      const double dv = et + wave_sum(below ? -x[t] : 0.0);
+      const double l = below ? x[t] / dv : 0.0;
       if (lane == 0) {
         F.D[Pc.a + t] = dv;
         F.rfin[Pc.a + t] = rt;
       }
-      if (lane > t && lane < w) {
-        const double l = bt[lane] / dv;
-        col0[(int64_t)t * Pc.ld + dp + w - 1 - lane] = l;
-        es[lane] = fma(-l, et, es[lane]);
-        rs[lane] = fma(-l, rt, rs[lane]);
-      }
+      if (below) col0[(int64_t)t * Pc.ld + dp + w - 1 - lane] = l;
+      er = fma(-l, et, er);
+      rr = fma(-l, rt, rr);
+      colS[lane] = x[t];
+      __syncthreads();
+#pragma unroll
+      for (int t2 = t + 1; t2 < kFacPiece; ++t2) x[t2] = fma(-l, colS[t2], x[t2]);
+      __syncthreads();
     }
-    // S_{a+i, a+t2} -= L_{a+i,a+t} D_t L_{a+t2,a+t} = L_{a+i,a+t} S_{a+t2,a+t}
-    // for t < t2 < i
-    if (lane > t + 1 && lane < w) {
-      const double li = bt[lane] / dv;
-      for (int32_t t2 = t + 1 + wave; t2 < lane; t2 += kDiagThreads / 64)
-        blk[t2 * kFacPiece + lane] = fma(-li, bt[t2], blk[t2 * kFacPiece + lane]);
-    }
-    __syncthreads();
   }
 }
 
@@ -291,7 +285,7 @@ __global__ __launch_bounds__(64) void fac_scatter_kernel(FacArgs F, int32_t d0) 
     }
     double rsum = 0.0;
     for (int32_t k = lane; k < Pc.w; k += 64) rsum = fma(-F.lu[Pc.luc_off + (int64_t)k * Pc.ldu + e], F.rfin[Pc.a + k], rsum);
-    racc += wave_sum_all(rsum);
+    racc += wave_sum(rsum);
     __syncthreads();
   }
   if (lane == 0) F.r[F.top_node[t]] += racc;
@@ -451,7 +445,7 @@ Status device_factor(FactorHandle& Fh, const GraphHandle& G, const NumericPlan& 
     const int32_t nc = Q.lev_ptr[step + 1] - Q.lev_ptr[step];
     if (nc > 0) {
       hipLaunchKernelGGL(fac_esum_kernel, dim3(nc * 16), dim3(256), 0, s, A, Q.lev_ptr[step]);
-      hipLaunchKernelGGL(fac_diag_kernel, dim3(nc), dim3(kDiagThreads), 0, s, A, Q.lev_ptr[step]);
+      hipLaunchKernelGGL(fac_diag_kernel, dim3(nc), dim3(64), 0, s, A, Q.lev_ptr[step]);
     }
     const int32_t nu = Q.ur_ptr[step + 1] - Q.ur_ptr[step];
     if (nu > 0) hipLaunchKernelGGL(fac_urows_kernel, dim3(nu), dim3(kFacRowTile), 0, s, A, Q.ur_ptr[step]);
