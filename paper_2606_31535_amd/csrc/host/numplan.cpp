@@ -2,6 +2,7 @@
 #include "numplan.h"
 
 #include <algorithm>
+#include <atomic>
 
 namespace peers {
 
@@ -20,20 +21,26 @@ Status build_numeric_plan(const Ingested& ing, const Symbolic& S, const FactorPl
   Q.N = N;
   Q.nnz = S.colptr[N];
   Q.height = S.height;
-  // A at the factor's positions
+  const int threads = default_threads();
+  // A at the factor's positions (columns in parallel: each writes its own)
   Q.lx0.assign(Q.nnz, 0.0);
   Q.r0.assign(N, 0.0);
-  for (int32_t j = 0; j < N; ++j) {
-    const int32_t r = S.perm[j];
-    Q.r0[j] = ing.gnd[r];
-    for (int64_t p = ing.A.ptr[r]; p < ing.A.ptr[r + 1]; ++p) {
-      const int32_t i = S.iperm[ing.A.idx[p]];
-      if (i <= j) continue;
-      const int64_t pos = find_row(S, j, i);
-      if (pos < 0) { set_error("numeric plan: an entry of A outside the factor pattern"); return E_INTERNAL; }
-      Q.lx0[pos] += ing.A.val[p];
+  std::atomic<bool> outside{false};
+  parallel_for((N + 4095) / 4096, threads, [&](int64_t blk) {
+    const int32_t j1 = (int32_t)std::min<int64_t>(N, (blk + 1) * 4096);
+    for (int32_t j = (int32_t)(blk * 4096); j < j1; ++j) {
+      const int32_t r = S.perm[j];
+      Q.r0[j] = ing.gnd[r];
+      for (int64_t p = ing.A.ptr[r]; p < ing.A.ptr[r + 1]; ++p) {
+        const int32_t i = S.iperm[ing.A.idx[p]];
+        if (i <= j) continue;
+        const int64_t pos = find_row(S, j, i);
+        if (pos < 0) outside = true;
+        else Q.lx0[pos] += ing.A.val[p];
+      }
     }
-  }
+  });
+  if (outside) { set_error("numeric plan: an entry of A outside the factor pattern"); return E_INTERNAL; }
   // 1. bottom tasks, columns ascending, and their pair targets
   const int32_t nbt = (int32_t)P.btask_nwin.size();
   Q.bt_ptr.assign(1, 0);
@@ -168,28 +175,36 @@ Status build_numeric_plan(const Ingested& ing, const Symbolic& S, const FactorPl
     Q.sc_ptr.push_back((int32_t)Q.sc_dest.size());
   }
   Q.steps = nlev;
-  // 4. top columns' factor values go to L_CC (lcc) or L_{U,C} (luc)
-  Q.top_x_ptr.assign(1, 0);
+  // 4. top columns' factor values go to L_CC (lcc) or L_{U,C} (luc): rows
+  //    of the chain by their offset, rows above it by their position in U_C
+  //    (the pattern of the chain's last column, ascending)
+  Q.top_x_ptr.assign(P.ntop + 1, 0);
   for (int32_t t = 0; t < P.ntop; ++t) {
     const int32_t j = P.top_node[t];
-    const Chain& C = P.chains[P.top_chain[t]];
-    const int32_t jj = j - C.a;
-    int64_t e = 0;
-    for (int64_t p = S.colptr[j]; p < S.colptr[j + 1]; ++p) {
-      const int32_t i = S.rowidx[p];
-      if (i <= C.b) {
-        Q.top_src.push_back(C.lcc_off + (int64_t)jj * C.ldl + (i - C.a));
-      } else {
-        // position of i in U_C: U_C ascending; rows of column j above the
-        // chain are a subset of it in the same order
-        const int64_t off = P.top_off[P.top_index[i]];
-        while (e < C.nU && P.u_off[C.u_begin + e] != off) ++e;
-        if (e == C.nU) { set_error("numeric plan: a row above a chain is not in U_C"); return E_INTERNAL; }
-        Q.top_src.push_back(kLxFromLuc | (C.luc_off + (int64_t)jj * C.ldb + e));
+    Q.top_x_ptr[t + 1] = Q.top_x_ptr[t] + (S.colptr[j + 1] - S.colptr[j]);
+  }
+  Q.top_src.assign(Q.top_x_ptr[P.ntop], 0);
+  std::atomic<bool> bad{false};
+  parallel_for((int64_t)P.chains.size(), threads, [&](int64_t ci) {
+    const Chain& C = P.chains[ci];
+    const int32_t* U = S.rowidx.data() + S.colptr[C.b];
+    for (int32_t v = C.a; v <= C.b; ++v) {
+      const int32_t jj = v - C.a;
+      int64_t x = Q.top_x_ptr[P.top_index[v]];
+      int32_t e = 0;
+      for (int64_t p = S.colptr[v]; p < S.colptr[v + 1]; ++p, ++x) {
+        const int32_t i = S.rowidx[p];
+        if (i <= C.b) {
+          Q.top_src[x] = C.lcc_off + (int64_t)jj * C.ldl + (i - C.a);
+        } else {
+          while (e < C.nU && U[e] != i) ++e;  // both ascending
+          if (e == C.nU) { bad = true; return; }
+          Q.top_src[x] = kLxFromLuc | (C.luc_off + (int64_t)jj * C.ldb + e);
+        }
       }
     }
-    Q.top_x_ptr.push_back((int64_t)Q.top_src.size());
-  }
+  });
+  if (bad) { set_error("numeric plan: a row above a chain is not in U_C"); return E_INTERNAL; }
   Q.bnode_node = P.bnode_node;
   Q.bottom_records = (int64_t)P.bnode_node.size();
   return OK;

@@ -94,7 +94,11 @@ Status build_plan(const Symbolic& S, const Numeric* Fp, FactorPlan& P) {
         const int32_t r = S.rowidx[p];
         if (r > c.b && mark[r] != ci) { mark[r] = ci; U.push_back(r); }
       }
-    std::sort(U.begin(), U.end());
+    // the rows above the chain that any of its columns reaches are exactly
+    // the pattern of its last column (parent(v) = v + 1 inside the chain, and
+    // struct(v) minus parent(v) lies in struct(parent(v)))
+    if ((int64_t)U.size() != S.colptr[c.b + 1] - S.colptr[c.b]) { set_error("plan: inconsistent U"); return E_INTERNAL; }
+    U.assign(S.rowidx.begin() + S.colptr[c.b], S.rowidx.begin() + S.colptr[c.b + 1]);
     c.nU = (int32_t)U.size();
     c.u_begin = (int64_t)P.u_off.size();
     for (int32_t e = 0; e < c.nU; ++e) {
@@ -116,36 +120,19 @@ Status build_plan(const Symbolic& S, const Numeric* Fp, FactorPlan& P) {
     luc_elems += c.nU > 0 ? c.ldb * c.w : 0;
   }
   // gather table: store offset of every U_C column (needs all store bases)
-  {
-    std::vector<int32_t> Ulist;
-    for (int32_t ci = 0; ci < nch; ++ci) {
-      const Chain& c = P.chains[ci];
-      Ulist.clear();
-      for (int32_t v = c.a; v <= c.b; ++v)
-        for (int64_t p = S.colptr[v]; p < S.colptr[v + 1]; ++p) {
-          const int32_t r = S.rowidx[p];
-          if (r > c.b) Ulist.push_back(r);
-        }
-      std::sort(Ulist.begin(), Ulist.end());
-      Ulist.erase(std::unique(Ulist.begin(), Ulist.end()), Ulist.end());
-      if ((int32_t)Ulist.size() != c.nU) { set_error("plan: inconsistent U"); return E_INTERNAL; }
-      for (int32_t e = 0; e < c.nU; ++e) P.u_off[c.u_begin + e] = P.top_off[P.top_index[Ulist[e]]];
-    }
+  for (int32_t ci = 0; ci < nch; ++ci) {
+    const Chain& c = P.chains[ci];
+    const int32_t* U = S.rowidx.data() + S.colptr[c.b];
+    for (int32_t e = 0; e < c.nU; ++e) P.u_off[c.u_begin + e] = P.top_off[P.top_index[U[e]]];
   }
   // dense L_CC (unit diagonal stored) and L_{U,C}, column-major
   P.lcc.assign(lcc_elems, 0.0);
   P.luc.assign(luc_elems, 0.0);
   {
-    std::vector<int32_t> Ulist;
     for (int32_t ci = 0; ci < nch; ++ci) {
       const Chain& c = P.chains[ci];
-      Ulist.clear();
-      for (int32_t v = c.a; v <= c.b; ++v)
-        for (int64_t p = S.colptr[v]; p < S.colptr[v + 1]; ++p)
-          if (S.rowidx[p] > c.b) Ulist.push_back(S.rowidx[p]);
-      std::sort(Ulist.begin(), Ulist.end());
-      Ulist.erase(std::unique(Ulist.begin(), Ulist.end()), Ulist.end());
-      for (int32_t e = 0; e < c.nU; ++e) upos[Ulist[e]] = e;
+      const int32_t* U = S.rowidx.data() + S.colptr[c.b];
+      for (int32_t e = 0; e < c.nU; ++e) upos[U[e]] = e;
       for (int32_t j = 0; j < c.w; ++j) {
         const int32_t v = c.a + j;
         P.lcc[c.lcc_off + (int64_t)j * c.ldl + j] = 1.0;
