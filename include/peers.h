@@ -80,7 +80,9 @@ typedef struct {
                                  peers_factor_upload of the graph (bottom subtrees, then the
                                  top chains level by level with FP64 matrix-core products);
                                  until then peers_graph_export_factor returns UNSUPPORTED and
-                                 t_numeric is 0; afterwards t_numeric is the device time */
+                                 t_numeric is 0; afterwards t_numeric is the device time.
+                                 Uploads of such a graph from several threads run one at a
+                                 time; the first forms the factor, the others reuse it */
 } peers_graph_opts;
 
 typedef struct {

@@ -298,6 +298,10 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
   hipStream_t s = (hipStream_t)hip_stream;
   hipError_t he = hipSetDevice(D->ordinal);
   if (he != hipSuccess) return (peers_status)hip_fail(he, "hipSetDevice");
+  // the upload reads the graph's factor, and forms it first for a graph
+  // created with numeric_on_device: uploads of such a graph run one at a time
+  std::unique_lock<std::mutex> num_lock(G.num_mu, std::defer_lock);
+  if (G.numeric_on_device) num_lock.lock();
   std::unique_ptr<FactorHandle> F(new FactorHandle());
   F->dev = D;
   F->n = G.ing.n;

@@ -72,7 +72,9 @@ peers_status peers_graph_create(int64_t n, int64_t m, const int32_t* eu, const i
 
 peers_status peers_graph_stats_get(peers_graph g, peers_graph_stats* out) {
   if (!g || !out) { set_error("null argument"); return PEERS_E_INVALID_ARG; }
-  *out = reinterpret_cast<GraphHandle*>(g)->stats;
+  const GraphHandle& G = *reinterpret_cast<GraphHandle*>(g);
+  std::lock_guard<std::mutex> lk(G.num_mu);
+  *out = G.stats;
   return PEERS_OK;
 }
 
@@ -97,6 +99,7 @@ peers_status peers_graph_export_symbolic(peers_graph g, int32_t* perm, int32_t* 
 peers_status peers_graph_export_factor(peers_graph g, double* Lx, double* D) {
   if (!g) { set_error("null graph"); return PEERS_E_INVALID_ARG; }
   const GraphHandle& G = *reinterpret_cast<GraphHandle*>(g);
+  std::lock_guard<std::mutex> lk(G.num_mu);
   if (!G.numeric_ready) {
     set_error("the factor of this graph is formed on the device by its first peers_factor_upload");
     return PEERS_E_UNSUPPORTED;

@@ -194,6 +194,7 @@ peers_status peers_cpu_query(peers_graph g, int64_t q, const int32_t* qu, const 
                              double* R_out, peers_cpu_stats* stats) {
   if (!g || q < 0 || (q > 0 && (!qu || !qv || !R_out))) { set_error("null argument"); return PEERS_E_INVALID_ARG; }
   const GraphHandle& G = *reinterpret_cast<GraphHandle*>(g);
+  std::lock_guard<std::mutex> lk(G.num_mu);  // the factor stays as it is while it is read
   if (!G.numeric_ready) {
     set_error("the factor of this graph is formed on the device by its first peers_factor_upload");
     return PEERS_E_UNSUPPORTED;

@@ -2,6 +2,8 @@
 // statistics reported through the C ABI.
 #pragma once
 
+#include <mutex>
+
 #include "../../../include/peers.h"
 #include "host.h"
 
@@ -15,9 +17,11 @@ struct GraphHandle {
   std::vector<int32_t> eu, ev;  // the input edge list (all-edge queries in input order)
   bool store64 = false;         // peers_graph_opts::store_offsets_64
   // numeric factor formed on the device by the first upload (num is filled
-  // then, from the device's result)
+  // then, from the device's result); num_mu orders that upload against other
+  // uploads of the graph and against readers of num and stats
   bool numeric_on_device = false;
   bool numeric_ready = true;
+  mutable std::mutex num_mu;
 };
 
 Status build_graph(int64_t n, int64_t m, const int32_t* eu, const int32_t* ev, const double* w, int32_t ground,

@@ -132,3 +132,42 @@ def test_device_factor_full_size(dev, cfg, gen):
     finally:
         P.peers_factor_release(f)
         P.peers_graph_destroy(hd)
+
+
+def test_concurrent_uploads_of_one_device_factor_graph(dev):
+    # two threads upload the same numeric_on_device graph at once: the uploads
+    # run one at a time, the first forms the factor and the second reuses it;
+    # both factors give the same bits
+    import threading
+    g = synth.pdn_multilayer(side=40, layers=3, seed=5)
+    h = P.peers_graph_create(g.n, g.eu, g.ev, g.w, g.ground, coords=g.coords, numeric_on_device=True)
+    fs, errs = [None, None], []
+
+    def up(i):
+        try:
+            fs[i] = P.peers_factor_upload(dev, h)
+        except Exception as e:  # reported below
+            errs.append(e)
+
+    ts = [threading.Thread(target=up, args=(i,)) for i in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    try:
+        assert not errs, errs
+        Rs = []
+        for f in fs:
+            R = np.full(g.m, np.nan)
+            P.peers_query_all_edges(f, R)
+            Rs.append(R)
+        assert np.array_equal(Rs[0].view(np.int64), Rs[1].view(np.int64))
+        Ro = dense.resistances(g, g.eu, g.ev)
+        assert float(np.max(np.abs(Rs[0] - Ro) / Ro)) <= TOL
+        Lx, D = P.peers_graph_export_factor(h)
+        assert np.all(D > 0)
+    finally:
+        for f in fs:
+            if f is not None:
+                P.peers_factor_release(f)
+        P.peers_graph_destroy(h)
