@@ -324,7 +324,10 @@ __global__ __launch_bounds__(256) void fac_isd_kernel(FacArgs F, int32_t N, int3
 
 inline unsigned grid1(int64_t n, int64_t per) { return (unsigned)std::max<int64_t>(1, (n + per - 1) / per); }
 
+// Device buffers of the factorization. With `dry` set nothing is allocated:
+// the calls only add up the bytes (so the budget is reserved exactly first).
 struct DevBufs {
+  bool dry = false;
   std::vector<void*> ptrs;
   uint64_t bytes = 0;
   hipError_t err = hipSuccess;
@@ -332,6 +335,10 @@ struct DevBufs {
   T* put(const std::vector<T>& v, hipStream_t s) {
     void* p = nullptr;
     const size_t b = std::max<size_t>(v.size() * sizeof(T), 8);
+    if (dry) {
+      bytes += b;
+      return nullptr;
+    }
     if (err == hipSuccess) err = hipMalloc(&p, b);
     if (err != hipSuccess) return nullptr;
     ptrs.push_back(p);
@@ -343,6 +350,10 @@ struct DevBufs {
   T* alloc(size_t n) {
     void* p = nullptr;
     const size_t b = std::max<size_t>(n * sizeof(T), 8);
+    if (dry) {
+      bytes += b;
+      return nullptr;
+    }
     if (err == hipSuccess) err = hipMalloc(&p, b);
     if (err != hipSuccess) return nullptr;
     ptrs.push_back(p);
@@ -362,64 +373,74 @@ Status device_factor(FactorHandle& Fh, const GraphHandle& G, const NumericPlan& 
   const FactorPlan& P = *Fh.plan;
   const Symbolic& S = G.sym;
   const int32_t N = S.N;
-  // device memory of the factorization, budgeted while it lives
-  const uint64_t est = (uint64_t)Q.nnz * 12 + (uint64_t)N * 40 + (uint64_t)P.ntop * 8 + Q.bpair.size() * 8 + Q.tg_k.size() * 12 +
-                       (uint64_t)(2 * std::max<int64_t>(Q.luc_elems, 1) + std::max<int64_t>(Q.g_elems, 1)) * 8 +
-                       Q.pieces.size() * sizeof(FacPiece) + Q.pu_depth.size() * 8 + Q.top_src.size() * 8 +
-                       P.coef_p.size() * 16 + (uint64_t)(1 << 24);
+  // the factorization's buffers; a dry pass first adds up their bytes, which
+  // are reserved against the device budget while the factorization runs
+  auto setup = [&](DevBufs& B, FacArgs& A, GemmArgs& GA) {
+    A.colptr = B.put(S.colptr, s);
+    A.rowidx = B.put(S.rowidx, s);
+    A.depth = B.put(S.depth, s);
+    A.top_index = B.put(P.top_index, s);
+    A.Lx = B.put(Q.lx0, s);
+    A.D = B.alloc<double>(N);
+    A.r = B.put(Q.r0, s);
+    A.rfin = B.alloc<double>(N);
+    A.e = B.alloc<double>((size_t)std::max<int32_t>(P.ntop, 1));
+    A.bt_ptr = B.put(Q.bt_ptr, s);
+    A.bcol = B.put(Q.bcol, s);
+    A.bpair_ptr = B.put(Q.bpair_ptr, s);
+    A.bpair = B.put(Q.bpair, s);
+    A.tg_ptr = B.put(Q.tg_ptr, s);
+    A.tg_k = B.put(Q.tg_k, s);
+    A.tg_p = B.put(Q.tg_p, s);
+    A.top_node = Fh.sweep.top_node;
+    A.top_off = Fh.sweep.top_off;
+    A.T = (double*)Fh.store;
+    A.pieces = B.put(Q.pieces, s);
+    A.pu_depth = B.put(Q.pu_depth, s);
+    A.pu_top = B.put(Q.pu_top, s);
+    A.lu = B.alloc<double>((size_t)std::max<int64_t>(Q.luc_elems, 1));
+    A.lud = B.alloc<double>((size_t)std::max<int64_t>(Q.luc_elems, 1));
+    A.G = B.alloc<double>((size_t)std::max<int64_t>(Q.g_elems, 1));
+    A.lev_piece = B.put(Q.lev_piece, s);
+    A.ur_piece = B.put(Q.ur_piece, s);
+    A.ur_row0 = B.put(Q.ur_row0, s);
+    A.sc_dest = B.put(Q.sc_dest, s);
+    A.sc_src_ptr = B.put(Q.sc_src_ptr, s);
+    A.sc_piece = B.put(Q.sc_piece, s);
+    A.sc_pos = B.put(Q.sc_pos, s);
+    A.lcc = lcc_dev;
+    A.luc = luc_dev;
+    A.top_x_ptr = B.put(Q.top_x_ptr, s);
+    A.top_src = B.put(Q.top_src, s);
+    A.coef_p = B.put(P.coef_p, s);
+    A.coef_off = B.put(P.coef_off, s);
+    A.bnode_base = (char*)Fh.sweep.bnode;
+    A.bent_base = (char*)Fh.sweep.bent;
+    A.bnode_node = B.put(Q.bnode_node, s);
+    A.isd = const_cast<double*>(Fh.sweep.isd);
+    A.top_isd = const_cast<double*>(Fh.sweep.top_isd);
+    GA = Fh.gemm;
+    GA.probs = B.put(Q.probs, s);
+    GA.tasks = B.put(Q.tasks, s);
+    GA.buf[BUF_LUC] = A.lu;
+    GA.buf[BUF_BT] = A.lud;
+    GA.buf[BUF_G] = A.G;
+  };
+  uint64_t est = 0;
+  {
+    DevBufs dry;
+    dry.dry = true;
+    FacArgs A0{};
+    GemmArgs G0{};
+    setup(dry, A0, G0);
+    est = dry.bytes;
+  }
   Status st = Fh.dev->reserve(est);
   if (st != OK) return st;
   DevBufs B;
   FacArgs A{};
-  A.colptr = B.put(S.colptr, s);
-  A.rowidx = B.put(S.rowidx, s);
-  A.depth = B.put(S.depth, s);
-  A.top_index = B.put(P.top_index, s);
-  A.Lx = B.put(Q.lx0, s);
-  A.D = B.alloc<double>(N);
-  A.r = B.put(Q.r0, s);
-  A.rfin = B.alloc<double>(N);
-  A.e = B.alloc<double>((size_t)std::max<int32_t>(P.ntop, 1));
-  A.bt_ptr = B.put(Q.bt_ptr, s);
-  A.bcol = B.put(Q.bcol, s);
-  A.bpair_ptr = B.put(Q.bpair_ptr, s);
-  A.bpair = B.put(Q.bpair, s);
-  A.tg_ptr = B.put(Q.tg_ptr, s);
-  A.tg_k = B.put(Q.tg_k, s);
-  A.tg_p = B.put(Q.tg_p, s);
-  A.top_node = Fh.sweep.top_node;
-  A.top_off = Fh.sweep.top_off;
-  A.T = (double*)Fh.store;
-  A.pieces = B.put(Q.pieces, s);
-  A.pu_depth = B.put(Q.pu_depth, s);
-  A.pu_top = B.put(Q.pu_top, s);
-  A.lu = B.alloc<double>((size_t)std::max<int64_t>(Q.luc_elems, 1));
-  A.lud = B.alloc<double>((size_t)std::max<int64_t>(Q.luc_elems, 1));
-  A.G = B.alloc<double>((size_t)std::max<int64_t>(Q.g_elems, 1));
-  A.lev_piece = B.put(Q.lev_piece, s);
-  A.ur_piece = B.put(Q.ur_piece, s);
-  A.ur_row0 = B.put(Q.ur_row0, s);
-  A.sc_dest = B.put(Q.sc_dest, s);
-  A.sc_src_ptr = B.put(Q.sc_src_ptr, s);
-  A.sc_piece = B.put(Q.sc_piece, s);
-  A.sc_pos = B.put(Q.sc_pos, s);
-  A.lcc = lcc_dev;
-  A.luc = luc_dev;
-  A.top_x_ptr = B.put(Q.top_x_ptr, s);
-  A.top_src = B.put(Q.top_src, s);
-  A.coef_p = B.put(P.coef_p, s);
-  A.coef_off = B.put(P.coef_off, s);
-  A.bnode_base = (char*)Fh.sweep.bnode;
-  A.bent_base = (char*)Fh.sweep.bent;
-  A.bnode_node = B.put(Q.bnode_node, s);
-  A.isd = const_cast<double*>(Fh.sweep.isd);
-  A.top_isd = const_cast<double*>(Fh.sweep.top_isd);
-  GemmArgs GA = Fh.gemm;
-  GA.probs = B.put(Q.probs, s);
-  GA.tasks = B.put(Q.tasks, s);
-  GA.buf[BUF_LUC] = A.lu;
-  GA.buf[BUF_BT] = A.lud;
-  GA.buf[BUF_G] = A.G;
+  GemmArgs GA{};
+  setup(B, A, GA);
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipError_t e = B.err;
   auto finish = [&](Status r) {
