@@ -97,6 +97,12 @@ void batch_layout(const DeviceHandle& D, const std::vector<BatchEntry>& E, Batch
           if (need(i, P.prob_chain[P.ntasks[t].prob])) items.push_back(GroupItem{i, 0, t});
     });
   }
+  // dense rows above bottom subtrees: the items of each class
+  for (int c = 0; c < kDenseGroups; ++c)
+    stage(GK_DENSE + c, [&](int32_t i) {
+      const DeviceQueryPlan& Q = *E[i].plan;
+      if (Q.dense) range(i, Q.dclass_ptr[c], Q.dclass_ptr[c + 1]);
+    });
   // bottom subtrees: one item list per candidate schedule
   {
     std::vector<GroupItem> nat;
@@ -168,7 +174,8 @@ Status batch_launch(const BatchLayout& L, void* mem, hipStream_t s) {
 
 Status run_sweep_pruned(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t s, bool profile,
                         const SweepWork* work) {
-  std::vector<BatchEntry> be{BatchEntry{&F, &D, R_dev, work ? work->part : nullptr, work ? work->stage : nullptr}};
+  std::vector<BatchEntry> be{
+      BatchEntry{&F, &D, R_dev, work ? work->part : nullptr, work ? work->stage : nullptr}};
   auto L = std::make_shared<BatchLayout>();
   batch_layout(*F.dev, be, *L);
   void* mem = D.layout_mem;
@@ -213,7 +220,7 @@ Status run_sweep_pruned(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipS
   for (int k = nst - 1; k >= 0; --k) {
     const int kd = L->stages[k].kind;
     const bool finish = kd == GK_REDUCE || kd == GK_TOP_QUERY || kd == GK_ZERO || kd == GK_GENERAL;
-    if (kd == GK_BOTTOM || kd == GK_BOTTOM_WIDE || finish) b1 = k;
+    if (kd == GK_BOTTOM || kd == GK_BOTTOM_WIDE || kd >= GK_DENSE || finish) b1 = k;
     if (finish) b2 = k;
   }
   if (profile) (void)hipEventRecord(F.ev[0], s);
@@ -223,7 +230,8 @@ Status run_sweep_pruned(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipS
     if (k == nst) break;
     st = batch_launch_stage(*L, L->stages[k], mem, s);
     if (st != OK) return st;
-    if (L->stages[k].kind == GK_BOTTOM || L->stages[k].kind == GK_BOTTOM_WIDE) ++bottom;
+    const int kd = L->stages[k].kind;
+    if (kd == GK_BOTTOM || kd == GK_BOTTOM_WIDE || kd >= GK_DENSE) ++bottom;
     else if (k < b1) ++top;
   }
   if (profile) (void)hipEventRecord(F.ev[3], s);
@@ -488,7 +496,7 @@ peers_status peers_batch_query(peers_device d, int32_t nb, const peers_factor* f
         u = hu.data();
         v = hv.data();
       }
-      st = plan_for_pairs(*e.F, e.q, u, v, e.own, s);
+      st = plan_for_pairs(*e.F, e.q, u, v, e.own, s, true);
       if (st != OK) break;
       e.plan = &e.own;
     }

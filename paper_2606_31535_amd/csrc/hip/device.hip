@@ -85,12 +85,28 @@ static void pack_query_plan(const QueryPlan& Q, DeviceQueryPlan& D, Packer& pk) 
   pk.add(Q.tq_hi, &D.args.tq_hi);
   pk.add(Q.tq_out, &D.args.tq_out);
   pk.add(Q.zero_out, &D.args.zero_out);
+  D.args.ditems = nullptr;
+  D.args.dq_list = nullptr;
+  D.args.bq_bu = D.args.bq_bv = nullptr;
+  D.args.bq_g0 = nullptr;
+  D.args.nditems = 0;
+  D.args.dpart_off = Q.nslots;
+  if (Q.dense) {
+    pk.add(Q.ditems, &D.args.ditems);
+    pk.add(Q.dq_list, &D.args.dq_list);
+    pk.add(Q.bq_bu, &D.args.bq_bu);
+    pk.add(Q.bq_bv, &D.args.bq_bv);
+    pk.add(Q.bq_g0, &D.args.bq_g0);
+    D.args.nditems = (int64_t)Q.ditems.size();
+  }
+  D.dense = Q.dense;
+  D.dclass_ptr = Q.dclass_ptr;
   D.args.nbq = Q.nbq();
   D.args.ntq = (int64_t)Q.tq_out.size();
   D.args.nzero = (int64_t)Q.zero_out.size();
   D.args.nwork = (int64_t)Q.work_task.size();
   D.args.ngp = (int64_t)Q.gp.size();
-  D.nslots = Q.nslots;
+  D.nslots = Q.nslots + (Q.dense ? Q.nbq() : 0);  // the dense sums follow the window-group slots
   D.stage_elems = Q.stage_elems;
   D.work_task = Q.work_task;
   D.work_win = Q.work_win;
@@ -202,8 +218,13 @@ Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t
   }
   F.top_launches = launches;
   if (profile) HIP_TRY(hipEventRecord(F.ev[1], s));
+  int32_t bl = 0;
+  if (D.dense) {
+    HIP_TRY(launch_dense(F.sweep, q, D.dclass_ptr.data(), s));
+    for (int c = 0; c < kDenseGroups; ++c) bl += D.dclass_ptr[c + 1] > D.dclass_ptr[c] ? 1 : 0;
+  }
   HIP_TRY(launch_bottom(F.sweep, q, s));
-  F.bottom_launches = q.nwork > 0 ? 1 : 0;
+  F.bottom_launches = bl + (q.nwork > 0 ? 1 : 0);
   if (profile) HIP_TRY(hipEventRecord(F.ev[2], s));
   HIP_TRY(launch_finish(F.sweep, q, s));
   if (profile) HIP_TRY(hipEventRecord(F.ev[3], s));
@@ -211,12 +232,12 @@ Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t
 }
 
 Status build_query_plan_handle(const FactorHandle& F, int64_t q, const int32_t* a, const int32_t* b,
-                               QueryPlan& Q) {
-  return build_query_plan(F.first, F.depth, *F.plan, q, a, b, Q, &F.anc);
+                               QueryPlan& Q, bool dense) {
+  return build_query_plan(F.first, F.depth, *F.plan, q, a, b, Q, &F.anc, nullptr, dense);
 }
 
 Status plan_for_pairs(FactorHandle& F, int64_t q, const int32_t* u, const int32_t* v, DeviceQueryPlan& DQ,
-                      hipStream_t s) {
+                      hipStream_t s, bool dense) {
   std::vector<int32_t> a(q), b(q);
   for (int64_t k = 0; k < q; ++k) {
     if (u[k] < 0 || u[k] >= F.n || v[k] < 0 || v[k] >= F.n) {
@@ -228,7 +249,7 @@ Status plan_for_pairs(FactorHandle& F, int64_t q, const int32_t* u, const int32_
     if (u[k] == v[k]) a[k] = b[k];
   }
   QueryPlan Q;
-  Status st = build_query_plan_handle(F, q, a.data(), b.data(), Q);
+  Status st = build_query_plan_handle(F, q, a.data(), b.data(), Q, dense);
   if (st != OK) return st;
   return upload_query_plan(F, Q, DQ, s);
 }
@@ -338,7 +359,7 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
       if (G.eu[e] == G.ev[e]) a[e] = b[e];  // self-loop: R = 0
     }
     QueryPlan Q;
-    st = build_query_plan(F->first, F->depth, P, F->m, a.data(), b.data(), Q);
+    st = build_query_plan(F->first, F->depth, P, F->m, a.data(), b.data(), Q, nullptr, nullptr, true);
     if (st != OK) return (peers_status)st;
     if (Q.n_general) { set_error("internal: an edge whose endpoints are not etree-related"); return PEERS_E_INTERNAL; }
     F->t_edge_plan = now_s() - tp;
@@ -373,9 +394,17 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
   pk.add(P.bnode, &A.bnode);
   pk.add(P.bent, &A.bent);
   pk.add(P.isd, &A.isd);
+  pk.add(P.sub_p0, &A.sub_p0);
+  pk.add(P.sub_p1, &A.sub_p1);
+  pk.add(P.sub_K, &A.sub_K);
+  pk.add(P.sub_ubeg, &A.sub_ubeg);
+  pk.add(P.sub_udep, &A.sub_udep);
+  pk.add(P.sub_uoff, &A.sub_uoff);
+  pk.add(P.sub_bbase, &A.sub_bbase);
+  A.nsub = (int32_t)P.sub_p0.size();
   A.nbase = (int32_t)P.base_blocks.size();
   A.store_wide = (P.store_wide || G.store64) ? 1 : 0;
-  F->resident_bytes = pk.total + (uint64_t)std::max<int64_t>(P.bt_elems, 1) * 8;
+  F->resident_bytes = pk.total + (uint64_t)std::max<int64_t>(P.bt_elems, 1) * 8 + (uint64_t)std::max<int64_t>(P.b_elems, 1) * 8;
   F->store_bytes = (uint64_t)(std::max<int64_t>(P.store_elems, kWin) + std::max<int64_t>(P.x_elems, 1) +
                               std::max<int64_t>(P.t_elems, 1)) * 8;
   const uint64_t luc_bytes = (uint64_t)std::max<int64_t>(P.bt_elems, 1) * 8;
@@ -388,11 +417,13 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
   if (he == hipSuccess) he = hipMalloc(&F->xbuf, (size_t)std::max<int64_t>(P.x_elems, 1) * 8);
   if (he == hipSuccess) he = hipMalloc(&F->tbuf, (size_t)std::max<int64_t>(P.t_elems, 1) * 8);
   if (he == hipSuccess) he = hipMalloc(&F->btbuf, (size_t)std::max<int64_t>(P.bt_elems, 1) * 8);
+  if (he == hipSuccess) he = hipMalloc(&F->bbuf, (size_t)std::max<int64_t>(P.b_elems, 1) * 8);
   void* lucbuf = nullptr;
   if (he == hipSuccess) he = hipMalloc(&lucbuf, luc_bytes);
   if (he != hipSuccess) { D->release(luc_bytes); return (peers_status)hip_fail(he, "hipMalloc(top workspace)"); }
   A.store = (double*)F->store;
   A.X = (double*)F->xbuf;
+  A.B = (double*)F->bbuf;
   st = pk.commit(F->base, s);
   if (st != OK) { (void)hipFree(lucbuf); D->release(luc_bytes); return (peers_status)st; }
   A.lcc = lcc_dev;
@@ -431,7 +462,10 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
   {
     const double t0 = now_s();
     int32_t nl = 0;
-    st = run_chain_inverse(*F, s, nl);
+    // B_S of the bottom subtrees from the records' final coefficients
+    he = launch_bxfer(F->sweep, s);
+    st = he == hipSuccess ? OK : hip_fail(he, "bottom transfer blocks");
+    if (st == OK) st = run_chain_inverse(*F, s, nl);
     if (st == OK) {
       he = launch_gemm(F->gemm, P.bpre_begin, P.bpre_end - P.bpre_begin, s);
       if (he != hipSuccess) st = hip_fail(he, "transfer blocks");
@@ -503,6 +537,7 @@ void peers_factor_release(peers_factor f) {
   if (F->xbuf) (void)hipFree(F->xbuf);
   if (F->tbuf) (void)hipFree(F->tbuf);
   if (F->btbuf) (void)hipFree(F->btbuf);
+  if (F->bbuf) (void)hipFree(F->bbuf);
   for (auto& e : F->ev)
     if (e) (void)hipEventDestroy(e);
   if (F->part) (void)hipFree(F->part);
@@ -626,7 +661,7 @@ peers_status peers_query_all_to_ground(peers_factor f, double* R_out, uint32_t f
     std::vector<int32_t> a(F->n), b(F->n, -1);
     for (int64_t x = 0; x < F->n; ++x) a[x] = perm_index(*F, (int32_t)x);
     QueryPlan Q;
-    Status st = build_query_plan_handle(*F, F->n, a.data(), b.data(), Q);
+    Status st = build_query_plan_handle(*F, F->n, a.data(), b.data(), Q, true);
     if (st == OK) st = upload_query_plan(*F, Q, F->to_ground, s);
     if (st == OK) st = ensure_workspace(*F, F->to_ground.nslots, F->n, F->to_ground.stage_elems);
     if (st != OK) {
@@ -673,7 +708,7 @@ peers_status peers_query(peers_factor f, int64_t q, const int32_t* qu, const int
     v = hv.data();
   }
   DeviceQueryPlan DQ;
-  Status st = plan_for_pairs(*F, q, u, v, DQ, s);
+  Status st = plan_for_pairs(*F, q, u, v, DQ, s, true);
   if (st != OK) return (peers_status)st;
   st = ensure_workspace(*F, DQ.nslots, q, DQ.stage_elems);
   if (st == OK) {

@@ -42,6 +42,9 @@ struct DeviceQueryPlan {
   std::vector<int32_t> work_task, work_win;  // host copies (batch schedules)
   std::vector<char> chain_need;              // top chains the plan reads
   bool prune_top = false;
+  // dense rows above bottom subtrees: item ranges per class (host)
+  bool dense = false;
+  std::vector<int64_t> dclass_ptr;
   // grouped-launch image of a pruned plan on its own factor (owned)
   void* layout_mem = nullptr;
   uint64_t layout_bytes = 0;
@@ -64,6 +67,7 @@ struct FactorHandle {
   void* xbuf = nullptr;   // L_CC^{-1} workspace
   void* tbuf = nullptr;   // recursion temporaries
   void* btbuf = nullptr;  // transfer blocks B_C (resident)
+  void* bbuf = nullptr;   // bottom subtrees' B_S (resident)
   double t_transform = 0, t_layout = 0, t_edge_plan = 0, t_transfer = 0, t_numeric_device = 0;
   void* part = nullptr;
   void* res = nullptr;
@@ -101,18 +105,20 @@ Status ensure_workspace(FactorHandle& F, int64_t nslots, int64_t nres, int64_t n
 // Workspace of one sweep given by the caller instead of the factor's own
 // (partial slots, staging, and the launch layout of a pruned sweep).
 struct SweepWork {
-  double* part = nullptr;
+  double* part = nullptr;  // partial slots, then the dense sums (the plan's nslots)
   double* stage = nullptr;
   void* layout = nullptr;
   uint64_t layout_cap = 0;  // bytes available at `layout`
 };
 Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t s, bool profile,
                  const SweepWork* work = nullptr);
+// dense: the plan may sum rows above bottom subtrees in the dense form (for
+// plans that run through run_sweep or a batch on the factor's own workspace)
 Status build_query_plan_handle(const FactorHandle& F, int64_t q, const int32_t* a, const int32_t* b,
-                               QueryPlan& Q);
+                               QueryPlan& Q, bool dense = false);
 // Validates q pairs of original ids, builds their plan and uploads it.
 Status plan_for_pairs(FactorHandle& F, int64_t q, const int32_t* u, const int32_t* v, DeviceQueryPlan& D,
-                      hipStream_t s);
+                      hipStream_t s, bool dense = false);
 
 // Reduced-permuted index of an original node id (-1 for the ground).
 inline int32_t perm_index(const FactorHandle& F, int32_t x) {

@@ -13,8 +13,8 @@
 // held until the call's work has finished), so two of them never share the
 // array at once; nothing else in the library uses it. Every word a call
 // reads from the array is written earlier in the same call (plan and layout
-// by copies, partial slots and staging by the sweep before the reduction
-// reads them), so nothing needs clearing between calls.
+// by copies, partial slots, dense sums and staging by the sweep before the
+// reduction reads them), so nothing needs clearing between calls.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -103,13 +103,15 @@ peers_status peers_query_noalloc(peers_factor f, int64_t q, const int32_t* qu, c
     if (u[k] == v[k]) a[k] = b[k];
   }
   QueryPlan Q;
-  Status st = build_query_plan_handle(*F, q, a.data(), b.data(), Q);
+  Status st = build_query_plan_handle(*F, q, a.data(), b.data(), Q, true);
   if (st != OK) return (peers_status)st;
-  // scratch layout: plan, partial slots, results (host output only), staging,
-  // then the launch layout of a pruned sweep in what is left
+  // scratch layout: plan, partial slots (and dense sums), results (host
+  // output only), staging, then the launch layout of a pruned sweep in what
+  // is left
   const bool dev_out = flags & PEERS_OUT_DEVICE;
   const uint64_t plan_b = align256(query_plan_bytes(Q));
-  const uint64_t part_b = align256((uint64_t)std::max<int64_t>(Q.nslots, 1) * 8);
+  const int64_t nslots = Q.nslots + (Q.dense ? Q.nbq() : 0);
+  const uint64_t part_b = align256((uint64_t)std::max<int64_t>(nslots, 1) * 8);
   const uint64_t res_b = dev_out ? 0 : align256((uint64_t)q * 8);
   const uint64_t stage_b = align256((uint64_t)std::max<int64_t>(Q.stage_elems, 1) * 8);
   const uint64_t fixed = plan_b + part_b + res_b + stage_b;

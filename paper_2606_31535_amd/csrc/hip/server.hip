@@ -213,7 +213,7 @@ Launch launch(Server& S, Slot& sl, const std::vector<ReqPtr>& take,
       a.insert(a.end(), r->a.begin(), r->a.end());
       b.insert(b.end(), r->b.begin(), r->b.end());
     }
-    pst[i] = build_query_plan_handle(*F, q, a.data(), b.data(), plans[i]);
+    pst[i] = build_query_plan_handle(*F, q, a.data(), b.data(), plans[i], true);
   };
   {
     std::vector<std::thread> th;
@@ -262,16 +262,23 @@ Launch launch(Server& S, Slot& sl, const std::vector<ReqPtr>& take,
     d.args.ntq = (int64_t)sl.hplans[i].tq_out.size();
     d.args.nzero = (int64_t)sl.hplans[i].zero_out.size();
     d.args.ngp = (int64_t)sl.hplans[i].gp.size();
+    d.args.nditems = (int64_t)sl.hplans[i].ditems.size();
+    d.dense = sl.hplans[i].dense;
+    d.dclass_ptr = sl.hplans[i].dclass_ptr;
     be.push_back(BatchEntry{planned[i], &sl.dplans[i], nullptr, nullptr, nullptr});
   }
   BatchLayout probe;
   batch_layout(*S.D, be, probe);
   const uint64_t layout_off = bytes;
   bytes += align256(probe.bytes);
+  // partial slots (with the dense sums after them), results, staging
+  auto part_bytes = [](const QueryPlan& Q) {
+    return align256((uint64_t)std::max<int64_t>(Q.nslots + (Q.dense ? Q.nbq() : 0), 1) * 8);
+  };
   for (size_t i = 0; i < np; ++i) {
     const QueryPlan& Q = sl.hplans[i];
     woff[i] = bytes;
-    bytes += align256((uint64_t)std::max<int64_t>(Q.nslots, 1) * 8) + align256((uint64_t)std::max<int64_t>(Q.q, 1) * 8) +
+    bytes += part_bytes(Q) + align256((uint64_t)std::max<int64_t>(Q.q, 1) * 8) +
              align256((uint64_t)std::max<int64_t>(Q.stage_elems, 1) * 8);
   }
   Launch how = reserve_arena(S, sl, bytes, err);
@@ -282,7 +289,7 @@ Launch launch(Server& S, Slot& sl, const std::vector<ReqPtr>& take,
     const QueryPlan& Q = sl.hplans[i];
     st = upload_query_plan_to(Q, sl.dplans[i], ar + poff[i], sl.stream);
     be[i].part = (double*)(ar + woff[i]);
-    be[i].R_dev = (double*)(ar + woff[i] + align256((uint64_t)std::max<int64_t>(Q.nslots, 1) * 8));
+    be[i].R_dev = (double*)(ar + woff[i] + part_bytes(Q));
     be[i].stage = (double*)((char*)be[i].R_dev + align256((uint64_t)std::max<int64_t>(Q.q, 1) * 8));
   }
   if (st == OK) {

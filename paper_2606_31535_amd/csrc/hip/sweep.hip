@@ -10,6 +10,11 @@
 //    Z[rows above C, C] = Z[rows above C, U_C] B_C with the ancestor columns
 //    gathered from the top store (64 x 32 tiles for wide chains, one-wave
 //    64 x 16 tiles for narrow ones).
+//  * dense rows above bottom subtrees (host/plan.h, kDenseMaxK): at upload,
+//    bxfer_kernel forms B_S of every bottom subtree; every sweep,
+//    dense_kernel sums the rows above each subtree for its queries as
+//    ||Z[rows, U_S] w||^2 on the matrix cores, and the bottom sweep starts
+//    past those rows where every query of a task has such a sum.
 //  * bottom_kernel: one wavefront per (bottom subtree task, group of two
 //    windows). Nodes are visited in descending index, a topological order of
 //    every row's traversal; the values of the current root path live in a
@@ -675,13 +680,212 @@ __device__ __forceinline__ void reduce_body(const QueryArgs& Q, int64_t blk) {
   if (j >= Q.nbq) return;
   const BQuery bq = Q.bq[j];
   if (bq.kind == kQStage) return;
-  double s = 0.0;
+  // the dense sum of the rows above the subtree first (when the plan has
+  // one for this query), then the sweep's window groups in order
+  const int32_t g0 = Q.bq_g0 ? Q.bq_g0[j] : 0;
+  double s = g0 > 0 ? Q.part[Q.dpart_off + j] : 0.0;
   const int32_t ng = (bq.nwin + kWinPerWave - 1) / kWinPerWave;
-  for (int32_t g = 0; g < ng; ++g) s += Q.part[(int64_t)g * Q.nbq + j];
+  for (int32_t g = g0; g < ng; ++g) s += Q.part[(int64_t)g * Q.nbq + j];
   Q.R[bq.out] = s;
 }
 
 __global__ __launch_bounds__(256) void reduce_bottom_kernel(QueryArgs Q) { reduce_body(Q, blockIdx.x); }
+
+// B_S of one bottom subtree (one wavefront, lane e = column e of U_S): eq 11
+// inside the subtree with the columns of U_S as unit vectors, nodes in
+// processing order (every node after its ancestors), the columns of the
+// current root path kept per local depth in LDS. Top-store entries of a
+// record name their column by its store offset, which identifies its lane.
+typedef double XferStack[kBottomMaxHeight][kWin];
+__device__ __forceinline__ void bxfer_body(const SweepArgs& A, int32_t sub, XferStack& st) {
+  const int lane = threadIdx.x & 63;
+  const int32_t K = load_uniform(A.sub_K + sub);
+  if (K == 0 || K > kDenseMaxK) return;
+  const int64_t mine = lane < K ? A.sub_uoff[load_uniform(A.sub_ubeg + sub) + lane] : -1;
+  const int32_t p0 = load_uniform(A.sub_p0 + sub), p1 = load_uniform(A.sub_p1 + sub);
+  double* __restrict__ Bs = A.B + load_uniform(A.sub_bbase + sub);
+  auto slot = [](int32_t code) { return (code & kSlotMask) >> 1; };
+  for (int32_t p = p0; p < p1; ++p) {
+    const BNode b = load_uniform(A.bnode + p);
+    const int32_t sl = b.slots;
+    const int32_t ninl = (sl >> kInlineCountShift) & 3;
+    double acc = 0.0;
+    if (ninl > 0) acc = fma(b.lc[0], st[slot(sl)][lane], acc);
+    if (ninl > 1) acc = fma(b.lc[1], st[slot(sl >> kSlotBits)][lane], acc);
+    if (ninl > 2) acc = fma(b.lc[2], st[slot(sl >> (2 * kSlotBits))][lane], acc);
+    const int32_t nl = b.n_more & 0xffff, nt = (int32_t)((uint32_t)b.n_more >> 16);
+    for (int32_t e = 0; e < nl; ++e) {
+      const BEnt be = load_uniform(A.bent + b.ent + e);
+      acc = fma(be.coef, st[slot((int32_t)be.ref)][lane], acc);
+    }
+    // a store reference's low word is its column's first window
+    auto top = [&](int64_t ref, double c) {
+      if ((int64_t)(uint32_t)ref * kWin == mine) acc += c;
+    };
+    top(b.tref[0], b.tc[0]);
+    top(b.tref[1], b.tc[1]);
+    for (int32_t e = 0; e < nt; ++e) {
+      const BEnt be = load_uniform(A.bent + b.ent + nl + e);
+      top(be.ref, be.coef);
+    }
+    st[slot(sl >> kOwnSlotShift)][lane] = acc;
+    if (lane < K) Bs[(int64_t)(p - p0) * K + lane] = acc;
+  }
+}
+
+__global__ __launch_bounds__(64 * kBottomWaves) void bxfer_kernel(SweepArgs A) {
+  __shared__ XferStack st[kBottomWaves];
+  const int wave = threadIdx.x >> 6;
+  const int32_t sub = blockIdx.x * kBottomWaves + wave;
+  if (sub < A.nsub) bxfer_body(A, sub, st[wave]);
+}
+
+// One dense item (one workgroup): rows [0, rows) of Z[rows, U_S] W for up
+// to G column tiles of 16 queries, on v_mfma_f64_16x16x4f64 (A lane l: row
+// l%16 of a 16-row tile, column 4s + l/16 of U_S; B lane l: element
+// (4s + l/16, l%16) of a column tile of W; C lane l: four rows of query
+// l%16). W is formed in LDS from B_S: column c of tile g is B_S e_u -
+// B_S e_v (v in S), B_S e_u - e_k (v the k-th column of U_S) or B_S e_u
+// (the ground), zero past the queries and past |U_S|. Each wave takes every
+// fourth step of RT row tiles; a loaded row block serves all column tiles.
+// Products are squared and added per lane; the four lanes of a query, then
+// the four waves, are summed in a fixed order. Columns of U_S are ordered by
+// depth, descending, so k-group s is needed only for rows above the depth
+// of its first column; inside a group, rows at or past a column's depth read
+// the store's leading zero block.
+// Calls f(std::integral_constant<int, n>) for a run-time n in [1, KS).
+template <int KS, class F>
+__device__ __forceinline__ void dense_dispatch(int32_t n, F&& f) {
+  if constexpr (KS > 1) {
+    if (n == KS - 1) f(std::integral_constant<int, KS - 1>());
+    else dense_dispatch<KS - 1>(n, f);
+  }
+}
+
+template <int GRP>
+struct DenseLds {
+  double w[1 << (GRP % kDenseTileKinds)][dense_steps(GRP / kDenseTileKinds)][kWin];
+  double red[kBottomWaves][1 << (GRP % kDenseTileKinds)][kDenseTile];
+};
+
+// GRP = class * kDenseTileKinds + log2(column tiles)
+template <int GRP>
+__device__ __forceinline__ void dense_body(const SweepArgs& A, const QueryArgs& Q, int64_t it, DenseLds<GRP>& L) {
+  constexpr int CLS = GRP / kDenseTileKinds;
+  constexpr int KS = dense_steps(CLS), G = 1 << (GRP % kDenseTileKinds), RT = dense_rt(CLS);
+  const int tid = threadIdx.x, lane = tid & 63, kq = lane >> 4, r = lane & 15;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const DItem d = load_struct(Q.ditems + it);
+  const int32_t K = load_uniform(A.sub_K + d.sub), ub = load_uniform(A.sub_ubeg + d.sub);
+  for (int e = tid; e < G * KS * kWin; e += 64 * kBottomWaves) {
+    const int g = e / (KS * kWin), s = (e / kWin) % KS, l = e % kWin;
+    const int32_t k = 4 * s + (l >> 4), qi = g * kDenseTile + (l & 15);
+    double v = 0.0;
+    if (qi < d.nq && k < K) {
+      const int64_t j = Q.dq_list[d.q0 + qi];
+      const int64_t bu = Q.bq_bu[j], bv = Q.bq_bv[j];
+      v = A.B[bu + k];
+      if (bv >= 0) v -= A.B[bv + k];
+      else if (bv != kDenseNoV && k == (int32_t)(-1 - bv)) v -= 1.0;
+    }
+    L.w[g][s][l] = v;
+  }
+  __syncthreads();
+  const double* __restrict__ z = A.store;
+  int32_t uo[KS], ud[KS], sd[KS];  // (the planner keeps store offsets of dense plans below 2^31)
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int32_t k = 4 * s + kq;
+    uo[s] = k < K ? (int32_t)A.sub_uoff[ub + k] : 0;
+    ud[s] = k < K ? A.sub_udep[ub + k] : 0;
+    sd[s] = 4 * s < K ? load_uniform(A.sub_udep + ub + 4 * s) : 0;
+  }
+  double sq[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) sq[g] = 0.0;
+  // row blocks of this wave, the next one's loads in flight during each
+  constexpr int32_t kStep = kBottomWaves * 16 * RT;
+  auto load = [&](int32_t d0, double (&a)[KS][RT]) {
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int i = 0; i < RT; ++i) {
+        const int32_t row = d0 + 16 * i + r;
+        // unconditional (a load on a branch would make the join wait for it)
+        a[s][i] = z[sd[s] > d0 && row < ud[s] ? uo[s] + row : r];
+      }
+  };
+  // the k-groups needed for rows from d0 on (a prefix), as a constant per
+  // case so that every product of a block is straight-line code
+  auto nsteps = [&](int32_t d0) {
+    int32_t n = 0;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) n += sd[s] > d0 ? 1 : 0;
+    return n;
+  };
+  auto block_n = [&](auto NS, const double (&a)[KS][RT]) {
+    constexpr int N = decltype(NS)::value;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+#pragma unroll
+      for (int i = 0; i < RT; ++i) {
+        f64x4 c = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < N; ++s) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s][i], L.w[g][s][lane], c, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sq[g] = fma(c[e], c[e], sq[g]);
+      }
+      // one column tile's products at a time (their accumulators stay few)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+  auto block = [&](int32_t d0, const double (&a)[KS][RT]) {
+    const int32_t n = nsteps(d0);
+    if (KS == 1 || n == KS) block_n(std::integral_constant<int, KS>(), a);
+    else dense_dispatch<KS>(n, [&](auto NS) { block_n(NS, a); });
+  };
+  double a0[KS][RT], a1[KS][RT];
+  int32_t d0 = wave * 16 * RT;
+  if (d0 < d.rows) load(d0, a0);
+  while (d0 < d.rows) {
+    if (d0 + kStep < d.rows) load(d0 + kStep, a1);
+    block(d0, a0);
+    d0 += kStep;
+    if (d0 >= d.rows) break;
+    if (d0 + kStep < d.rows) load(d0 + kStep, a0);
+    block(d0, a1);
+    d0 += kStep;
+  }
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    sq[g] += __shfl_xor(sq[g], 16);
+    sq[g] += __shfl_xor(sq[g], 32);
+    if (lane < kDenseTile) L.red[wave][g][lane] = sq[g];
+  }
+  __syncthreads();
+  for (int t = tid; t < d.nq; t += 64 * kBottomWaves) {
+    const int g = t / kDenseTile, c = t % kDenseTile;
+    Q.part[Q.dpart_off + Q.dq_list[d.q0 + t]] = (L.red[0][g][c] + L.red[1][g][c]) + (L.red[2][g][c] + L.red[3][g][c]);
+  }
+}
+
+template <int GRP>
+__global__ __launch_bounds__(64 * kBottomWaves) __attribute__((amdgpu_waves_per_eu(4))) void dense_kernel(
+    SweepArgs A, QueryArgs Q, int64_t i0) {
+  __shared__ DenseLds<GRP> L;
+  dense_body<GRP>(A, Q, i0 + blockIdx.x, L);
+}
+
+// Calls f(std::integral_constant<int, x>) for a run-time group x in [X, kDenseGroups).
+template <int X, class F>
+void dense_group(int x, F&& f) {
+  if constexpr (X < kDenseGroups) {
+    // (groups with more tiles than their class takes hold no items)
+    if constexpr ((1 << (X % kDenseTileKinds)) <= dense_tiles(X / kDenseTileKinds))
+      if (x == X) return f(std::integral_constant<int, X>());
+    dense_group<X + 1>(x, f);
+  }
+}
 
 // Pairs whose endpoints are not ancestor-related (eq 12 over the union of the
 // two root paths): rows above the lowest common ancestor are shared, so
@@ -890,6 +1094,18 @@ __global__ __launch_bounds__(256) void grouped_top_query_kernel(const FactorArgs
   top_query_body(load_struct(&fa[f].a), load_struct(&fa[f].q), load_uniform(&items[i].local));
 }
 
+// dense items of many factors: one workgroup per item
+template <int GRP>
+__global__ __launch_bounds__(64 * kBottomWaves) __attribute__((amdgpu_waves_per_eu(4))) void grouped_dense_kernel(
+    const FactorArgs* __restrict__ fa, const GroupItem* __restrict__ items, int64_t nitems) {
+  __shared__ DenseLds<GRP> L;
+  for (int64_t i = blockIdx.x; i < nitems; i += gridDim.x) {
+    const int32_t f = load_uniform(&items[i].fa);
+    dense_body<GRP>(load_struct(&fa[f].a), load_struct(&fa[f].q), load_uniform(&items[i].local), L);
+    __syncthreads();
+  }
+}
+
 template <int KIND>
 __global__ __launch_bounds__(256) void grouped_kernel(const FactorArgs* __restrict__ fa,
                                                       const GroupItem* __restrict__ items, int64_t nitems) {
@@ -948,7 +1164,15 @@ hipError_t launch_grouped(int kind, const FactorArgs* fa, const GroupItem* items
       break;
     case GK_ZERO: hipLaunchKernelGGL(grouped_kernel<GK_ZERO>, g, dim3(256), 0, s, fa, items, nitems); break;
     case GK_GENERAL: hipLaunchKernelGGL(grouped_kernel<GK_GENERAL>, g, dim3(256), 0, s, fa, items, nitems); break;
-    default: return hipErrorInvalidValue;
+    default:
+      if (kind >= GK_DENSE && kind < GK_DENSE + kDenseGroups) {
+        dense_group<0>(kind - GK_DENSE, [&](auto X) {
+          hipLaunchKernelGGL(grouped_dense_kernel<decltype(X)::value>, g, dim3(64 * kBottomWaves), 0, s, fa, items,
+                             nitems);
+        });
+        break;
+      }
+      return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
@@ -986,6 +1210,24 @@ hipError_t launch_bottom(const SweepArgs& a, const QueryArgs& q, hipStream_t s) 
     hipLaunchKernelGGL(bottom_kernel<true>, dim3((unsigned)q.nwork), dim3(64 * kBottomWaves), 0, s, a, q);
   else
     hipLaunchKernelGGL(bottom_kernel<false>, dim3((unsigned)q.nwork), dim3(64 * kBottomWaves), 0, s, a, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_bxfer(const SweepArgs& a, hipStream_t s) {
+  if (a.nsub <= 0) return hipSuccess;
+  hipLaunchKernelGGL(bxfer_kernel, dim3((unsigned)((a.nsub + kBottomWaves - 1) / kBottomWaves)), dim3(64 * kBottomWaves),
+                     0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense(const SweepArgs& a, const QueryArgs& q, const int64_t* dclass_ptr, hipStream_t s) {
+  for (int x = 0; x < kDenseGroups; ++x) {
+    const int64_t i0 = dclass_ptr[x], n = dclass_ptr[x + 1] - dclass_ptr[x];
+    if (n <= 0) continue;
+    dense_group<0>(x, [&](auto X) {
+      hipLaunchKernelGGL(dense_kernel<decltype(X)::value>, dim3((unsigned)n), dim3(64 * kBottomWaves), 0, s, a, q, i0);
+    });
+  }
   return hipGetLastError();
 }
 

@@ -44,6 +44,16 @@ struct SweepArgs {
   const BEnt* bent;
   const double* isd;
   int32_t store_wide;  // 1: store byte offsets need 64 bits
+  // dense form of the rows above bottom subtrees (host/plan.h, kDenseMaxK)
+  int32_t nsub;
+  const int32_t* sub_p0;
+  const int32_t* sub_p1;
+  const int32_t* sub_K;
+  const int32_t* sub_ubeg;
+  const int32_t* sub_udep;
+  const int64_t* sub_uoff;
+  const int64_t* sub_bbase;
+  double* B;  // B_S of every subtree, formed at upload
 };
 
 struct QueryArgs {
@@ -65,6 +75,15 @@ struct QueryArgs {
   double* stage;  // staged bottom columns of non-ancestor pairs
   double* part;
   double* R;
+  // dense work items (null when the plan has none): their queries in
+  // dq_list, the dense sum of bottom query j at part[dpart_off + j]
+  const DItem* ditems;
+  int64_t nditems;
+  const int32_t* dq_list;
+  const int64_t* bq_bu;
+  const int64_t* bq_bv;
+  const int32_t* bq_g0;
+  int64_t dpart_off;
 };
 
 // Everything one factor's sweep reads, for grouped launches over many factors.
@@ -88,7 +107,9 @@ enum GroupKind : int {
   GK_REDUCE = 4, GK_TOP_QUERY = 5, GK_ZERO = 6, GK_GENERAL = 7, GK_GEMM_NARROW = 8,
   // the bottom step of a group holding a factor with 64-bit store offsets
   // (GK_BOTTOM runs only the 32-bit form, which keeps its register count low)
-  GK_BOTTOM_WIDE = 9
+  GK_BOTTOM_WIDE = 9,
+  // dense rows above bottom subtrees: the items of each group (GK_DENSE + group)
+  GK_DENSE = 10
 };
 
 // Items per finish block of each kind (threads, or wavefronts per item; the
@@ -104,6 +125,10 @@ hipError_t launch_gemm_level(const GemmArgs& g, int64_t task0, int64_t ntasks, i
 hipError_t launch_inv_base(const SweepArgs& a, hipStream_t s);
 hipError_t launch_chain_rows(const SweepArgs& a, int32_t ntop, hipStream_t s);
 hipError_t launch_bottom(const SweepArgs& a, const QueryArgs& q, hipStream_t s);
+// B_S of every subtree with |U_S| <= kDenseMaxK (upload, after the records hold the factor)
+hipError_t launch_bxfer(const SweepArgs& a, hipStream_t s);
+// the dense sums of every item (dclass_ptr: the plan's item ranges per class, host memory)
+hipError_t launch_dense(const SweepArgs& a, const QueryArgs& q, const int64_t* dclass_ptr, hipStream_t s);
 hipError_t launch_finish(const SweepArgs& a, const QueryArgs& q, hipStream_t s);
 
 }  // namespace peers

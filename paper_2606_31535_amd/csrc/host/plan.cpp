@@ -312,6 +312,24 @@ Status build_plan(const Symbolic& S, const Numeric* Fp, FactorPlan& P) {
     const int32_t sz = r - S.first[r] + 1;
     if (cur > 0 && cur + sz > kBottomMaxNodes) close_task();
     if (p >= 0) P.btask_attach.push_back(chain_of[p]);  // the chain this subtree hangs from
+    {
+      // U_S = struct(r): every row of the subtree's columns outside it
+      const int32_t K = (int32_t)(S.colptr[r + 1] - S.colptr[r]);
+      P.sub_p0.push_back((int32_t)P.bnode.size());
+      P.sub_p1.push_back((int32_t)P.bnode.size() + sz);
+      P.sub_K.push_back(K);
+      P.sub_ubeg.push_back((int32_t)P.sub_uoff.size());
+      for (int64_t q = S.colptr[r]; q < S.colptr[r + 1]; ++q) {
+        const int32_t u = S.rowidx[q];
+        if (P.top_index[u] < 0) { set_error("plan: a row outside a bottom subtree is not a top node"); return E_INTERNAL; }
+        P.sub_uoff.push_back(P.top_off[P.top_index[u]]);
+        P.sub_udep.push_back(S.depth[u]);
+        P.sub_unode.push_back(u);
+      }
+      P.sub_bbase.push_back(P.b_elems);
+      if (K <= kDenseMaxK) P.b_elems += (int64_t)K * sz;
+      P.bpos_sub.insert(P.bpos_sub.end(), sz, (int32_t)P.sub_p0.size() - 1);
+    }
     for (int32_t v = r; v >= S.first[r]; --v) {
       BNode bn{};
       bn.isd = P.isd[v];
@@ -454,9 +472,100 @@ int32_t AncestorTable::lca(int32_t a, int32_t b) const {
   return std::max(a, b);
 }
 
+// The dense form's part of a query plan (see kDenseMaxK): which tasks use it,
+// their first sweep window, the w of every query, and the dense work items.
+static void plan_dense(const FactorPlan& P, const std::vector<int32_t>& depth, int64_t nb,
+                       const std::vector<int32_t>& jlo, const std::vector<int32_t>& jhi, QueryPlan& Q,
+                       std::vector<int32_t>& tw0) {
+  // the dense sums address the store with 32-bit element offsets
+  if (P.store_elems > INT32_MAX) return;
+  const std::vector<int32_t>& pos = P.node_pos;
+  Q.bq_bu.assign(nb + 1, 0);
+  Q.bq_bv.assign(nb + 1, kDenseNoV);
+  Q.bq_g0.assign(nb + 1, 0);
+  std::vector<char> ok(nb, 0);
+  for (int64_t j = 0; j < nb; ++j) {
+    const int32_t lo = jlo[j], hi = jhi[j];
+    if (lo < 0) continue;  // a staging entry
+    const int32_t sub = P.bpos_sub[pos[lo]];
+    const int32_t K = P.sub_K[sub];
+    if (K > kDenseMaxK) continue;
+    int64_t bv = kDenseNoV;
+    if (hi >= 0 && P.small[hi]) {
+      // an ancestor in the same subtree
+      if (P.bpos_sub[pos[hi]] != sub) continue;
+      bv = P.sub_bbase[sub] + (int64_t)(pos[hi] - P.sub_p0[sub]) * K;
+    } else if (hi >= 0) {
+      // a top node: one of the columns of U_S, or the form does not apply
+      const int32_t* U = P.sub_unode.data() + P.sub_ubeg[sub];
+      const int32_t* it = std::lower_bound(U, U + K, hi);
+      if (it == U + K || *it != hi) continue;
+      bv = -1 - (int64_t)(it - U);
+    }
+    Q.bq_bu[j] = P.sub_bbase[sub] + (int64_t)(pos[lo] - P.sub_p0[sub]) * K;
+    Q.bq_bv[j] = bv;
+    ok[j] = 1;
+  }
+  const int32_t nbt = (int32_t)P.btask_nwin.size();
+  std::vector<DItem> items;
+  std::vector<int32_t> cls;
+  for (int32_t t = 0; t < nbt; ++t) {
+    const int32_t j0 = Q.bq_ptr[P.btask_ptr[t]], j1 = Q.bq_ptr[P.btask_ptr[t + 1]];
+    if (j0 == j1) continue;
+    // rows above the task's shallowest subtree, in whole window groups
+    int32_t rmin = INT32_MAX;
+    for (int32_t p = P.btask_ptr[t]; p < P.btask_ptr[t + 1]; p = P.sub_p1[P.bpos_sub[p]])
+      rmin = std::min(rmin, depth[P.bnode_node[p]] - 1);  // a subtree's first record is its root
+    const int32_t w0 = kWinPerWave * (rmin / (kWin * kWinPerWave));
+    if (w0 == 0) continue;
+    bool all = true;
+    for (int32_t j = j0; j < j1; ++j) {
+      if (ok[j]) Q.bq_g0[j] = w0 / kWinPerWave;
+      else all = false;
+    }
+    if (all) tw0[t] = w0;
+    for (int32_t p = P.btask_ptr[t]; p < P.btask_ptr[t + 1];) {
+      const int32_t sub = P.bpos_sub[p];
+      const int32_t s0 = Q.bq_ptr[P.sub_p0[sub]], s1 = Q.bq_ptr[P.sub_p1[sub]];
+      const int32_t l0 = (int32_t)Q.dq_list.size();
+      for (int32_t j = s0; j < s1; ++j)
+        if (ok[j]) Q.dq_list.push_back(j);
+      const int32_t l1 = (int32_t)Q.dq_list.size();
+      const int cl = dense_class(P.sub_K[sub]);
+      // the subtree's column tiles in items of 1, 2, 4 or 8 tiles, largest first
+      for (int32_t c = l0; c < l1;) {
+        const int32_t tiles = (l1 - c + kDenseTile - 1) / kDenseTile;
+        int lg = 0;
+        while (lg + 1 < kDenseTileKinds && (1 << (lg + 1)) <= std::min(tiles, dense_tiles(cl))) ++lg;
+        const int32_t nq = std::min((int32_t)kDenseTile << lg, l1 - c);
+        items.push_back(DItem{sub, c, nq, kWin * w0});
+        cls.push_back(cl * kDenseTileKinds + lg);
+        c += nq;
+      }
+      p = P.sub_p1[sub];
+    }
+  }
+  // by class, then largest first (rows times column tiles; a subtree's items
+  // stay adjacent)
+  std::vector<int64_t> ord(items.size());
+  for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int64_t)i;
+  auto cost = [&](int64_t x) { return (int64_t)items[x].rows * ((items[x].nq + kDenseTile - 1) / kDenseTile); };
+  std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) {
+    if (cls[x] != cls[y]) return cls[x] < cls[y];
+    return cost(x) > cost(y);
+  });
+  Q.dclass_ptr.assign(kDenseGroups + 1, 0);
+  for (int64_t x : ord) {
+    Q.ditems.push_back(items[x]);
+    Q.dclass_ptr[cls[x] + 1]++;
+  }
+  for (int c = 0; c < kDenseGroups; ++c) Q.dclass_ptr[c + 1] += Q.dclass_ptr[c];
+  Q.dense = !Q.ditems.empty();
+}
+
 Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int32_t>& depth,
                         const FactorPlan& P, int64_t q, const int32_t* a, const int32_t* b, QueryPlan& Q,
-                        const AncestorTable* anc, const std::vector<int32_t>* export_nodes) {
+                        const AncestorTable* anc, const std::vector<int32_t>* export_nodes, bool dense) {
   const int32_t N = P.N;
   Q = QueryPlan();
   Q.q = q;
@@ -558,6 +667,7 @@ Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int
   const int64_t nb = Q.bq_ptr[nbn];
   Q.bq.resize(nb);
   std::vector<int32_t> fill(Q.bq_ptr.begin(), Q.bq_ptr.end() - 1);
+  std::vector<int32_t> jlo(dense ? nb : 0, -1), jhi(dense ? nb : 0, -1);  // endpoints per entry (-1: staging)
   // staging entries first within their node's bucket
   if (!stage_of.empty())
     for (int32_t x = 0; x < N; ++x) {
@@ -573,6 +683,10 @@ Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int
     const int32_t lo = lo_of[k];
     if (lo < 0 || !P.small[lo]) continue;
     const int32_t hi = hi_of[k];
+    if (dense) {
+      jlo[fill[pos[lo]]] = lo;
+      jhi[fill[pos[lo]]] = hi;
+    }
     BQuery& bq = Q.bq[fill[pos[lo]]++];
     bq.out = k;
     bq.nwin = nwin_of(depth[lo]);
@@ -599,20 +713,16 @@ Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int
   // kWinPerWave windows (groups past a query's column are never read)
   const int32_t groups = (std::max(Q.max_nwin, P.max_btask_nwin) + kWinPerWave - 1) / kWinPerWave;
   Q.nslots = (int64_t)groups * nb;
-  // work list: the tasks with at least one bucket entry, every window
+  // top chains the plan reads: those of the swept subtrees' attachment
+  // points (subtrees with at least one bucket entry), of its top endpoints,
+  // and every ancestor chain of those
   const int32_t nbt = (int32_t)P.btask_nwin.size();
   const int32_t nch = (int32_t)P.chains.size();
+  auto swept = [&](int32_t t) { return Q.bq_ptr[P.btask_ptr[t + 1]] != Q.bq_ptr[P.btask_ptr[t]]; };
   Q.chain_need.assign(nch, 0);
-  for (int32_t t = 0; t < nbt; ++t) {
-    if (Q.bq_ptr[P.btask_ptr[t + 1]] == Q.bq_ptr[P.btask_ptr[t]]) continue;
-    for (int32_t w = 0; w < P.btask_nwin[t]; w += kBottomWaves * kWinPerWave) {
-      Q.work_task.push_back(t);
-      Q.work_win.push_back(w);
-    }
-    for (int32_t k = P.btask_attach_ptr[t]; k < P.btask_attach_ptr[t + 1]; ++k) Q.chain_need[P.btask_attach[k]] = 1;
-  }
-  // top chains the plan reads: those of its top endpoints and of the swept
-  // subtrees' attachment points, and every ancestor chain of those
+  for (int32_t t = 0; t < nbt; ++t)
+    if (swept(t))
+      for (int32_t k = P.btask_attach_ptr[t]; k < P.btask_attach_ptr[t + 1]; ++k) Q.chain_need[P.btask_attach[k]] = 1;
   for (int32_t lo : Q.tq_lo) Q.chain_need[P.top_chain[lo]] = 1;
   for (int32_t x : gp_top) Q.chain_need[P.top_chain[P.top_index[x]]] = 1;
   for (int32_t c = 0; c < nch; ++c)
@@ -620,6 +730,18 @@ Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int
   int32_t need = 0;
   for (int32_t c = 0; c < nch; ++c) need += Q.chain_need[c];
   Q.prune_top = need < nch;
+  // first window of each task's sweep: 0, or past the rows that the dense
+  // form covers for every subtree of the task
+  std::vector<int32_t> tw0(nbt, 0);
+  if (dense && nb > 0 && !P.sub_p0.empty()) plan_dense(P, depth, nb, jlo, jhi, Q, tw0);
+  // work list: the swept tasks, every window from the first
+  for (int32_t t = 0; t < nbt; ++t) {
+    if (!swept(t)) continue;
+    for (int32_t w = tw0[t]; w < P.btask_nwin[t]; w += kBottomWaves * kWinPerWave) {
+      Q.work_task.push_back(t);
+      Q.work_win.push_back(w);
+    }
+  }
   return OK;
 }
 

@@ -64,6 +64,33 @@ constexpr int kBottomMaxNodes = 512;
 constexpr int kBottomWaves = 4;       // wavefronts per bottom workgroup
 constexpr int kWinPerWave = 2;        // windows per bottom wavefront (lane l: depths t*64 + l)
 constexpr int32_t kGroundCode = INT32_MIN;
+// Dense form of the rows above a bottom subtree S with root r. Every column
+// of S restricted to the rows above S is a combination of the columns of
+// U_S = struct(r) (top nodes, all ancestors of r), by eq 11 applied inside S:
+//     Z[above S, S] = Z[above S, U_S] B_S,   B_S = -L_{U_S,S} L_SS^{-1},
+// with B_S >= 0 and every column summing to at most 1. A query (u, v) with u
+// in S then gets its rows above S as
+//     sum_d (Z[d, U_S] w)^2,   w = B_S e_u - (B_S e_v | e_v | 0)
+// for v in S, v in U_S, or the ground: per subtree a product of the top-store
+// columns of U_S (rows x |U_S|) with the queries' w (|U_S| x queries) on the
+// FP64 matrix cores, squared and summed per query. The sweep then runs only
+// the rows from the subtree's own depth on. Subtrees with |U_S| above
+// kDenseMaxK keep the full sweep.
+constexpr int kDenseMaxK = 64;
+constexpr int kDenseTile = 16;        // queries per MFMA column tile
+constexpr int kDenseClasses = 5;      // |U_S| padded to 4, 8, 16, 32 or 64
+constexpr int dense_class(int32_t K) { return K <= 4 ? 0 : K <= 8 ? 1 : K <= 16 ? 2 : K <= 32 ? 3 : 4; }
+constexpr int dense_steps(int cls) { return 1 << cls; }  // k-groups of 4 per class
+// column tiles per dense work item: 1, 2, 4 or 8 (at most dense_tiles of
+// the class; each loaded row block of U_S serves all of them), and row
+// tiles per step, per class. Items are grouped by (class, tiles): group
+// class * kDenseTileKinds + log2(tiles).
+constexpr int dense_tiles(int cls) { return cls <= 1 ? 8 : cls <= 3 ? 4 : 2; }
+constexpr int dense_rt(int cls) { return cls <= 1 ? 4 : cls == 2 ? 2 : 1; }
+constexpr int kDenseTileKinds = 4;
+constexpr int kDenseGroups = kDenseClasses * kDenseTileKinds;
+// w of a query whose higher endpoint is the ground
+constexpr int64_t kDenseNoV = INT64_MIN;
 
 // Device buffers a GEMM operand can live in.
 enum GemmBuf : int32_t { BUF_STORE = 0, BUF_LCC = 1, BUF_X = 2, BUF_T = 3, BUF_BT = 4, BUF_LUC = 5, BUF_G = 6, BUF_COUNT = 7 };
@@ -177,6 +204,14 @@ struct FactorPlan {
   int32_t max_btask_nwin = 0;
   std::vector<double> isd;          // per node D^{-1/2}
   int32_t max_lslot = 0;
+  // bottom subtrees (in processing order): record range, U_S = struct(root)
+  // (ascending, so depth descending) with its store offsets and depths, and
+  // the column-major B_S (column of the node at position p at
+  // sub_bbase + (p - sub_p0) * sub_K; only for sub_K <= kDenseMaxK)
+  std::vector<int32_t> sub_p0, sub_p1, sub_K, sub_ubeg, sub_udep, sub_unode;
+  std::vector<int64_t> sub_uoff, sub_bbase;
+  std::vector<int32_t> bpos_sub;    // per processing position: its subtree
+  int64_t b_elems = 0;
   // work statistics (FMAs)
   double f_top = 0, f_top_gemm = 0, f_top_inv = 0, f_bpre = 0, f_bottom_computed = 0;
   // where the coefficient -L_ki of each bottom-column entry (CSC position)
@@ -208,6 +243,15 @@ enum BQueryKind : int32_t { kQSlot = 0, kQInl0 = 1, kQInl1 = 2, kQGround = 3, kQ
 // The first kWinPerWave windows of the top store are zero; loads of windows
 // past a column's depth are pointed there.
 constexpr int64_t kStoreZeroBlock = (int64_t)kWin * kWinPerWave;
+
+// One dense work item: up to kDenseTile * (its tiles) bottom queries of one
+// subtree (dq_list[q0 .. q0 + nq)), rows [0, rows) of their sums.
+struct DItem {
+  int32_t sub;     // subtree
+  int32_t q0;      // first of the item's entries in dq_list
+  int32_t nq;      // queries
+  int32_t rows;    // a multiple of kWin * kWinPerWave
+};
 
 // A pair whose endpoints are not ancestor-related: both columns are read
 // whole after the sweep (top store, or the staging buffer for bottom nodes)
@@ -260,6 +304,22 @@ struct QueryPlan {
   // is not every chain, and only those chains' top steps need to run
   std::vector<char> chain_need;
   bool prune_top = false;
+  // dense rows above bottom subtrees. Which rows of a query the dense form
+  // covers depends only on the factor and on the query itself (not on the
+  // other queries of the plan), so a query gets the same bits in any plan.
+  // Work items grouped by class and tiles (items [dclass_ptr[x],
+  // dclass_ptr[x+1]) of group x), their bottom queries in dq_list; per bottom
+  // query the B_S column offsets of its endpoints (bq_bv: >= 0 a column of B,
+  // -1 - e for the e-th column of U_S, kDenseNoV for the ground) and the
+  // first window group its sweep sums (bq_g0 > 0: the dense sum covers the
+  // rows above it). A task's sweep starts past the dense rows when every one
+  // of its queries has a dense sum.
+  std::vector<DItem> ditems;
+  std::vector<int32_t> dq_list;
+  std::vector<int64_t> dclass_ptr;
+  std::vector<int64_t> bq_bu, bq_bv;
+  std::vector<int32_t> bq_g0;
+  bool dense = false;
   // columns requested for export (in request order): element offset in the
   // top store (export_staged 0) or in the staging buffer (1)
   std::vector<int64_t> export_off;
@@ -273,8 +333,11 @@ struct QueryPlan {
 // export_nodes (optional, permuted indices): columns the sweep must leave in
 // device memory for export (bottom columns are staged, top columns are in
 // the store); their locations land in export_off / export_staged.
+// dense: sum the rows above bottom subtrees in the dense form for the queries
+// that allow it.
 Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int32_t>& depth,
                         const FactorPlan& P, int64_t q, const int32_t* a, const int32_t* b, QueryPlan& Q,
-                        const AncestorTable* anc = nullptr, const std::vector<int32_t>* export_nodes = nullptr);
+                        const AncestorTable* anc = nullptr, const std::vector<int32_t>* export_nodes = nullptr,
+                        bool dense = false);
 
 }  // namespace peers

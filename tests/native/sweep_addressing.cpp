@@ -13,7 +13,9 @@
 // Usage: sweep_addressing GRAPH_FILE NUM_RANDOM_PAIRS SEED
 // GRAPH_FILE: int64 n, int64 m, int32 ground, int32 has_coords, then eu[m],
 // ev[m] (int32), w[m] (float64), coords[n*3] (float64) if has_coords.
+#include <algorithm>
 #include <cinttypes>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -47,7 +49,7 @@ constexpr uint32_t kBQ = sizeof(BQuery);
 struct Sizes {
   int64_t store_elems;   // elements the store allocation holds
   int64_t stage_elems;
-  int64_t nslots;
+  int64_t nslots;        // partial slots, then the dense sums
 };
 
 // The bottom sweep's read of a top-store column (32-bit byte offsets): the
@@ -70,7 +72,86 @@ void check_store_ref(const FactorPlan& P, const Sizes& Z, int64_t ref, int32_t t
 
 struct Marks {
   std::vector<uint8_t> part_written;
+  std::vector<uint8_t> dense_written;
 };
+
+// B_S of every subtree (upload): the records each wave walks, the columns of
+// B it writes, and the LDS path stack it indexes.
+void check_bxfer(const FactorPlan& P) {
+  const int32_t nsub = (int32_t)P.sub_p0.size();
+  REQUIRE((int32_t)P.sub_p1.size() == nsub && (int32_t)P.sub_K.size() == nsub && (int32_t)P.sub_bbase.size() == nsub,
+          "subtree tables");
+  for (int32_t s = 0; s < nsub; ++s) {
+    const int32_t K = P.sub_K[s], p0 = P.sub_p0[s], p1 = P.sub_p1[s];
+    REQUIRE(p0 < p1 && p1 <= (int32_t)P.bnode_node.size(), "subtree records [%d, %d)", p0, p1);
+    REQUIRE(P.sub_ubeg[s] >= 0 && (int64_t)P.sub_ubeg[s] + K <= (int64_t)P.sub_uoff.size(), "U_S range");
+    if (K == 0 || K > kDenseMaxK) continue;
+    REQUIRE(P.sub_bbase[s] >= 0 && P.sub_bbase[s] + (int64_t)K * (p1 - p0) <= P.b_elems, "B_S of subtree %d", s);
+    for (int32_t k = 1; k < K; ++k)
+      REQUIRE(P.sub_udep[P.sub_ubeg[s] + k] < P.sub_udep[P.sub_ubeg[s] + k - 1], "U_S depths descending");
+    for (int32_t p = p0; p < p1; ++p) {
+      REQUIRE(P.bpos_sub[p] == s, "position %d's subtree", p);
+      const BNode& b = P.bnode[p];
+      const int32_t nl = b.n_more & 0xffff, nt = (int32_t)((uint32_t)b.n_more >> 16);
+      REQUIRE(b.ent >= 0 && (int64_t)b.ent + nl + nt <= (int64_t)P.bent.size(), "overflow entries");
+    }
+  }
+}
+
+// Dense items: every read of B (forming w), U_S and the store, and every
+// dense sum written.
+void check_dense(const FactorPlan& P, const QueryPlan& Q, const Sizes& Z, const std::vector<int32_t>& depth,
+                 Marks& M) {
+  const int64_t nbq = Q.nbq();
+  M.dense_written.assign((size_t)std::max<int64_t>(nbq, 1), 0);
+  if (!Q.dense) {
+    REQUIRE(Q.ditems.empty(), "items without the dense flag");
+    return;
+  }
+  REQUIRE((int)Q.dclass_ptr.size() == kDenseGroups + 1 && Q.dclass_ptr[0] == 0 &&
+              Q.dclass_ptr[kDenseGroups] == (int64_t)Q.ditems.size(), "group ranges");
+  REQUIRE((int64_t)Q.bq_bu.size() == nbq + 1 && (int64_t)Q.bq_bv.size() == nbq + 1 && (int64_t)Q.bq_g0.size() == nbq + 1,
+          "per-query dense tables");
+  REQUIRE(kStoreZeroBlock >= kDenseTile, "zero block covers a row tile");
+  REQUIRE(Z.store_elems <= INT32_MAX, "dense sums address the store with 32-bit element offsets");
+  for (int x = 0; x < kDenseGroups; ++x) {
+    const int c = x / kDenseTileKinds, tiles = 1 << (x % kDenseTileKinds);
+    REQUIRE(Q.dclass_ptr[x + 1] == Q.dclass_ptr[x] || tiles <= dense_tiles(c), "group %d", x);
+    for (int64_t it = Q.dclass_ptr[x]; it < Q.dclass_ptr[x + 1]; ++it) {
+      const DItem& d = Q.ditems[it];
+      REQUIRE(d.sub >= 0 && d.sub < (int32_t)P.sub_p0.size(), "item subtree");
+      const int32_t K = P.sub_K[d.sub], ub = P.sub_ubeg[d.sub];
+      REQUIRE(K > 0 && K <= kDenseMaxK && dense_class(K) == c, "item class %d for |U_S| %d", c, K);
+      REQUIRE(d.nq >= 1 && d.nq <= kDenseTile * tiles, "item queries %d", d.nq);
+      const int32_t js0 = Q.bq_ptr[P.sub_p0[d.sub]], js1 = Q.bq_ptr[P.sub_p1[d.sub]];
+      REQUIRE(d.q0 >= 0 && (int64_t)d.q0 + d.nq <= (int64_t)Q.dq_list.size(), "item query list");
+      for (int32_t q = 0; q < d.nq; ++q)
+        REQUIRE(Q.dq_list[d.q0 + q] >= js0 && Q.dq_list[d.q0 + q] < js1, "item query outside the subtree");
+      const int32_t root = P.bnode_node[P.sub_p0[d.sub]];
+      REQUIRE(d.rows > 0 && d.rows % (kWin * NW) == 0 && d.rows <= depth[root] - 1, "item rows %d (root depth %d)",
+              d.rows, depth[root]);
+      // U_S columns: rows read are below min(rows, depth) of each column
+      for (int32_t k = 0; k < K; ++k) {
+        const int64_t off = P.sub_uoff[ub + k];
+        const int32_t rmax = std::min(d.rows, P.sub_udep[ub + k]);
+        REQUIRE(off >= kStoreZeroBlock && off + rmax <= Z.store_elems, "U_S column read");
+      }
+      for (int32_t q = 0; q < d.nq; ++q) {
+        const int64_t j = Q.dq_list[d.q0 + q];
+        REQUIRE(Q.bq_g0[j] * kWin * NW == d.rows, "first sweep window of query %" PRId64, j);
+        const int64_t bb = P.sub_bbase[d.sub], be = bb + (int64_t)K * (P.sub_p1[d.sub] - P.sub_p0[d.sub]);
+        REQUIRE(Q.bq_bu[j] >= bb && Q.bq_bu[j] + K <= be, "B column of u");
+        const int64_t bv = Q.bq_bv[j];
+        if (bv >= 0) REQUIRE(bv >= bb && bv + K <= be, "B column of v");
+        else if (bv != kDenseNoV) REQUIRE(-1 - bv < K, "U_S column of v");
+        const int64_t slot = Q.nslots + j;
+        REQUIRE(slot < Z.nslots, "dense sum slot %" PRId64 " of %" PRId64, slot, Z.nslots);
+        REQUIRE(!M.dense_written[j], "query %" PRId64 " in two dense items", j);
+        M.dense_written[j] = 1;
+      }
+    }
+  }
+}
 
 void check_bottom(const FactorPlan& P, const QueryPlan& Q, const Sizes& Z, bool wide, Marks& M, int64_t& node_waves) {
   const int64_t nbq = Q.nbq();
@@ -166,7 +247,10 @@ void check_finish(const FactorPlan& P, const QueryPlan& Q, const Sizes& Z, const
     if (b.kind == kQStage) continue;
     REQUIRE(b.out >= 0 && b.out < Q.q, "output index %" PRId64, b.out);
     const int32_t ng = (b.nwin + NW - 1) / NW;
-    for (int32_t g = 0; g < ng; ++g) {
+    const int32_t g0 = Q.dense ? Q.bq_g0[j] : 0;
+    REQUIRE(g0 >= 0 && g0 < ng, "first window group %d of %d", g0, ng);
+    if (g0 > 0) REQUIRE(M.dense_written[j], "reduction reads an unwritten dense sum %" PRId64, j);
+    for (int32_t g = g0; g < ng; ++g) {
       const int64_t slot = (int64_t)g * nbq + j;
       REQUIRE(slot < Q.nslots && M.part_written[slot], "reduction reads unwritten slot %" PRId64, slot);
     }
@@ -190,6 +274,91 @@ void check_finish(const FactorPlan& P, const QueryPlan& Q, const Sizes& Z, const
     REQUIRE(g.out >= 0 && g.out < Q.q, "non-ancestor output");
   }
   for (int64_t o : Q.zero_out) REQUIRE(o >= 0 && o < Q.q, "zero output");
+}
+
+// Values of the dense form on a small graph: for every query with a dense
+// sum, the rows above its subtree from B_S (formed from the records as the
+// upload kernel does) and w, plus its rows from the subtree on, against the
+// plain sum over all rows of its columns of Z (eq 11 on the factor, eq 12).
+void check_dense_values(const GraphHandle& G, const FactorPlan& P, const QueryPlan& Q, const int32_t* a,
+                        const int32_t* b, double& worst) {
+  if (!Q.dense) return;
+  const Symbolic& S = G.sym;
+  const int32_t N = S.N;
+  std::vector<std::vector<double>> z(N);
+  for (int32_t i = N - 1; i >= 0; --i) {
+    z[i].assign(S.depth[i], 0.0);
+    z[i][S.depth[i] - 1] = 1.0 / std::sqrt(G.num.D[i]);
+    for (int64_t p = S.colptr[i]; p < S.colptr[i + 1]; ++p) {
+      const int32_t k = S.rowidx[p];
+      for (int32_t d = 0; d < S.depth[k]; ++d) z[i][d] -= G.num.Lx[p] * z[k][d];
+    }
+  }
+  std::vector<double> store((size_t)std::max<int64_t>(P.store_elems, kWin), 0.0);
+  for (int32_t t = 0; t < P.ntop; ++t)
+    for (int32_t d = 0; d < P.top_depth[t]; ++d) store[P.top_off[t] + d] = z[P.top_node[t]][d];
+  // B_S per subtree
+  std::vector<double> B((size_t)std::max<int64_t>(P.b_elems, 1), 0.0);
+  for (size_t sb = 0; sb < P.sub_p0.size(); ++sb) {
+    const int32_t K = P.sub_K[sb];
+    if (K == 0 || K > kDenseMaxK) continue;
+    std::vector<double> st((size_t)kBottomMaxHeight * K, 0.0), acc(K);
+    for (int32_t p = P.sub_p0[sb]; p < P.sub_p1[sb]; ++p) {
+      const BNode& bn = P.bnode[p];
+      const int32_t ninl = (bn.slots >> kInlineCountShift) & 3;
+      const int32_t nl = bn.n_more & 0xffff, nt = (int32_t)((uint32_t)bn.n_more >> 16);
+      std::fill(acc.begin(), acc.end(), 0.0);
+      auto path = [&](int32_t code, double c) {
+        for (int32_t k = 0; k < K; ++k) acc[k] += c * st[(size_t)((code & kSlotMask) >> 1) * K + k];
+      };
+      auto top = [&](int64_t ref, double c) {
+        for (int32_t k = 0; k < K; ++k)
+          if ((int64_t)(uint32_t)ref * kWin == P.sub_uoff[P.sub_ubeg[sb] + k]) acc[k] += c;
+      };
+      for (int32_t e = 0; e < ninl; ++e) path(bn.slots >> (kSlotBits * e), bn.lc[e]);
+      for (int32_t e = 0; e < nl; ++e) path((int32_t)P.bent[bn.ent + e].ref, P.bent[bn.ent + e].coef);
+      top(bn.tref[0], bn.tc[0]);
+      top(bn.tref[1], bn.tc[1]);
+      for (int32_t e = 0; e < nt; ++e) top(P.bent[bn.ent + nl + e].ref, P.bent[bn.ent + nl + e].coef);
+      const int32_t own = ((bn.slots >> kOwnSlotShift) & kSlotMask) >> 1;
+      for (int32_t k = 0; k < K; ++k) {
+        st[(size_t)own * K + k] = acc[k];
+        B[P.sub_bbase[sb] + (int64_t)(p - P.sub_p0[sb]) * K + k] = acc[k];
+      }
+    }
+  }
+  for (const DItem& d : Q.ditems) {
+    const int32_t K = P.sub_K[d.sub], ub = P.sub_ubeg[d.sub];
+    for (int32_t c = 0; c < d.nq; ++c) {
+      const int64_t j = Q.dq_list[d.q0 + c];
+      std::vector<double> w(K);
+      for (int32_t k = 0; k < K; ++k) {
+        const int64_t bv = Q.bq_bv[j];
+        w[k] = B[Q.bq_bu[j] + k] - (bv >= 0 ? B[bv + k] : (bv != kDenseNoV && k == -1 - bv) ? 1.0 : 0.0);
+      }
+      double dense = 0.0;
+      for (int32_t row = 0; row < d.rows; ++row) {
+        double y = 0.0;
+        for (int32_t k = 0; k < K; ++k)
+          if (row < P.sub_udep[ub + k]) y += w[k] * store[P.sub_uoff[ub + k] + row];
+        dense += y * y;
+      }
+      const int64_t k = Q.bq[j].out;
+      const int32_t x = a[k], y = b[k];
+      const int32_t lo = x < 0 ? y : (y < 0 ? x : std::min(x, y));
+      const int32_t hi = (x < 0 || y < 0) ? -1 : std::max(x, y);
+      double rest = 0.0, full = 0.0;
+      for (int32_t r = 0; r < S.depth[lo]; ++r) {
+        const double zh = (hi >= 0 && r < S.depth[hi]) ? z[hi][r] : 0.0;
+        const double df = z[lo][r] - zh;
+        full += df * df;
+        if (r >= d.rows) rest += df * df;
+      }
+      const double err = std::fabs(dense + rest - full) / full;
+      worst = std::max(worst, err);
+      REQUIRE(err < 1e-11, "query %" PRId64 ": dense %.17g + sweep rows %.17g vs %.17g", j, dense, rest, full);
+    }
+  }
 }
 
 // Chain rows and the chain-level GEMM tiles of the top phase.
@@ -269,6 +438,17 @@ int main(int argc, char** argv) {
   const bool wide = P.store_wide;
   int64_t node_waves = 0;
   Marks M;
+  check_bxfer(P);
+  const bool small = n <= 20000;
+  double worst = 0.0;
+  auto run_plan = [&](const QueryPlan& Q, const int32_t* qa, const int32_t* qb) {
+    Z.stage_elems = std::max<int64_t>(Q.stage_elems, 1);
+    Z.nslots = Q.nslots + (Q.dense ? Q.nbq() : 0);
+    check_dense(P, Q, Z, G.sym.depth, M);
+    check_bottom(P, Q, Z, wide, M, node_waves);
+    check_finish(P, Q, Z, M);
+    if (small) check_dense_values(G, P, Q, qa, qb, worst);
+  };
   // 1. all edges, as the resident plan of an uploaded factor
   {
     std::vector<int32_t> a(m), b(m);
@@ -277,14 +457,15 @@ int main(int argc, char** argv) {
       b[e] = pidx(ev[e]);
       if (eu[e] == ev[e]) a[e] = b[e];
     }
-    QueryPlan Q;
-    st = build_query_plan(G.sym.first, G.sym.depth, P, m, a.data(), b.data(), Q);
-    if (st != OK) { std::fprintf(stderr, "edge plan: %d %s\n", st, last_error()); return 3; }
-    REQUIRE(Q.n_general == 0, "an edge whose endpoints are not ancestor-related");
-    Z.stage_elems = std::max<int64_t>(Q.stage_elems, 1);
-    Z.nslots = Q.nslots;
-    check_bottom(P, Q, Z, wide, M, node_waves);
-    check_finish(P, Q, Z, M);
+    for (int dense = 0; dense < 2; ++dense) {
+      QueryPlan Q;
+      st = build_query_plan(G.sym.first, G.sym.depth, P, m, a.data(), b.data(), Q, nullptr, nullptr, dense != 0);
+      if (st != OK) { std::fprintf(stderr, "edge plan: %d %s\n", st, last_error()); return 3; }
+      REQUIRE(Q.n_general == 0, "an edge whose endpoints are not ancestor-related");
+      run_plan(Q, a.data(), b.data());
+      if (dense) std::printf("edges: %zu dense items, %" PRId64 " sweep work items\n", Q.ditems.size(),
+                             (int64_t)Q.work_task.size());
+    }
   }
   // 2. random pairs (non-ancestor pairs stage bottom columns), ground pairs,
   //    self pairs and duplicated edges
@@ -304,15 +485,38 @@ int main(int argc, char** argv) {
       a.push_back(x == y ? pidx(y) : pidx(x));
       b.push_back(pidx(y));
     }
+    for (int dense = 0; dense < 2; ++dense) {
+      QueryPlan Q;
+      st = build_query_plan(G.sym.first, G.sym.depth, P, (int64_t)a.size(), a.data(), b.data(), Q, &anc, nullptr,
+                            dense != 0);
+      if (st != OK) { std::fprintf(stderr, "pair plan: %d %s\n", st, last_error()); return 3; }
+      run_plan(Q, a.data(), b.data());
+      std::printf("pairs: %" PRId64 " non-ancestor, %" PRId64 " staged elements, %zu dense items\n", Q.n_general,
+                  Q.stage_elems, Q.ditems.size());
+    }
+    // a few edges: a plan that reads only some top chains
+    {
+      std::vector<int32_t> fa, fb;
+      for (int64_t e = 0; e < std::min<int64_t>(m, 64); ++e) {
+        fa.push_back(pidx(eu[e * (m / std::min<int64_t>(m, 64))]));
+        fb.push_back(pidx(ev[e * (m / std::min<int64_t>(m, 64))]));
+        if (fa.back() == fb.back()) fa.back() = fb.back();
+      }
+      QueryPlan Q;
+      st = build_query_plan(G.sym.first, G.sym.depth, P, (int64_t)fa.size(), fa.data(), fb.data(), Q, &anc, nullptr, true);
+      if (st != OK) { std::fprintf(stderr, "few-pair plan: %d %s\n", st, last_error()); return 3; }
+      run_plan(Q, fa.data(), fb.data());
+      std::printf("few pairs: %s top, %zu dense items\n", Q.prune_top ? "pruned" : "whole", Q.ditems.size());
+    }
+    // every node with the ground
+    std::vector<int32_t> ga(n), gb(n, -1);
+    for (int64_t x = 0; x < n; ++x) ga[x] = pidx((int32_t)x);
     QueryPlan Q;
-    st = build_query_plan(G.sym.first, G.sym.depth, P, (int64_t)a.size(), a.data(), b.data(), Q, &anc);
-    if (st != OK) { std::fprintf(stderr, "pair plan: %d %s\n", st, last_error()); return 3; }
-    Z.stage_elems = std::max<int64_t>(Q.stage_elems, 1);
-    Z.nslots = Q.nslots;
-    check_bottom(P, Q, Z, wide, M, node_waves);
-    check_finish(P, Q, Z, M);
-    std::printf("pairs: %" PRId64 " non-ancestor, %" PRId64 " staged elements\n", Q.n_general, Q.stage_elems);
+    st = build_query_plan(G.sym.first, G.sym.depth, P, n, ga.data(), gb.data(), Q, &anc, nullptr, true);
+    if (st != OK) { std::fprintf(stderr, "ground plan: %d %s\n", st, last_error()); return 3; }
+    run_plan(Q, ga.data(), gb.data());
   }
+  if (small) std::printf("dense values: worst relative difference %.3g\n", worst);
   check_top(P, Z);
   std::printf("ok: n %" PRId64 " m %" PRId64 " height %d store %.3f GB (%s offsets) node-waves %" PRId64
               " checks %" PRId64 "\n",

@@ -5,8 +5,12 @@ planner on a graph and replays the address arithmetic of every sweep kernel
 in the integer widths the kernels use: the bottom sweep's 32-bit record,
 query-record and top-store byte offsets, staging writes, partial-slot
 indices (and that the ordered reduction reads only slots the sweep wrote),
-the top-node and non-ancestor pair reads, and the chain-level GEMM tiles'
-gathered columns and output tiles. Each access is checked against the size of
+the top-node and non-ancestor pair reads, the chain-level GEMM tiles'
+gathered columns and output tiles, and the dense sums above bottom subtrees
+(the B_S records each upload wave walks, every U_S column and B column read,
+every dense sum written and read back). On graphs up to 20,000 nodes it also
+checks the values of the dense form: the rows above a query's subtree from
+B_S and w plus its sweep rows against the plain sum over every row. Each access is checked against the size of
 its buffer. The program is built with AddressSanitizer and
 UndefinedBehaviorSanitizer, so the host preparation (ingest, ordering,
 symbolic and numeric factorization, plans) runs under them at the same time.
