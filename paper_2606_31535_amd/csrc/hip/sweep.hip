@@ -811,8 +811,9 @@ __device__ __forceinline__ void dense_body(const SweepArgs& A, const QueryArgs& 
 #pragma unroll
       for (int i = 0; i < RT; ++i) {
         const int32_t row = d0 + 16 * i + r;
-        // unconditional (a load on a branch would make the join wait for it)
-        a[s][i] = z[sd[s] > d0 && row < ud[s] ? uo[s] + row : r];
+        // unconditional, also past the last block (a load on a branch would
+        // make the join wait for it); rows past the item read zeros
+        a[s][i] = z[sd[s] > d0 && row < ud[s] && row < d.rows ? uo[s] + row : r];
       }
   };
   // the k-groups needed for rows from d0 on (a prefix), as a constant per
@@ -846,13 +847,13 @@ __device__ __forceinline__ void dense_body(const SweepArgs& A, const QueryArgs& 
   };
   double a0[KS][RT], a1[KS][RT];
   int32_t d0 = wave * 16 * RT;
-  if (d0 < d.rows) load(d0, a0);
+  load(d0, a0);
   while (d0 < d.rows) {
-    if (d0 + kStep < d.rows) load(d0 + kStep, a1);
+    load(d0 + kStep, a1);
     block(d0, a0);
     d0 += kStep;
     if (d0 >= d.rows) break;
-    if (d0 + kStep < d.rows) load(d0 + kStep, a0);
+    load(d0 + kStep, a0);
     block(d0, a1);
     d0 += kStep;
   }
