@@ -101,6 +101,10 @@ static void pack_query_plan(const QueryPlan& Q, DeviceQueryPlan& D, Packer& pk) 
   }
   D.dense = Q.dense;
   D.dclass_ptr = Q.dclass_ptr;
+  D.dgroup_cost.assign(Q.dense ? kDenseGroups : 0, 0.0);
+  for (int x = 0; Q.dense && x < kDenseGroups; ++x)
+    for (int64_t i = Q.dclass_ptr[x]; i < Q.dclass_ptr[x + 1]; ++i)
+      D.dgroup_cost[x] += (double)Q.ditems[i].rows * (1 << (x % kDenseTileKinds)) * dense_steps(x / kDenseTileKinds);
   D.args.nbq = Q.nbq();
   D.args.ntq = (int64_t)Q.tq_out.size();
   D.args.nzero = (int64_t)Q.zero_out.size();
@@ -220,10 +224,41 @@ Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t
   if (profile) HIP_TRY(hipEventRecord(F.ev[1], s));
   int32_t bl = 0;
   if (D.dense) {
-    HIP_TRY(launch_dense(F.sweep, q, D.dclass_ptr.data(), s));
     for (int c = 0; c < kDenseGroups; ++c) bl += D.dclass_ptr[c + 1] > D.dclass_ptr[c] ? 1 : 0;
+    if (work) {
+      // caller workspace (a caller that may capture the stream): one stream
+      HIP_TRY(launch_dense(F.sweep, q, D.dclass_ptr.data(), -1, s));
+    } else {
+      // the dense groups on side streams, largest first to the least loaded,
+      // beside the sweep on s (they write disjoint sums; the finish step on s
+      // waits for all of them)
+      if (!F.fork_ev) {
+        HIP_TRY(hipEventCreateWithFlags(&F.fork_ev, hipEventDisableTiming));
+        for (int k = 0; k < FactorHandle::kSideStreams; ++k) {
+          HIP_TRY(hipStreamCreateWithFlags(&F.side[k], hipStreamNonBlocking));
+          HIP_TRY(hipEventCreateWithFlags(&F.join_ev[k], hipEventDisableTiming));
+        }
+      }
+      HIP_TRY(hipEventRecord(F.fork_ev, s));
+      std::vector<int> ord;
+      for (int x = 0; x < kDenseGroups; ++x)
+        if (D.dclass_ptr[x + 1] > D.dclass_ptr[x]) ord.push_back(x);
+      std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return D.dgroup_cost[x] > D.dgroup_cost[y]; });
+      double load[FactorHandle::kSideStreams] = {0, 0, 0};
+      for (int k = 0; k < FactorHandle::kSideStreams; ++k) HIP_TRY(hipStreamWaitEvent(F.side[k], F.fork_ev, 0));
+      for (int x : ord) {
+        int k = 0;
+        for (int j = 1; j < FactorHandle::kSideStreams; ++j)
+          if (load[j] < load[k]) k = j;
+        load[k] += D.dgroup_cost[x];
+        HIP_TRY(launch_dense(F.sweep, q, D.dclass_ptr.data(), x, F.side[k]));
+      }
+      for (int k = 0; k < FactorHandle::kSideStreams; ++k) HIP_TRY(hipEventRecord(F.join_ev[k], F.side[k]));
+    }
   }
   HIP_TRY(launch_bottom(F.sweep, q, s));
+  if (D.dense && !work)
+    for (int k = 0; k < FactorHandle::kSideStreams; ++k) HIP_TRY(hipStreamWaitEvent(s, F.join_ev[k], 0));
   F.bottom_launches = bl + (q.nwork > 0 ? 1 : 0);
   if (profile) HIP_TRY(hipEventRecord(F.ev[2], s));
   HIP_TRY(launch_finish(F.sweep, q, s));
@@ -540,6 +575,11 @@ void peers_factor_release(peers_factor f) {
   if (F->bbuf) (void)hipFree(F->bbuf);
   for (auto& e : F->ev)
     if (e) (void)hipEventDestroy(e);
+  for (int k = 0; k < FactorHandle::kSideStreams; ++k) {
+    if (F->side[k]) (void)hipStreamDestroy(F->side[k]);
+    if (F->join_ev[k]) (void)hipEventDestroy(F->join_ev[k]);
+  }
+  if (F->fork_ev) (void)hipEventDestroy(F->fork_ev);
   if (F->part) (void)hipFree(F->part);
   if (F->res) (void)hipFree(F->res);
   if (F->stage) (void)hipFree(F->stage);

@@ -42,9 +42,11 @@ struct DeviceQueryPlan {
   std::vector<int32_t> work_task, work_win;  // host copies (batch schedules)
   std::vector<char> chain_need;              // top chains the plan reads
   bool prune_top = false;
-  // dense rows above bottom subtrees: item ranges per class (host)
+  // dense rows above bottom subtrees: item ranges per group and each
+  // group's matrix-core work (MFMA count estimate) (host)
   bool dense = false;
   std::vector<int64_t> dclass_ptr;
+  std::vector<double> dgroup_cost;
   // grouped-launch image of a pruned plan on its own factor (owned)
   void* layout_mem = nullptr;
   uint64_t layout_bytes = 0;
@@ -82,6 +84,12 @@ struct FactorHandle {
   std::atomic<int64_t> server_refs{0};
   // per-phase timing of the last profiled sweep
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // side streams of the bottom step (dense groups beside the sweep), made
+  // at first use; fork and join events
+  static constexpr int kSideStreams = 3;
+  hipStream_t side[kSideStreams] = {nullptr, nullptr, nullptr};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kSideStreams] = {nullptr, nullptr, nullptr};
   bool timed = false;
   int32_t top_launches = 0, bottom_launches = 0;
   double top_flops = 0, bottom_flops = 0, top_bytes = 0, bottom_bytes = 0, finish_flops = 0;

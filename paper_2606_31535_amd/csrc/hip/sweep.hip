@@ -1221,10 +1221,10 @@ hipError_t launch_bxfer(const SweepArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_dense(const SweepArgs& a, const QueryArgs& q, const int64_t* dclass_ptr, hipStream_t s) {
+hipError_t launch_dense(const SweepArgs& a, const QueryArgs& q, const int64_t* dclass_ptr, int only, hipStream_t s) {
   for (int x = 0; x < kDenseGroups; ++x) {
     const int64_t i0 = dclass_ptr[x], n = dclass_ptr[x + 1] - dclass_ptr[x];
-    if (n <= 0) continue;
+    if (n <= 0 || (only >= 0 && x != only)) continue;
     dense_group<0>(x, [&](auto X) {
       hipLaunchKernelGGL(dense_kernel<decltype(X)::value>, dim3((unsigned)n), dim3(64 * kBottomWaves), 0, s, a, q, i0);
     });

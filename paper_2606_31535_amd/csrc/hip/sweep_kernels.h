@@ -127,8 +127,9 @@ hipError_t launch_chain_rows(const SweepArgs& a, int32_t ntop, hipStream_t s);
 hipError_t launch_bottom(const SweepArgs& a, const QueryArgs& q, hipStream_t s);
 // B_S of every subtree with |U_S| <= kDenseMaxK (upload, after the records hold the factor)
 hipError_t launch_bxfer(const SweepArgs& a, hipStream_t s);
-// the dense sums of every item (dclass_ptr: the plan's item ranges per class, host memory)
-hipError_t launch_dense(const SweepArgs& a, const QueryArgs& q, const int64_t* dclass_ptr, hipStream_t s);
+// the dense sums of the items of group x, or of every group for x < 0
+// (dclass_ptr: the plan's item ranges per group, host memory)
+hipError_t launch_dense(const SweepArgs& a, const QueryArgs& q, const int64_t* dclass_ptr, int x, hipStream_t s);
 hipError_t launch_finish(const SweepArgs& a, const QueryArgs& q, hipStream_t s);
 
 }  // namespace peers
