@@ -83,6 +83,8 @@ typedef struct {
                                  t_numeric is 0; afterwards t_numeric is the device time.
                                  Uploads of such a graph from several threads run one at a
                                  time; the first forms the factor, the others reuse it */
+  int32_t sweep_only;         /* 1: the sweep sums every row of every bottom query (no dense
+                                 sums of the rows above bottom subtrees); for tests */
 } peers_graph_opts;
 
 typedef struct {

@@ -38,7 +38,8 @@ class PeersError(RuntimeError):
 class peers_graph_opts(C.Structure):
     _fields_ = [("ordering", C.c_int32), ("coords", C.POINTER(C.c_double)),
                 ("given_order", C.POINTER(C.c_int32)), ("threads", C.c_int32), ("leaf_size", C.c_int32),
-                ("store_offsets_64", C.c_int32), ("numeric_on_device", C.c_int32)]
+                ("store_offsets_64", C.c_int32), ("numeric_on_device", C.c_int32),
+                ("sweep_only", C.c_int32)]
 
 
 class peers_graph_stats(C.Structure):
@@ -253,7 +254,8 @@ def _factor_edges(f):
 # --------------------------------------------------------------------------- graph
 
 def peers_graph_create(n, eu, ev, w, ground=0, coords=None, ordering=PEERS_ORDER_AUTO,
-                       given_order=None, threads=0, leaf_size=0, store_offsets_64=False, numeric_on_device=False):
+                       given_order=None, threads=0, leaf_size=0, store_offsets_64=False, numeric_on_device=False,
+                       sweep_only=False):
     eu, ev, w = _i32(eu), _i32(ev), _f64(w)
     if not (eu.shape == ev.shape == w.shape):
         raise ValueError("eu, ev, w must have the same length")
@@ -272,6 +274,7 @@ def peers_graph_create(n, eu, ev, w, ground=0, coords=None, ordering=PEERS_ORDER
     opts.leaf_size = leaf_size
     opts.store_offsets_64 = 1 if store_offsets_64 else 0
     opts.numeric_on_device = 1 if numeric_on_device else 0
+    opts.sweep_only = 1 if sweep_only else 0
     h = _vp()
     _check(lib().peers_graph_create(int(n), int(eu.shape[0]), _ptr(eu, C.c_int32), _ptr(ev, C.c_int32),
                                     _ptr(w, C.c_double), int(ground), C.byref(opts), C.byref(h)),

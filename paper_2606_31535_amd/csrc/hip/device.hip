@@ -268,7 +268,7 @@ Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t
 
 Status build_query_plan_handle(const FactorHandle& F, int64_t q, const int32_t* a, const int32_t* b,
                                QueryPlan& Q, bool dense) {
-  return build_query_plan(F.first, F.depth, *F.plan, q, a, b, Q, &F.anc, nullptr, dense);
+  return build_query_plan(F.first, F.depth, *F.plan, q, a, b, Q, &F.anc, nullptr, dense && F.dense_ok);
 }
 
 Status plan_for_pairs(FactorHandle& F, int64_t q, const int32_t* u, const int32_t* v, DeviceQueryPlan& DQ,
@@ -367,6 +367,7 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
   F->iperm = G.sym.iperm;
   F->first = G.sym.first;
   F->depth = G.sym.depth;
+  F->dense_ok = !G.sweep_only;
   F->plan.reset(new FactorPlan());
   double tp = now_s();
   // a graph created with numeric_on_device has no factor values yet: the
@@ -394,7 +395,7 @@ peers_status peers_factor_upload(peers_device d, peers_graph g, void* hip_stream
       if (G.eu[e] == G.ev[e]) a[e] = b[e];  // self-loop: R = 0
     }
     QueryPlan Q;
-    st = build_query_plan(F->first, F->depth, P, F->m, a.data(), b.data(), Q, nullptr, nullptr, true);
+    st = build_query_plan(F->first, F->depth, P, F->m, a.data(), b.data(), Q, nullptr, nullptr, F->dense_ok);
     if (st != OK) return (peers_status)st;
     if (Q.n_general) { set_error("internal: an edge whose endpoints are not etree-related"); return PEERS_E_INTERNAL; }
     F->t_edge_plan = now_s() - tp;

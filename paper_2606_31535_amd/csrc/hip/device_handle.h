@@ -62,6 +62,7 @@ struct FactorHandle {
   std::vector<int32_t> first, depth;
   AncestorTable anc;  // lowest common ancestors for non-ancestor pairs
   std::unique_ptr<FactorPlan> plan;
+  bool dense_ok = true;  // plans may use the dense sums (not with peers_graph_opts::sweep_only)
   SweepArgs sweep{};
   GemmArgs gemm{};
   void* base = nullptr;

@@ -19,6 +19,7 @@ Status build_graph(int64_t n, int64_t m, const int32_t* eu, const int32_t* ev, c
   std::vector<int32_t> order;
   const int leaf = o.leaf_size > 0 ? o.leaf_size : 64;
   G.store64 = o.store_offsets_64 != 0;
+  G.sweep_only = o.sweep_only != 0;
   int ordering = o.ordering;
   if (ordering == PEERS_ORDER_AUTO) ordering = o.coords ? PEERS_ORDER_COORD : PEERS_ORDER_GRAPH;
   if (ordering == PEERS_ORDER_COORD) {

@@ -16,6 +16,7 @@ struct GraphHandle {
   peers_graph_stats stats{};
   std::vector<int32_t> eu, ev;  // the input edge list (all-edge queries in input order)
   bool store64 = false;         // peers_graph_opts::store_offsets_64
+  bool sweep_only = false;      // peers_graph_opts::sweep_only
   // numeric factor formed on the device by the first upload (num is filled
   // then, from the device's result); num_mu orders that upload against other
   // uploads of the graph and against readers of num and stats
