@@ -229,36 +229,37 @@ Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t
       // caller workspace (a caller that may capture the stream): one stream
       HIP_TRY(launch_dense(F.sweep, q, D.dclass_ptr.data(), -1, s));
     } else {
-      // the dense groups on side streams, largest first to the least loaded,
-      // beside the sweep on s (they write disjoint sums; the finish step on s
-      // waits for all of them)
-      if (!F.fork_ev) {
-        HIP_TRY(hipEventCreateWithFlags(&F.fork_ev, hipEventDisableTiming));
-        for (int k = 0; k < FactorHandle::kSideStreams; ++k) {
-          HIP_TRY(hipStreamCreateWithFlags(&F.side[k], hipStreamNonBlocking));
-          HIP_TRY(hipEventCreateWithFlags(&F.join_ev[k], hipEventDisableTiming));
-        }
-      }
-      HIP_TRY(hipEventRecord(F.fork_ev, s));
+      // the dense groups on the device's side streams, largest first to the
+      // least loaded, beside the sweep on s (they write disjoint sums; the
+      // finish step on s waits for all of them)
+      DeviceHandle& V = *F.dev;
+      std::lock_guard<std::mutex> g(V.side_mu);
+      constexpr int NS = DeviceHandle::kSideStreams;
+      HIP_TRY(hipEventRecord(V.fork_ev, s));
       std::vector<int> ord;
       for (int x = 0; x < kDenseGroups; ++x)
         if (D.dclass_ptr[x + 1] > D.dclass_ptr[x]) ord.push_back(x);
       std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return D.dgroup_cost[x] > D.dgroup_cost[y]; });
-      double load[FactorHandle::kSideStreams] = {0, 0, 0};
-      for (int k = 0; k < FactorHandle::kSideStreams; ++k) HIP_TRY(hipStreamWaitEvent(F.side[k], F.fork_ev, 0));
+      double load[NS] = {0, 0, 0};
+      for (int k = 0; k < NS; ++k) HIP_TRY(hipStreamWaitEvent(V.side[k], V.fork_ev, 0));
       for (int x : ord) {
         int k = 0;
-        for (int j = 1; j < FactorHandle::kSideStreams; ++j)
+        for (int j = 1; j < NS; ++j)
           if (load[j] < load[k]) k = j;
         load[k] += D.dgroup_cost[x];
-        HIP_TRY(launch_dense(F.sweep, q, D.dclass_ptr.data(), x, F.side[k]));
+        HIP_TRY(launch_dense(F.sweep, q, D.dclass_ptr.data(), x, V.side[k]));
       }
-      for (int k = 0; k < FactorHandle::kSideStreams; ++k) HIP_TRY(hipEventRecord(F.join_ev[k], F.side[k]));
+      for (int k = 0; k < NS; ++k) HIP_TRY(hipEventRecord(V.join_ev[k], V.side[k]));
+      HIP_TRY(launch_bottom(F.sweep, q, s));
+      for (int k = 0; k < NS; ++k) HIP_TRY(hipStreamWaitEvent(s, V.join_ev[k], 0));
+      F.bottom_launches = bl + (q.nwork > 0 ? 1 : 0);
+      if (profile) HIP_TRY(hipEventRecord(F.ev[2], s));
+      HIP_TRY(launch_finish(F.sweep, q, s));
+      if (profile) HIP_TRY(hipEventRecord(F.ev[3], s));
+      return OK;
     }
   }
   HIP_TRY(launch_bottom(F.sweep, q, s));
-  if (D.dense && !work)
-    for (int k = 0; k < FactorHandle::kSideStreams; ++k) HIP_TRY(hipStreamWaitEvent(s, F.join_ev[k], 0));
   F.bottom_launches = bl + (q.nwork > 0 ? 1 : 0);
   if (profile) HIP_TRY(hipEventRecord(F.ev[2], s));
   HIP_TRY(launch_finish(F.sweep, q, s));
@@ -313,6 +314,15 @@ peers_status peers_device_open(int32_t ordinal, uint64_t hbm_budget_bytes, peers
     D->cus = 256;
   D->total = total;
   D->budget = hbm_budget_bytes ? std::min<uint64_t>(hbm_budget_bytes, total) : (uint64_t)(0.9 * (double)total);
+  e = hipEventCreateWithFlags(&D->fork_ev, hipEventDisableTiming);
+  for (int k = 0; k < DeviceHandle::kSideStreams && e == hipSuccess; ++k) {
+    e = hipStreamCreateWithFlags(&D->side[k], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&D->join_ev[k], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    peers_device_close(reinterpret_cast<peers_device>(D));
+    return (peers_status)hip_fail(e, "side streams");
+  }
   *out = reinterpret_cast<peers_device>(D);
   return PEERS_OK;
 }
@@ -321,6 +331,12 @@ void peers_device_close(peers_device d) {
   if (!d) return;
   auto* D = reinterpret_cast<DeviceHandle*>(d);
   batch_cache_free(*D);
+  (void)hipSetDevice(D->ordinal);
+  for (int k = 0; k < DeviceHandle::kSideStreams; ++k) {
+    if (D->side[k]) (void)hipStreamDestroy(D->side[k]);
+    if (D->join_ev[k]) (void)hipEventDestroy(D->join_ev[k]);
+  }
+  if (D->fork_ev) (void)hipEventDestroy(D->fork_ev);
   delete D;
 }
 
@@ -576,11 +592,7 @@ void peers_factor_release(peers_factor f) {
   if (F->bbuf) (void)hipFree(F->bbuf);
   for (auto& e : F->ev)
     if (e) (void)hipEventDestroy(e);
-  for (int k = 0; k < FactorHandle::kSideStreams; ++k) {
-    if (F->side[k]) (void)hipStreamDestroy(F->side[k]);
-    if (F->join_ev[k]) (void)hipEventDestroy(F->join_ev[k]);
-  }
-  if (F->fork_ev) (void)hipEventDestroy(F->fork_ev);
+
   if (F->part) (void)hipFree(F->part);
   if (F->res) (void)hipFree(F->res);
   if (F->stage) (void)hipFree(F->stage);

@@ -27,6 +27,14 @@ struct DeviceHandle {
   void release(uint64_t bytes);
   BatchCache* batches = nullptr;  // guarded by batch_mu
   std::mutex batch_mu;
+  // side streams of the bottom step (dense groups beside the sweep) with
+  // their fork and join events, made when the device is opened; side_mu is
+  // held while one sweep enqueues its fork, side launches and join
+  static constexpr int kSideStreams = 3;
+  hipStream_t side[kSideStreams] = {nullptr, nullptr, nullptr};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kSideStreams] = {nullptr, nullptr, nullptr};
+  std::mutex side_mu;
 };
 
 void batch_cache_free(DeviceHandle& D);
@@ -85,12 +93,6 @@ struct FactorHandle {
   std::atomic<int64_t> server_refs{0};
   // per-phase timing of the last profiled sweep
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  // side streams of the bottom step (dense groups beside the sweep), made
-  // at first use; fork and join events
-  static constexpr int kSideStreams = 3;
-  hipStream_t side[kSideStreams] = {nullptr, nullptr, nullptr};
-  hipEvent_t fork_ev = nullptr;
-  hipEvent_t join_ev[kSideStreams] = {nullptr, nullptr, nullptr};
   bool timed = false;
   int32_t top_launches = 0, bottom_launches = 0;
   double top_flops = 0, bottom_flops = 0, top_bytes = 0, bottom_bytes = 0, finish_flops = 0;
