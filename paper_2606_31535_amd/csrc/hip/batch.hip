@@ -97,8 +97,8 @@ void batch_layout(const DeviceHandle& D, const std::vector<BatchEntry>& E, Batch
           if (need(i, P.prob_chain[P.ntasks[t].prob])) items.push_back(GroupItem{i, 0, t});
     });
   }
-  // dense rows above bottom subtrees: the items of each class
-  for (int c = 0; c < kDenseGroups; ++c)
+  // dense rows above bottom subtrees: the items of each group
+  for (int c = 0; c < kDenseAllGroups; ++c)
     stage(GK_DENSE + c, [&](int32_t i) {
       const DeviceQueryPlan& Q = *E[i].plan;
       if (Q.dense) range(i, Q.dclass_ptr[c], Q.dclass_ptr[c + 1]);

@@ -75,6 +75,16 @@ void DeviceHandle::release(uint64_t bytes) {
   used = bytes > used ? 0 : used - bytes;
 }
 
+// Matrix-core work of each dense group (rows x column tiles x k-groups).
+void dense_costs(const QueryPlan& Q, std::vector<double>& group) {
+  group.assign(Q.dense ? kDenseAllGroups : 0, 0.0);
+  for (int x = 0; Q.dense && x < kDenseAllGroups; ++x) {
+    const int cls = x < kDenseGroups ? x / kDenseTileKinds : x - kDenseGroups;
+    const int tiles = x < kDenseGroups ? 1 << (x % kDenseTileKinds) : 1;
+    for (int64_t i = Q.dclass_ptr[x]; i < Q.dclass_ptr[x + 1]; ++i) group[x] += (double)Q.ditems[i].rows * tiles * dense_steps(cls);
+  }
+}
+
 static void pack_query_plan(const QueryPlan& Q, DeviceQueryPlan& D, Packer& pk) {
   pk.add(Q.work_task, &D.args.work_task);
   pk.add(Q.work_win, &D.args.work_win);
@@ -101,10 +111,7 @@ static void pack_query_plan(const QueryPlan& Q, DeviceQueryPlan& D, Packer& pk) 
   }
   D.dense = Q.dense;
   D.dclass_ptr = Q.dclass_ptr;
-  D.dgroup_cost.assign(Q.dense ? kDenseGroups : 0, 0.0);
-  for (int x = 0; Q.dense && x < kDenseGroups; ++x)
-    for (int64_t i = Q.dclass_ptr[x]; i < Q.dclass_ptr[x + 1]; ++i)
-      D.dgroup_cost[x] += (double)Q.ditems[i].rows * (1 << (x % kDenseTileKinds)) * dense_steps(x / kDenseTileKinds);
+  dense_costs(Q, D.dgroup_cost);
   D.args.nbq = Q.nbq();
   D.args.ntq = (int64_t)Q.tq_out.size();
   D.args.nzero = (int64_t)Q.zero_out.size();
@@ -224,7 +231,7 @@ Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t
   if (profile) HIP_TRY(hipEventRecord(F.ev[1], s));
   int32_t bl = 0;
   if (D.dense) {
-    for (int c = 0; c < kDenseGroups; ++c) bl += D.dclass_ptr[c + 1] > D.dclass_ptr[c] ? 1 : 0;
+    for (int c = 0; c < kDenseAllGroups; ++c) bl += D.dclass_ptr[c + 1] > D.dclass_ptr[c] ? 1 : 0;
     if (work) {
       // caller workspace (a caller that may capture the stream): one stream
       HIP_TRY(launch_dense(F.sweep, q, D.dclass_ptr.data(), -1, s));
@@ -237,7 +244,7 @@ Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t
       constexpr int NS = DeviceHandle::kSideStreams;
       HIP_TRY(hipEventRecord(V.fork_ev, s));
       std::vector<int> ord;
-      for (int x = 0; x < kDenseGroups; ++x)
+      for (int x = 0; x < kDenseAllGroups; ++x)
         if (D.dclass_ptr[x + 1] > D.dclass_ptr[x]) ord.push_back(x);
       std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return D.dgroup_cost[x] > D.dgroup_cost[y]; });
       double load[NS] = {0, 0, 0};

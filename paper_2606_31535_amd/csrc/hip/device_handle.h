@@ -113,6 +113,8 @@ uint64_t query_plan_bytes(const QueryPlan& Q);
 Status upload_query_plan_to(const QueryPlan& Q, DeviceQueryPlan& D, void* mem, hipStream_t s);
 void free_query_plan(FactorHandle& F, DeviceQueryPlan& D);
 Status ensure_workspace(FactorHandle& F, int64_t nslots, int64_t nres, int64_t nstage);
+// Matrix-core work of a plan's dense groups (host estimates for scheduling).
+void dense_costs(const QueryPlan& Q, std::vector<double>& group);
 // Workspace of one sweep given by the caller instead of the factor's own
 // (partial slots, staging, and the launch layout of a pruned sweep).
 struct SweepWork {

@@ -614,7 +614,8 @@ __device__ __forceinline__ void bottom_body(const SweepArgs& A, const QueryArgs&
             // one side of a non-ancestor pair (its sum below is never read);
             // staged columns span whole window groups, so every window of the
             // group is written (zeros past the node's depth)
-            if (kind == kQStage) {
+            // (the windows below the entry's first one are the dense form's)
+            if (kind == kQStage && t0 >= (int32_t)load_uniform(&bq_at(qo)->out)) {
 #pragma unroll
               for (int v = 0; v < NW; ++v) Q.stage[h + (int64_t)(t0 + v) * kWin + lane] = acc[v];
             }
@@ -768,11 +769,14 @@ struct DenseLds {
   double red[kBottomWaves][1 << (GRP % kDenseTileKinds)][kDenseTile];
 };
 
-// GRP = class * kDenseTileKinds + log2(column tiles)
-template <int GRP>
+// GRP = class * kDenseTileKinds + log2(column tiles). STAGE: the item's
+// columns are staged bottom columns (one tile): each product is written to
+// the staging buffer at the rows it covers instead of squared.
+template <int GRP, bool STAGE>
 __device__ __forceinline__ void dense_body(const SweepArgs& A, const QueryArgs& Q, int64_t it, DenseLds<GRP>& L) {
   constexpr int CLS = GRP / kDenseTileKinds;
   constexpr int KS = dense_steps(CLS), G = 1 << (GRP % kDenseTileKinds), RT = dense_rt(CLS);
+  static_assert(!STAGE || G == 1, "staging items hold one column tile");
   const int tid = threadIdx.x, lane = tid & 63, kq = lane >> 4, r = lane & 15;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const DItem d = load_struct(Q.ditems + it);
@@ -803,6 +807,9 @@ __device__ __forceinline__ void dense_body(const SweepArgs& A, const QueryArgs& 
   double sq[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) sq[g] = 0.0;
+  // staging: this lane's column (its query's staging offset), -1 past the queries
+  int64_t sbase = -1;
+  if (STAGE && r < d.nq) sbase = Q.bq[Q.dq_list[d.q0 + r]].hiref;
   // row blocks of this wave, the next one's loads in flight during each
   constexpr int32_t kStep = kBottomWaves * 16 * RT;
   auto load = [&](int32_t d0, double (&a)[KS][RT]) {
@@ -824,7 +831,7 @@ __device__ __forceinline__ void dense_body(const SweepArgs& A, const QueryArgs& 
     for (int s = 0; s < KS; ++s) n += sd[s] > d0 ? 1 : 0;
     return n;
   };
-  auto block_n = [&](auto NS, const double (&a)[KS][RT]) {
+  auto block_n = [&](auto NS, int32_t d0, const double (&a)[KS][RT]) {
     constexpr int N = decltype(NS)::value;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -833,8 +840,17 @@ __device__ __forceinline__ void dense_body(const SweepArgs& A, const QueryArgs& 
         f64x4 c = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int s = 0; s < N; ++s) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s][i], L.w[g][s][lane], c, 0, 0, 0);
+        if constexpr (STAGE) {
+          // C lane l, element e: row 4e + l/16 of the tile, column l%16
 #pragma unroll
-        for (int e = 0; e < 4; ++e) sq[g] = fma(c[e], c[e], sq[g]);
+          for (int e = 0; e < 4; ++e) {
+            const int32_t row = d0 + 16 * i + 4 * e + kq;
+            if (sbase >= 0 && row < d.rows) Q.stage[sbase + row] = c[e];
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) sq[g] = fma(c[e], c[e], sq[g]);
+        }
       }
       // one column tile's products at a time (their accumulators stay few)
       __builtin_amdgcn_sched_barrier(0);
@@ -842,8 +858,8 @@ __device__ __forceinline__ void dense_body(const SweepArgs& A, const QueryArgs& 
   };
   auto block = [&](int32_t d0, const double (&a)[KS][RT]) {
     const int32_t n = nsteps(d0);
-    if (KS == 1 || n == KS) block_n(std::integral_constant<int, KS>(), a);
-    else dense_dispatch<KS>(n, [&](auto NS) { block_n(NS, a); });
+    if (KS == 1 || n == KS) block_n(std::integral_constant<int, KS>(), d0, a);
+    else dense_dispatch<KS>(n, [&](auto NS) { block_n(NS, d0, a); });
   };
   double a0[KS][RT], a1[KS][RT];
   int32_t d0 = wave * 16 * RT;
@@ -857,6 +873,7 @@ __device__ __forceinline__ void dense_body(const SweepArgs& A, const QueryArgs& 
     block(d0, a1);
     d0 += kStep;
   }
+  if constexpr (STAGE) return;
 #pragma unroll
   for (int g = 0; g < G; ++g) {
     sq[g] += __shfl_xor(sq[g], 16);
@@ -870,20 +887,25 @@ __device__ __forceinline__ void dense_body(const SweepArgs& A, const QueryArgs& 
   }
 }
 
-template <int GRP>
+template <int GRP, bool STAGE>
 __global__ __launch_bounds__(64 * kBottomWaves) __attribute__((amdgpu_waves_per_eu(4))) void dense_kernel(
     SweepArgs A, QueryArgs Q, int64_t i0) {
   __shared__ DenseLds<GRP> L;
-  dense_body<GRP>(A, Q, i0 + blockIdx.x, L);
+  dense_body<GRP, STAGE>(A, Q, i0 + blockIdx.x, L);
 }
 
-// Calls f(std::integral_constant<int, x>) for a run-time group x in [X, kDenseGroups).
+// Calls f(std::integral_constant<int, GRP>, std::bool_constant<STAGE>) for a
+// run-time group x in [X, kDenseAllGroups) (staging group kDenseGroups + c
+// runs the one-tile form of class c).
 template <int X, class F>
 void dense_group(int x, F&& f) {
   if constexpr (X < kDenseGroups) {
     // (groups with more tiles than their class takes hold no items)
     if constexpr ((1 << (X % kDenseTileKinds)) <= dense_tiles(X / kDenseTileKinds))
-      if (x == X) return f(std::integral_constant<int, X>());
+      if (x == X) return f(std::integral_constant<int, X>(), std::false_type());
+    dense_group<X + 1>(x, f);
+  } else if constexpr (X < kDenseAllGroups) {
+    if (x == X) return f(std::integral_constant<int, (X - kDenseGroups) * kDenseTileKinds>(), std::true_type());
     dense_group<X + 1>(x, f);
   }
 }
@@ -1095,14 +1117,14 @@ __global__ __launch_bounds__(256) void grouped_top_query_kernel(const FactorArgs
   top_query_body(load_struct(&fa[f].a), load_struct(&fa[f].q), load_uniform(&items[i].local));
 }
 
-// dense items of many factors: one workgroup per item
-template <int GRP>
+// dense items of many factors, one group per launch: one workgroup per item
+template <int GRP, bool STAGE>
 __global__ __launch_bounds__(64 * kBottomWaves) __attribute__((amdgpu_waves_per_eu(4))) void grouped_dense_kernel(
     const FactorArgs* __restrict__ fa, const GroupItem* __restrict__ items, int64_t nitems) {
   __shared__ DenseLds<GRP> L;
   for (int64_t i = blockIdx.x; i < nitems; i += gridDim.x) {
     const int32_t f = load_uniform(&items[i].fa);
-    dense_body<GRP>(load_struct(&fa[f].a), load_struct(&fa[f].q), load_uniform(&items[i].local), L);
+    dense_body<GRP, STAGE>(load_struct(&fa[f].a), load_struct(&fa[f].q), load_uniform(&items[i].local), L);
     __syncthreads();
   }
 }
@@ -1166,10 +1188,10 @@ hipError_t launch_grouped(int kind, const FactorArgs* fa, const GroupItem* items
     case GK_ZERO: hipLaunchKernelGGL(grouped_kernel<GK_ZERO>, g, dim3(256), 0, s, fa, items, nitems); break;
     case GK_GENERAL: hipLaunchKernelGGL(grouped_kernel<GK_GENERAL>, g, dim3(256), 0, s, fa, items, nitems); break;
     default:
-      if (kind >= GK_DENSE && kind < GK_DENSE + kDenseGroups) {
-        dense_group<0>(kind - GK_DENSE, [&](auto X) {
-          hipLaunchKernelGGL(grouped_dense_kernel<decltype(X)::value>, g, dim3(64 * kBottomWaves), 0, s, fa, items,
-                             nitems);
+      if (kind >= GK_DENSE && kind < GK_DENSE + kDenseAllGroups) {
+        dense_group<0>(kind - GK_DENSE, [&](auto X, auto ST) {
+          hipLaunchKernelGGL((grouped_dense_kernel<decltype(X)::value, decltype(ST)::value>), g,
+                             dim3(64 * kBottomWaves), 0, s, fa, items, nitems);
         });
         break;
       }
@@ -1222,11 +1244,12 @@ hipError_t launch_bxfer(const SweepArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_dense(const SweepArgs& a, const QueryArgs& q, const int64_t* dclass_ptr, int only, hipStream_t s) {
-  for (int x = 0; x < kDenseGroups; ++x) {
+  for (int x = 0; x < kDenseAllGroups; ++x) {
     const int64_t i0 = dclass_ptr[x], n = dclass_ptr[x + 1] - dclass_ptr[x];
     if (n <= 0 || (only >= 0 && x != only)) continue;
-    dense_group<0>(x, [&](auto X) {
-      hipLaunchKernelGGL(dense_kernel<decltype(X)::value>, dim3((unsigned)n), dim3(64 * kBottomWaves), 0, s, a, q, i0);
+    dense_group<0>(x, [&](auto X, auto ST) {
+      hipLaunchKernelGGL((dense_kernel<decltype(X)::value, decltype(ST)::value>), dim3((unsigned)n),
+                         dim3(64 * kBottomWaves), 0, s, a, q, i0);
     });
   }
   return hipGetLastError();

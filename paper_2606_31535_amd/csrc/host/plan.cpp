@@ -485,8 +485,9 @@ static void plan_dense(const FactorPlan& P, const std::vector<int32_t>& depth, i
   Q.bq_g0.assign(nb + 1, 0);
   std::vector<char> ok(nb, 0);
   for (int64_t j = 0; j < nb; ++j) {
+    // (a staging entry has hi -1 like a ground pair: its w is B_S e_lo)
     const int32_t lo = jlo[j], hi = jhi[j];
-    if (lo < 0) continue;  // a staging entry
+    if (lo < 0) continue;
     const int32_t sub = P.bpos_sub[pos[lo]];
     const int32_t K = P.sub_K[sub];
     if (K > kDenseMaxK) continue;
@@ -520,18 +521,28 @@ static void plan_dense(const FactorPlan& P, const std::vector<int32_t>& depth, i
     if (w0 == 0) continue;
     bool all = true;
     for (int32_t j = j0; j < j1; ++j) {
-      if (ok[j]) Q.bq_g0[j] = w0 / kWinPerWave;
-      else all = false;
+      if (!ok[j]) { all = false; continue; }
+      Q.bq_g0[j] = w0 / kWinPerWave;
+      if (Q.bq[j].kind == kQStage) Q.bq[j].out = w0;  // the dense form writes the windows below
     }
     if (all) tw0[t] = w0;
     for (int32_t p = P.btask_ptr[t]; p < P.btask_ptr[t + 1];) {
       const int32_t sub = P.bpos_sub[p];
       const int32_t s0 = Q.bq_ptr[P.sub_p0[sub]], s1 = Q.bq_ptr[P.sub_p1[sub]];
+      const int cl = dense_class(P.sub_K[sub]);
+      // staged columns: one column tile per item
+      const int32_t m0 = (int32_t)Q.dq_list.size();
+      for (int32_t j = s0; j < s1; ++j)
+        if (ok[j] && Q.bq[j].kind == kQStage) Q.dq_list.push_back(j);
+      const int32_t m1 = (int32_t)Q.dq_list.size();
+      for (int32_t c = m0; c < m1; c += kDenseTile) {
+        items.push_back(DItem{sub, c, std::min(kDenseTile, m1 - c), kWin * w0});
+        cls.push_back(kDenseGroups + cl);
+      }
       const int32_t l0 = (int32_t)Q.dq_list.size();
       for (int32_t j = s0; j < s1; ++j)
-        if (ok[j]) Q.dq_list.push_back(j);
+        if (ok[j] && Q.bq[j].kind != kQStage) Q.dq_list.push_back(j);
       const int32_t l1 = (int32_t)Q.dq_list.size();
-      const int cl = dense_class(P.sub_K[sub]);
       // the subtree's column tiles in items of 1, 2, 4 or 8 tiles, largest first
       for (int32_t c = l0; c < l1;) {
         const int32_t tiles = (l1 - c + kDenseTile - 1) / kDenseTile;
@@ -554,12 +565,12 @@ static void plan_dense(const FactorPlan& P, const std::vector<int32_t>& depth, i
     if (cls[x] != cls[y]) return cls[x] < cls[y];
     return cost(x) > cost(y);
   });
-  Q.dclass_ptr.assign(kDenseGroups + 1, 0);
+  Q.dclass_ptr.assign(kDenseAllGroups + 1, 0);
   for (int64_t x : ord) {
     Q.ditems.push_back(items[x]);
     Q.dclass_ptr[cls[x] + 1]++;
   }
-  for (int c = 0; c < kDenseGroups; ++c) Q.dclass_ptr[c + 1] += Q.dclass_ptr[c];
+  for (int c = 0; c < kDenseAllGroups; ++c) Q.dclass_ptr[c + 1] += Q.dclass_ptr[c];
   Q.dense = !Q.ditems.empty();
 }
 
@@ -672,6 +683,7 @@ Status build_query_plan(const std::vector<int32_t>& first, const std::vector<int
   if (!stage_of.empty())
     for (int32_t x = 0; x < N; ++x) {
       if (stage_of[x] < 0) continue;
+      if (dense) jlo[fill[pos[x]]] = x;  // (jhi stays -1: the staged node's own column)
       BQuery& bq = Q.bq[fill[pos[x]]++];
       bq.kind = kQStage;
       bq.hiref = stage_of[x];

@@ -89,6 +89,10 @@ constexpr int dense_tiles(int cls) { return cls <= 1 ? 8 : cls <= 3 ? 4 : 2; }
 constexpr int dense_rt(int cls) { return cls <= 1 ? 4 : cls == 2 ? 2 : 1; }
 constexpr int kDenseTileKinds = 4;
 constexpr int kDenseGroups = kDenseClasses * kDenseTileKinds;
+// then one group per class of staging items: the rows above S of a staged
+// column (a non-ancestor pair's bottom endpoint), Z[rows, U_S] B_S e_x,
+// written to the staging buffer (one column tile per item)
+constexpr int kDenseAllGroups = kDenseGroups + kDenseClasses;
 // w of a query whose higher endpoint is the ground
 constexpr int64_t kDenseNoV = INT64_MIN;
 
@@ -230,7 +234,7 @@ struct BQuery {
   int64_t hiref;   // kQSlot: path-stack slot; kQStore: store_ref; kQStage: staging offset
   int32_t kind;    // how the higher endpoint's column is found (kQ*)
   int32_t nwin;    // windows of the lower endpoint's column
-  int64_t out;     // output index
+  int64_t out;     // output index; kQStage: the first window the sweep writes
 };
 // BQuery::kind: the higher endpoint's column in the lower endpoint's sweep
 //   kQSlot   on the path stack (the higher endpoint is in the same subtree)
@@ -308,7 +312,8 @@ struct QueryPlan {
   // covers depends only on the factor and on the query itself (not on the
   // other queries of the plan), so a query gets the same bits in any plan.
   // Work items grouped by class and tiles (items [dclass_ptr[x],
-  // dclass_ptr[x+1]) of group x), their bottom queries in dq_list; per bottom
+  // dclass_ptr[x+1]) of group x), then the staging items of each class
+  // (group kDenseGroups + class), their bottom queries in dq_list; per bottom
   // query the B_S column offsets of its endpoints (bq_bv: >= 0 a column of B,
   // -1 - e for the e-th column of U_S, kDenseNoV for the ground) and the
   // first window group its sweep sums (bq_g0 > 0: the dense sum covers the

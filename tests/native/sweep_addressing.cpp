@@ -108,14 +108,15 @@ void check_dense(const FactorPlan& P, const QueryPlan& Q, const Sizes& Z, const 
     REQUIRE(Q.ditems.empty(), "items without the dense flag");
     return;
   }
-  REQUIRE((int)Q.dclass_ptr.size() == kDenseGroups + 1 && Q.dclass_ptr[0] == 0 &&
-              Q.dclass_ptr[kDenseGroups] == (int64_t)Q.ditems.size(), "group ranges");
+  REQUIRE((int)Q.dclass_ptr.size() == kDenseAllGroups + 1 && Q.dclass_ptr[0] == 0 &&
+              Q.dclass_ptr[kDenseAllGroups] == (int64_t)Q.ditems.size(), "group ranges");
   REQUIRE((int64_t)Q.bq_bu.size() == nbq + 1 && (int64_t)Q.bq_bv.size() == nbq + 1 && (int64_t)Q.bq_g0.size() == nbq + 1,
           "per-query dense tables");
   REQUIRE(kStoreZeroBlock >= kDenseTile, "zero block covers a row tile");
   REQUIRE(Z.store_elems <= INT32_MAX, "dense sums address the store with 32-bit element offsets");
-  for (int x = 0; x < kDenseGroups; ++x) {
-    const int c = x / kDenseTileKinds, tiles = 1 << (x % kDenseTileKinds);
+  for (int x = 0; x < kDenseAllGroups; ++x) {
+    const bool stage = x >= kDenseGroups;
+    const int c = stage ? x - kDenseGroups : x / kDenseTileKinds, tiles = stage ? 1 : 1 << (x % kDenseTileKinds);
     REQUIRE(Q.dclass_ptr[x + 1] == Q.dclass_ptr[x] || tiles <= dense_tiles(c), "group %d", x);
     for (int64_t it = Q.dclass_ptr[x]; it < Q.dclass_ptr[x + 1]; ++it) {
       const DItem& d = Q.ditems[it];
@@ -144,8 +145,15 @@ void check_dense(const FactorPlan& P, const QueryPlan& Q, const Sizes& Z, const 
         const int64_t bv = Q.bq_bv[j];
         if (bv >= 0) REQUIRE(bv >= bb && bv + K <= be, "B column of v");
         else if (bv != kDenseNoV) REQUIRE(-1 - bv < K, "U_S column of v");
+        REQUIRE((Q.bq[j].kind == kQStage) == stage, "staging entries in exactly the staging groups");
+        if (stage) {
+          // the item writes rows [0, rows) of the staged column; the sweep the rest
+          REQUIRE(Q.bq[j].out * kWin == d.rows && Q.bq[j].hiref >= 0 && Q.bq[j].hiref + d.rows <= Z.stage_elems,
+                  "staged rows of entry %" PRId64, j);
+          REQUIRE(Q.bq_bv[j] == kDenseNoV, "staging w is B_S e_x");
+        }
         const int64_t slot = Q.nslots + j;
-        REQUIRE(slot < Z.nslots, "dense sum slot %" PRId64 " of %" PRId64, slot, Z.nslots);
+        REQUIRE(stage || slot < Z.nslots, "dense sum slot %" PRId64 " of %" PRId64, slot, Z.nslots);
         REQUIRE(!M.dense_written[j], "query %" PRId64 " in two dense items", j);
         M.dense_written[j] = 1;
       }
@@ -342,6 +350,25 @@ void check_dense_values(const GraphHandle& G, const FactorPlan& P, const QueryPl
         for (int32_t k = 0; k < K; ++k)
           if (row < P.sub_udep[ub + k]) y += w[k] * store[P.sub_uoff[ub + k] + row];
         dense += y * y;
+      }
+      if (Q.bq[j].kind == kQStage) {
+        // a staged column: rows [0, rows) against the node's column of Z
+        int32_t node = -1;
+        for (int32_t p = P.sub_p0[d.sub]; p < P.sub_p1[d.sub] && node < 0; ++p)
+          if (Q.bq_ptr[p] <= j && j < Q.bq_ptr[p + 1]) node = P.bnode_node[p];
+        REQUIRE(node >= 0, "staged node of entry %" PRId64, j);
+        double zmax = 0.0, dmax = 0.0;
+        for (int32_t row = 0; row < d.rows; ++row) {
+          double yv = 0.0;
+          for (int32_t k2 = 0; k2 < K; ++k2)
+            if (row < P.sub_udep[ub + k2]) yv += w[k2] * store[P.sub_uoff[ub + k2] + row];
+          zmax = std::max(zmax, std::fabs(z[node][row]));
+          dmax = std::max(dmax, std::fabs(yv - z[node][row]));
+        }
+        const double err = zmax > 0 ? dmax / zmax : dmax;
+        worst = std::max(worst, err);
+        REQUIRE(err < 1e-12, "staged column of entry %" PRId64 ": difference %.3g of %.3g", j, dmax, zmax);
+        continue;
       }
       const int64_t k = Q.bq[j].out;
       const int32_t x = a[k], y = b[k];
