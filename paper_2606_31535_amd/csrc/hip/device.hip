@@ -75,6 +75,12 @@ void DeviceHandle::release(uint64_t bytes) {
   used = bytes > used ? 0 : used - bytes;
 }
 
+// Extra cost counted per dense launch when the groups are spread over the
+// side streams: 2e7 units of dense_costs take 40-80 us at the rates of the
+// large groups on the 1M-node mesh, about the time a launch of a few items
+// (a few long row walks) lasts.
+constexpr double kDenseLaunchFloor = 2e7;
+
 // Matrix-core work of each dense group (rows x column tiles x k-groups).
 void dense_costs(const QueryPlan& Q, std::vector<double>& group) {
   group.assign(Q.dense ? kDenseAllGroups : 0, 0.0);
@@ -236,9 +242,14 @@ Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t
       // caller workspace (a caller that may capture the stream): one stream
       HIP_TRY(launch_dense(F.sweep, q, D.dclass_ptr.data(), -1, s));
     } else {
-      // the dense groups on the device's side streams, largest first to the
-      // least loaded, beside the sweep on s (they write disjoint sums; the
-      // finish step on s waits for all of them)
+      // the dense groups on the device's side streams beside the sweep on s
+      // (they write disjoint sums; the finish step on s waits for all of
+      // them). Largest first to the least loaded stream, counting each launch
+      // at its cost plus kDenseLaunchFloor: a group with fewer items than the
+      // device holds workgroups takes about as long as its longest item, so
+      // the small groups are spread over the streams. Each stream then runs
+      // its groups smallest first, so those latency-bound launches of the
+      // three streams overlap at the start instead of queueing at the end.
       DeviceHandle& V = *F.dev;
       std::lock_guard<std::mutex> g(V.side_mu);
       constexpr int NS = DeviceHandle::kSideStreams;
@@ -248,14 +259,16 @@ Status run_sweep(FactorHandle& F, DeviceQueryPlan& D, double* R_dev, hipStream_t
         if (D.dclass_ptr[x + 1] > D.dclass_ptr[x]) ord.push_back(x);
       std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return D.dgroup_cost[x] > D.dgroup_cost[y]; });
       double load[NS] = {0, 0, 0};
-      for (int k = 0; k < NS; ++k) HIP_TRY(hipStreamWaitEvent(V.side[k], V.fork_ev, 0));
-      for (int x : ord) {
+      std::vector<int> on(ord.size());
+      for (size_t i = 0; i < ord.size(); ++i) {
         int k = 0;
         for (int j = 1; j < NS; ++j)
           if (load[j] < load[k]) k = j;
-        load[k] += D.dgroup_cost[x];
-        HIP_TRY(launch_dense(F.sweep, q, D.dclass_ptr.data(), x, V.side[k]));
+        load[k] += D.dgroup_cost[ord[i]] + kDenseLaunchFloor;
+        on[i] = k;
       }
+      for (int k = 0; k < NS; ++k) HIP_TRY(hipStreamWaitEvent(V.side[k], V.fork_ev, 0));
+      for (size_t i = ord.size(); i-- > 0;) HIP_TRY(launch_dense(F.sweep, q, D.dclass_ptr.data(), ord[i], V.side[on[i]]));
       for (int k = 0; k < NS; ++k) HIP_TRY(hipEventRecord(V.join_ev[k], V.side[k]));
       HIP_TRY(launch_bottom(F.sweep, q, s));
       for (int k = 0; k < NS; ++k) HIP_TRY(hipStreamWaitEvent(s, V.join_ev[k], 0));
