@@ -133,8 +133,8 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None.
+def recorded_traffic(kernel: str, workload: str, key: str = "hbm_bytes_per_launch"):
+    """HBM bytes (per launch, or the field `key`) from the committed rocprofv3 counter summary, or None.
 
     The summary (profiles/<kernel>_<workload>_traffic.txt) holds the
     FETCH_SIZE/WRITE_SIZE readings scaled by the copy-kernel calibration and
@@ -152,8 +152,8 @@ def recorded_traffic(kernel: str, workload: str):
     if fields.get("source_hash") != kernel_source_hash():
         return None
     try:
-        return float(fields["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
+        return float(fields[key].split()[0])
+    except (KeyError, ValueError, IndexError):
         return None
 
 
@@ -445,6 +445,17 @@ def bench_plain(args, g, desc, cpu=None) -> dict:
                                   ("bottom", "bottom_ms", "bottom_flops", "bottom_launches"))}
     phase_roofline["bottom"]["what"] = ("dense sums above bottom subtrees on the matrix cores (three side "
                                         "streams) beside the sweep of the rows from each subtree on")
+    # HBM bytes of each phase from the committed counter summaries (null when
+    # they were taken at other kernel sources): the chain levels' mean bytes per
+    # launch times their launches, and the whole bottom phase
+    lv_bytes = recorded_traffic("gemm_level_kernel", args.workload)
+    hbm_phase = {"top": None if lv_bytes is None else lv_bytes * (tm["top_launches"] - 1),
+                 "bottom": recorded_traffic("bottom_phase", args.workload, "hbm_bytes_per_sweep")}
+    for name, b in hbm_phase.items():
+        tbs = None if b is None else b / (phase_roofline[name]["phase_ms"] * 1e-3) / 1e12
+        phase_roofline[name]["hbm"] = {"bytes": b, "TB_per_s": None if b is None else round(tbs, 3),
+                                       "frac_of_hbm_peak": None if b is None else round(tbs * 1e3 / PEAK_HBM_GBS, 4)}
+    phase_roofline["top"]["hbm"]["what"] = "gemm_level_kernel launches (the chain-rows launch not counted)"
 
     # accuracy on the stored oracle sample, and Foster's theorem on all edges
     acc = {"foster_rel_residual": float(abs(math.fsum(g.w * Rh) - (g.n - 1)) / (g.n - 1))}
