@@ -161,7 +161,8 @@ __device__ __forceinline__ void gemm_accumulate(f64x4 (&C)[4][NB], const double*
 }
 
 // C[M x N] = alpha * A[M x K] * B[K x N] for one 64 x 32 output tile over the
-// reduction range [k0, k1) of its task. v_mfma_f64_16x16x4f64 operands:
+// reduction range [k0, k1) of its task (a problem's last tile with at most 16
+// columns left runs as 64 x 16). v_mfma_f64_16x16x4f64 operands:
 // A lane l = (row l%16, k l/16), B lane l = (k l/16, col l%16), C lane l reg
 // r = (row 4r + l/16, col l%16). The four waves take consecutive quarters of
 // the reduction range (multiples of 4) and are summed in LDS in a fixed
@@ -200,7 +201,23 @@ __device__ __forceinline__ void gemm_body(const GemmArgs* Gp, int64_t task, Gemm
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) C[rb][cb] = f64x4{0.0, 0.0, 0.0, 0.0};
   if (e0 < e1) {
-    if (pb.gather) {
+    if (tk.col0 + 16 >= pb.N) {
+      // at most 16 columns left in the tile: the 64 x 16 form (the same
+      // products and order for those columns, half the matrix instructions)
+      f64x4 C1[4][1];
+      const int32_t cols1[1] = {cols[0]};
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) C1[rb][0] = f64x4{0.0, 0.0, 0.0, 0.0};
+      if (pb.gather) {
+        if (pb.trans & 1) gemm_accumulate<true, true, 1>(C1, A, B, gt, pb, rows, cols1, kk, e0, e1);
+        else gemm_accumulate<true, false, 1>(C1, A, B, gt, pb, rows, cols1, kk, e0, e1);
+      } else {
+        if (pb.trans & 1) gemm_accumulate<false, true, 1>(C1, A, B, gt, pb, rows, cols1, kk, e0, e1);
+        else gemm_accumulate<false, false, 1>(C1, A, B, gt, pb, rows, cols1, kk, e0, e1);
+      }
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) C[rb][0] = C1[rb][0];
+    } else if (pb.gather) {
       if (pb.trans & 1) gemm_accumulate<true, true>(C, A, B, gt, pb, rows, cols, kk, e0, e1);
       else gemm_accumulate<true, false>(C, A, B, gt, pb, rows, cols, kk, e0, e1);
     } else {
